@@ -1,0 +1,82 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the
+pins catch each one: a transposed rotation, a wrong sign in the quaternion
+matrix, a dropped centre-of-mass term, a wrong sign in ds/dD."""
+import numpy as np
+import pytest
+
+import oracle.msd as om
+import oracle.path as op
+import workloads as wl
+
+
+def _rigid_pin_holds():
+    rng = np.random.default_rng(1)
+    x = rng.normal(0, 0.3, (9, 3))
+    y, _, _ = wl.rigid_copy(x, 2)
+    return om.msd(y, x) < 1e-14
+
+
+def _fd_pin_holds(w, wp):
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 0.3, (7, 3))
+    a, _, _ = wl.rigid_copy(x + rng.normal(0, 0.2, (7, 3)), 4)
+    g = om.msd_grad(x, a, w, wp)
+    h = 1e-6
+    fd = np.zeros_like(x)
+    for k in range(7):
+        for c in range(3):
+            xp = x.copy(); xp[k, c] += h
+            xm = x.copy(); xm[k, c] -= h
+            fd[k, c] = (om.msd(xp, a, w, wp) - om.msd(xm, a, w, wp)) / (2 * h)
+    return np.abs(g - fd).max() <= 1e-7 * np.abs(fd).max()
+
+
+def test_unmutated_pins_hold():
+    assert _rigid_pin_holds()
+    w, wp = np.linspace(0.3, 1, 7), np.linspace(1, 0.4, 7)
+    assert _fd_pin_holds(w, wp)
+
+
+def test_transposed_rotation_is_caught(monkeypatch):
+    orig = om.rotation_from_quaternion
+    monkeypatch.setattr(om, "rotation_from_quaternion", lambda q: np.swapaxes(orig(q), -1, -2))
+    assert not _rigid_pin_holds()
+
+
+def test_quaternion_matrix_sign_is_caught(monkeypatch):
+    orig = om.quaternion_matrix
+
+    def bad(M):
+        F = orig(M)
+        F[..., 0, 1] *= -1
+        F[..., 1, 0] *= -1
+        return F
+
+    monkeypatch.setattr(om, "quaternion_matrix", bad)
+    assert not _rigid_pin_holds()
+
+
+def test_dropped_rotation_term_is_caught(monkeypatch):
+    monkeypatch.setattr(om, "rotation_term", lambda Gamma, a_c, wp: 0.0 * a_c)
+    assert not _fd_pin_holds(np.linspace(0.3, 1, 7), np.linspace(1, 0.4, 7))
+
+
+def test_wrong_path_gradient_sign_is_caught(monkeypatch):
+    orig = op.path_sz
+
+    def bad(D, lam, q=None):
+        r = orig(D, lam, q)
+        r.c = -r.c
+        return r
+
+    monkeypatch.setattr(op, "path_sz", bad)
+    sysm = wl.small_path(6, 8, seed=5)
+    A = sysm.landmarks
+    x = sysm.waypoints[0] + 0.01
+    lam = op.landmark_lambda(A)
+    r = op.path_cv(x, A, lam)
+    h = 1e-6
+    xp = x.copy(); xp[2, 1] += h
+    xm = x.copy(); xm[2, 1] -= h
+    fd = (op.path_cv(xp, A, lam, grad=False).s - op.path_cv(xm, A, lam, grad=False).s) / (2 * h)
+    assert abs(r.ds_dx[2, 1] - fd) > 1e-6 * max(1.0, abs(fd))
