@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the path-CV hot path on one MI355X.
+
+Default workload (exact batched MSD, Algorithm 1 without a neighbour list):
+5,000-atom structure against 10,000 landmarks (600 MB of FP32 coordinates,
+SoA in HBM), s, z and both gradients every step, a fresh noisy frame per step.
+One step = one pcv_eval over all landmarks.  Metric: structure-landmark
+MSD+gradient evaluations per second (= L * steps / time).
+
+Prints one JSON line with the contract fields plus ``roofline`` (the landmark
+streaming kernel's algorithmic bytes, L*n*12 B per launch, over its average
+duration from HIP events recorded on its own stream) and ``cpu_baseline``
+(the FP64 oracle on a bounded sample of the same workload, host cores).
+
+Other workloads: ``--workload close`` (300 atoms x 500 landmarks, Algorithm 2
+along a random walk, steps/s) and ``--workload batch`` (64 uneven walkers in
+one persistent launch).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1801_02362_amd", "csrc", "pcv_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline_exact(sysm, frames, lam, budget_s: float = 12.0):
+    """Oracle path_cv (exact D, s, z and gradients) on the first k landmarks
+    for one frame, k grown until the run takes a few seconds."""
+    import numpy as np
+    from oracle.path import path_cv
+    A = sysm.landmarks
+    x = frames[0].astype(np.float64)
+    k = 50
+    while True:
+        t0 = time.perf_counter()
+        path_cv(x, A[:k].astype(np.float64), lam)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 3 or k >= A.shape[0]:
+            break
+        k = min(A.shape[0], int(k * max(2.0, budget_s / 3 / max(dt, 1e-3))))
+    reps = max(1, int(budget_s / max(dt, 1e-3) / 2))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        path_cv(x, A[:k].astype(np.float64), lam)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": k / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle (path_cv with gradients), first {k} of {A.shape[0]} landmarks x "
+                      f"{sysm.n_atoms} atoms, 1 frame, {reps} repetitions, single thread"}
+
+
+def bench_exact(args):
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+
+    n, L = args.atoms, args.landmarks
+    log(f"[bench] generating cfg2 workload: {n} atoms x {L} landmarks")
+    sysm, base = wl.cfg2(n_atoms=n, n_landmarks=L)
+    frames = wl.cfg2_frames(base, args.warmup + args.steps)
+    dev = torch.device("cuda", 0)
+    lm = torch.as_tensor(sysm.landmarks, device=dev)
+    cv = pcv.PathCV(lm, None, use_graph=True)
+    del lm
+    torch.cuda.empty_cache()
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])       # the structure buffer an MD engine would update in place
+    log(f"[bench] lambda={cv.lam:.3f} plan={cv.plan}")
+    for t in range(args.warmup):
+        x.copy_(x_all[t])
+        cv.eval(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        x.copy_(x_all[args.warmup + t])
+        cv.eval(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cv.check()
+    value = L * args.steps / dt
+    log(f"[bench] timed {args.steps} steps in {dt:.4f} s")
+
+    # Landmark-kernel duration from HIP events on its stream (eager launches).
+    reps = min(args.steps, 50)
+    cv.set_kernel_timing(True)
+    for t in range(reps):
+        x.copy_(x_all[t % (args.warmup + args.steps)])
+        cv.eval(x)
+    ms, cnt = cv.kernel_timing()
+    cv.set_kernel_timing(False)
+    kms = ms / max(cnt, 1)
+    alg_bytes = L * n * 12
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    traffic = counted_traffic(f"engine_exact_{n}x{L}")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "engine_kernel (landmark streaming, exact mode)", "kernel_ms": round(kms, 5),
+            "algorithmic_bytes_per_launch": alg_bytes}
+    out = {
+        "metric": "structure-landmark MSD+grad evals/s",
+        "value": round(value, 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 coords, f64 correlation/eigen/lse, f32 gradients",
+        "data": "synthetic",
+        "config": {"workload": f"exact path CV, {n} atoms x {L} landmarks (FP32 SoA, "
+                               f"{L * n * 12 / 1e6:.0f} MB), s, z, ds/dx, dz/dx per step, fresh frame per step",
+                   "n_atoms": n, "n_landmarks": L, "lambda": round(cv.lam, 4), "plan": cv.plan,
+                   "step_hbm_frac": round(alg_bytes / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline_exact(sysm, frames, cv.lam, args.cpu_budget)
+    cv.close()
+    return out
+
+
+def bench_close(args):
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    dev = torch.device("cuda", 0)
+    cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, eps=0.01)
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])
+    for t in range(args.warmup):
+        x.copy_(x_all[t])
+        cv.eval_close(x)
+    cv.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        x.copy_(x_all[args.warmup + t])
+        cv.eval_close(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = cv.stats()
+    ex = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), cv.lam)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for t in range(args.steps):
+        x.copy_(x_all[args.warmup + t])
+        ex.eval(x)
+    torch.cuda.synchronize()
+    dt_ex = time.perf_counter() - t1
+    out = {"metric": "close-structure steps/s", "value": round(args.steps / dt, 1), "unit": "steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 coords, f64 correlation/eigen/lse", "data": "synthetic",
+           "config": {"workload": "close structure (Algorithm 2), 300 atoms x 500 landmarks, random walk "
+                                  "step 0.005 nm, eps 0.01 nm^2", "stats": st,
+                      "exact_steps_per_s": round(args.steps / dt_ex, 1)}}
+    cv.close()
+    ex.close()
+    return out
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    ws = wl.cfg3(n_walkers=64, n_frames=1)
+    dev = torch.device("cuda", 0)
+    lams = []
+    for w in ws:
+        cv = pcv.PathCV(torch.as_tensor(w.system.landmarks, device=dev), None)
+        lams.append(cv.lam)
+        cv.close()
+    b = pcv.BatchPathCV([torch.as_tensor(w.system.landmarks, device=dev) for w in ws], lams, tune=args.tune,
+                        cache_path=os.path.join(ROOT, "paper_1801_02362_amd", "tune_cache.json") if args.tune else None)
+    x = torch.as_tensor(np.concatenate([w.frames[0] for w in ws]), device=dev)
+    for _ in range(args.warmup):
+        b.eval(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.eval(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pairs = sum(w.system.n_atoms * w.system.n_landmarks for w in ws)
+    evals = sum(w.system.n_landmarks for w in ws)
+    gbs = pairs * 12 / (dt / args.steps) / 1e9
+    out = {"metric": "structure-landmark MSD+grad evals/s", "value": round(evals * args.steps / dt, 1),
+           "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 coords, f64 correlation/eigen/lse", "data": "synthetic",
+           "config": {"workload": "64 walkers, atoms U[50,2000], landmarks U[200,5000], one persistent launch",
+                      "bytes_per_step": pairs * 12, "plan": b.plan, "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}}
+    b.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=["exact", "close", "batch"], default="exact")
+    ap.add_argument("--atoms", type=int, default=5000)
+    ap.add_argument("--landmarks", type=int, default=10000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU design is described but not implemented)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "exact":
+        out = bench_exact(args)
+    elif args.workload == "close":
+        out = bench_close(args)
+    else:
+        out = bench_batch(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

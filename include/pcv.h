@@ -1,0 +1,224 @@
+/*
+ * pcv.h -- C ABI of the MI355X (gfx950) path-collective-variable library.
+ *
+ * Path collective variables after Pazurikova, Olha, Krenek, Spiwok,
+ * "Acceleration of Mean Square Distance Calculations with Floating Close
+ * Structure in Metadynamics Simulations" (arXiv:1801.02362):
+ *
+ *   D(x, a_i)  Eq. 3: mean square distance after optimal superposition
+ *              (weighted centring, then the rotation from the top eigenpair
+ *              of the 4x4 quaternion matrix, Section 3);
+ *   s(x)       Eq. 2 with the landmark index as property (Section 2):
+ *              s = sum_i q_i exp(-lambda D_i) / sum_i exp(-lambda D_i),
+ *              q_i = i (1-based) unless the caller passes properties;
+ *   z(x)       -(1/lambda) ln sum_i exp(-lambda D_i) (distance from the path);
+ *   ds/dx, dz/dx   by the chain rule over Eq. 4 (exact) or Eq. 6 (close
+ *              structure), with respect to the raw (uncentred) coordinates;
+ *   Algorithm 2   the floating close structure y: every call superposes y
+ *              onto x exactly; if D(x, y) > epsilon (strict) y <- x and all
+ *              landmark rotations are recomputed and saved, otherwise each
+ *              landmark rotation is approximated by R_xy R_{a_i y} (Eq. 5).
+ *
+ * Units: nm and nm^2; lambda in nm^-2.  Weights (one set, used for both
+ * alignment and displacement, w = w') are normalised to sum to one.
+ *
+ * Memory: every coordinate, gradient and result pointer named "device" is
+ * HIP device memory owned by the caller (for example a torch tensor); the
+ * library never frees it.  Coordinates are AoS [n][3] (or [L][n][3]) in the
+ * handle's precision: float for PCV_FP32, double for PCV_FP64.  "host"
+ * pointers are read during the call only.  The handle owns its own device
+ * copies of the landmarks and all workspace; nothing is allocated per call.
+ *
+ * Streams: all work is enqueued on the handle's stream and returns without
+ * waiting (except where stated).  Results land in device memory; the caller
+ * synchronises that stream before reading them on the host.
+ *
+ * Errors: every entry point returns a pcv_status; no exception crosses the
+ * ABI.  pcv_last_error() gives a message for the last failing call on a
+ * handle.  A non-finite input structure is detected on the device: outputs
+ * are filled with NaN, the close-structure state and counters are left
+ * unchanged, and pcv_check() reports PCV_ENONFINITE.
+ *
+ * Threads: a handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef PCV_H
+#define PCV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pcv_status {
+  PCV_OK = 0,
+  PCV_EINVAL = -1,        /* bad argument (null pointer, negative size, bad option) */
+  PCV_ESTATE = -2,        /* call order (e.g. evaluate before landmarks are loaded) */
+  PCV_ESHAPE = -3,        /* size outside what the kernels support */
+  PCV_ENONFINITE = -4,    /* NaN or Inf in an input structure */
+  PCV_EHIP = -5,          /* HIP runtime error */
+  PCV_ENOMEM = -6,        /* device allocation failed */
+  PCV_EUNSUPPORTED = -7   /* valid request the library does not implement */
+} pcv_status;
+
+enum { PCV_FP32 = 32, PCV_FP64 = 64 };
+
+typedef struct pcv_options {
+  int device;        /* HIP device ordinal */
+  void* stream;      /* hipStream_t to enqueue on; NULL = the null stream */
+  int precision;     /* PCV_FP32 or PCV_FP64: coordinate and gradient type */
+  double eps;        /* close-structure threshold on D(x, y), nm^2 (Section 5: 0.01) */
+  int use_graph;     /* nonzero: replay per-call kernel sequences from a hipGraph */
+} pcv_options;
+
+typedef struct pcv_stats {
+  int64_t frames;          /* close-structure calls with finite input */
+  int64_t recomputes;      /* reassignments of the close structure (incl. the first call) */
+  int64_t expensive_msd;   /* exact superpositions: 1 per call with a close structure + L per reassignment */
+  int64_t approx_frames;   /* calls served by Eq. 5 */
+  int64_t exact_evals;     /* pcv_eval calls (each L exact superpositions) */
+  int64_t eigen_fallbacks; /* landmark solves that used the Jacobi fallback (degenerate spectrum) */
+} pcv_stats;
+
+typedef struct pcv_handle pcv_handle;
+
+/* Default options: device 0, null stream, FP32, eps = 0.01 nm^2, graphs on. */
+void pcv_default_options(pcv_options* opt);
+
+/* Create a handle on opt->device.  *out receives the handle (NULL on error). */
+pcv_status pcv_create(pcv_handle** out, const pcv_options* opt);
+
+/* Release the handle and its device memory (waits for its stream). NULL is a no-op. */
+pcv_status pcv_destroy(pcv_handle* h);
+
+/*
+ * Load the landmark (reference) structures a_i of Eq. 2 (Section 2).
+ *   n_atoms      atoms per structure, 1 .. pcv_max_atoms()
+ *   n_landmarks  L >= 1
+ *   coords       device, AoS [L][n][3] in the handle precision; copied (SoA,
+ *                values unchanged), so the caller may free it afterwards
+ *   q            host [L] properties q_i, or NULL for q_i = i (1-based)
+ *   w            host [n] non-negative weights (alignment = displacement),
+ *                or NULL for uniform; normalised to sum to one
+ *   lambda       sharpness > 0 (nm^-2); see pcv_path_lambda()
+ * Resets the close-structure state and counters.  Synchronises the stream.
+ */
+pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landmarks, const void* coords,
+                              const double* q, const double* w, double lambda);
+
+/* Largest supported n_atoms for the handle's precision. */
+int pcv_max_atoms(int precision);
+
+/*
+ * lambda = factor / mean_i D(a_i, a_{i+1}) over consecutive loaded landmarks
+ * (exact Eq. 3 distances computed on the device), the usual path-CV choice.
+ * Writes *lambda_out (host); does NOT change the handle's lambda.
+ * Synchronises the stream.  Needs L >= 2.
+ */
+pcv_status pcv_path_lambda(pcv_handle* h, double factor, double* lambda_out);
+
+/* Change lambda without reloading (resets the close-structure state). */
+pcv_status pcv_set_lambda(pcv_handle* h, double lambda);
+
+/*
+ * Algorithm 1 (no neighbour list): exact D to every landmark, s, z and their
+ * gradients for structure x.
+ *   x      device [n][3]
+ *   sz     device double[2]: s, z
+ *   ds_dx  device [n][3] or NULL;  dz_dx  device [n][3] or NULL
+ *   msd    device double[L] (the exact D_i) or NULL
+ */
+pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx, double* msd);
+
+/*
+ * Algorithm 2: one step with the floating close structure.  Outputs as in
+ * pcv_eval; msd receives D_i on reassignment steps and the Eq. 5
+ * approximations otherwise.  recomputed (device int or NULL) receives 1 on a
+ * reassignment step, 0 on an approximate step, -1 for non-finite input.
+ * The decision is taken on the device; no host synchronisation per call.
+ */
+pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx,
+                          double* msd, int* recomputed);
+
+/* Force the next pcv_eval_close to reassign (y <- x, all rotations recomputed). */
+pcv_status pcv_force_reassign(pcv_handle* h);
+
+/* Reassign now: y <- x and recompute every saved rotation R_{a_i y}. */
+pcv_status pcv_update_close(pcv_handle* h, const void* x);
+
+/* Counters (synchronises the stream). */
+pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out);
+pcv_status pcv_reset_stats(pcv_handle* h);
+
+/* Synchronise the stream and report a deferred device-side error (non-finite
+ * input since the last check), clearing it. */
+pcv_status pcv_check(pcv_handle* h);
+
+/* Engine tiling chosen for the loaded landmarks: threads per workgroup,
+ * atoms per thread, lanes per landmark, workgroups, work items. */
+pcv_status pcv_get_plan(pcv_handle* h, int* wg, int* apt, int* team, int* grid, int* items);
+
+/* Override the tiling (must cover n: team * apt >= n, team a power of two
+ * dividing wg, 16 <= team); items <= 0 picks the default count. */
+pcv_status pcv_set_plan(pcv_handle* h, int wg, int apt, int team, int items);
+
+/*
+ * Kernel timing for roofline measurements.  While enabled, calls run eagerly
+ * (no graph replay) and HIP events are recorded on the handle's stream around
+ * every launch of the landmark streaming kernel.  pcv_get_kernel_timing
+ * synchronises and returns the summed duration (ms) and launch count since
+ * timing was enabled.
+ */
+pcv_status pcv_set_kernel_timing(pcv_handle* h, int enable);
+pcv_status pcv_get_kernel_timing(pcv_handle* h, double* engine_ms, int64_t* engine_launches);
+
+const char* pcv_status_string(pcv_status s);
+const char* pcv_last_error(const pcv_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Batched walkers: many independent (structure, landmark set) problems of
+ * uneven size evaluated by one persistent launch of the landmark engine
+ * (exact Algorithm 1 per walker), optionally replayed from a hipGraph.
+ * ---------------------------------------------------------------------- */
+typedef struct pcv_batch pcv_batch;
+
+pcv_status pcv_batch_create(pcv_batch** out, const pcv_options* opt);
+pcv_status pcv_batch_destroy(pcv_batch* b);
+
+/*
+ * Load W walkers.
+ *   n_atoms[W], n_landmarks[W]   host; n_atoms[w] <= pcv_max_atoms()
+ *   coords      device, concatenation over walkers of AoS [L_w][n_w][3]
+ *   lambdas     host [W]
+ * Properties are q_i = i and weights uniform per walker.  Synchronises.
+ */
+pcv_status pcv_batch_load(pcv_batch* b, int n_walkers, const int* n_atoms, const int* n_landmarks,
+                          const void* coords, const double* lambdas);
+
+/*
+ * Choose tiles and schedule.  tune = 0: built-in heuristic; tune = 1: time
+ * every candidate on the device (each must reproduce the heuristic plan's
+ * results within tolerance to be eligible) and keep the fastest; the choice
+ * is cached in the JSON file named by cache_path (may be NULL).
+ * Synchronises.  Needs a prior pcv_batch_load.
+ */
+pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path);
+
+/*
+ * Evaluate all walkers:
+ *   x_all   device, concatenation of [n_w][3]
+ *   sz_all  device double[W][2]
+ *   ds_all, dz_all  device, concatenation of [n_w][3], or NULL
+ */
+pcv_status pcv_batch_eval(pcv_batch* b, const void* x_all, double* sz_all, void* ds_all, void* dz_all);
+
+/* Description of the chosen plan (static string owned by the batch). */
+const char* pcv_batch_plan_string(const pcv_batch* b);
+const char* pcv_batch_last_error(const pcv_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCV_H */

@@ -1,0 +1,334 @@
+"""Path collective variables with a floating close structure on MI355X.
+
+Thin Python binding over the C ABI in ``include/pcv.h`` (``libpcv.so``, built
+by ``python -m paper_1801_02362_amd.build``).  This module only marshals
+arguments: every step of the computation runs in the HIP kernels.  PyTorch
+supplies device memory and the stream; tensors must live on the GPU.
+
+Method: Pazurikova et al., arXiv:1801.02362 -- Eq. 2 (property-map / path
+CV), Eq. 3-4 (exact MSD and derivative), Algorithm 2 with Eq. 5-6 (floating
+close structure).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["PcvError", "PathCV", "BatchPathCV", "library_path", "load_library", "FP32", "FP64"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+FP32, FP64 = 32, 64
+_STATUS = {0: "ok", -1: "invalid argument", -2: "invalid call order", -3: "unsupported size",
+           -4: "non-finite input", -5: "HIP runtime error", -6: "out of device memory",
+           -7: "unsupported"}
+
+
+class PcvError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        self.status = status
+        super().__init__(f"pcv status {status} ({_STATUS.get(status, '?')}): {message}")
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
+                ("eps", ctypes.c_double), ("use_graph", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("frames", "recomputes", "expensive_msd", "approx_frames", "exact_evals", "eigen_fallbacks")]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libpcv.so")
+
+
+def load_library():
+    """Load ``libpcv.so`` from the package directory; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1801_02362_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i, d, st = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int
+    sig = {
+        "pcv_default_options": (None, [ctypes.POINTER(_Options)]),
+        "pcv_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_Options)]),
+        "pcv_destroy": (st, [vp]),
+        "pcv_load_landmarks": (st, [vp, i, i, vp, vp, vp, d]),
+        "pcv_max_atoms": (i, [i]),
+        "pcv_path_lambda": (st, [vp, d, ctypes.POINTER(d)]),
+        "pcv_set_lambda": (st, [vp, d]),
+        "pcv_eval": (st, [vp, vp, vp, vp, vp, vp]),
+        "pcv_eval_close": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "pcv_force_reassign": (st, [vp]),
+        "pcv_update_close": (st, [vp, vp]),
+        "pcv_get_stats": (st, [vp, ctypes.POINTER(_Stats)]),
+        "pcv_reset_stats": (st, [vp]),
+        "pcv_check": (st, [vp]),
+        "pcv_get_plan": (st, [vp] + [ctypes.POINTER(i)] * 5),
+        "pcv_set_plan": (st, [vp, i, i, i, i]),
+        "pcv_set_kernel_timing": (st, [vp, i]),
+        "pcv_get_kernel_timing": (st, [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)]),
+        "pcv_status_string": (ctypes.c_char_p, [st]),
+        "pcv_last_error": (ctypes.c_char_p, [vp]),
+        "pcv_batch_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_Options)]),
+        "pcv_batch_destroy": (st, [vp]),
+        "pcv_batch_load": (st, [vp, i, vp, vp, vp, vp]),
+        "pcv_batch_plan": (st, [vp, i, ctypes.c_char_p]),
+        "pcv_batch_eval": (st, [vp, vp, vp, vp, vp]),
+        "pcv_batch_plan_string": (ctypes.c_char_p, [vp]),
+        "pcv_batch_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_host_f64(a, size, what):
+    if a is None:
+        return None, None
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if arr.size != size:
+        raise ValueError(f"{what} must have {size} entries")
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+class PathCV:
+    """Path CVs of one structure against a landmark set on one GPU.
+
+    ``landmarks``: CUDA tensor ``[L][n][3]`` (float32 -> FP32 path, float64 ->
+    FP64 path).  ``lam``: sharpness; if None it is set to
+    ``lambda_factor / mean D(a_i, a_{i+1})`` computed on the device.
+    ``q``: per-landmark property (default 1..L).  ``w``: per-atom weights.
+    ``eps``: close-structure threshold (nm^2).
+    """
+
+    def __init__(self, landmarks, lam: float | None = None, *, q=None, w=None, eps: float = 0.01,
+                 lambda_factor: float = 2.3, use_graph: bool = True, stream=None, device: int | None = None):
+        import torch
+        L = load_library()
+        if not (landmarks.is_cuda and landmarks.dim() == 3 and landmarks.shape[2] == 3):
+            raise ValueError("landmarks must be a CUDA tensor [L][n][3]")
+        if landmarks.dtype not in (torch.float32, torch.float64):
+            raise ValueError("landmarks must be float32 or float64")
+        self._L = L
+        self.dtype = landmarks.dtype
+        self.n_landmarks, self.n_atoms = int(landmarks.shape[0]), int(landmarks.shape[1])
+        self.device = landmarks.device if device is None else torch.device("cuda", device)
+        self._stream = stream
+        opt = _Options()
+        L.pcv_default_options(ctypes.byref(opt))
+        opt.device = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        opt.stream = _stream_ptr(stream).value
+        opt.precision = FP64 if self.dtype == torch.float64 else FP32
+        opt.eps = float(eps)
+        opt.use_graph = 1 if use_graph else 0
+        h = ctypes.c_void_p()
+        self._check(L.pcv_create(ctypes.byref(h), ctypes.byref(opt)), None)
+        self._h = h
+        lm = landmarks.contiguous()
+        _, qp = _as_host_f64(q, self.n_landmarks, "q")
+        self._q_keep = q
+        _, wp = _as_host_f64(w, self.n_atoms, "w")
+        self._check(L.pcv_load_landmarks(h, self.n_atoms, self.n_landmarks, _ptr(lm), qp, wp,
+                                         ctypes.c_double(1.0 if lam is None else float(lam))))
+        if lam is None:
+            out = ctypes.c_double()
+            self._check(L.pcv_path_lambda(h, ctypes.c_double(lambda_factor), ctypes.byref(out)))
+            lam = out.value
+            self._check(L.pcv_set_lambda(h, ctypes.c_double(lam)))
+        self.lam = float(lam)
+        self._out = {}
+
+    # -- helpers --------------------------------------------------------
+    def _check(self, status, h="self"):
+        if status != 0:
+            msg = ""
+            if h == "self" and getattr(self, "_h", None) is not None:
+                msg = (self._L.pcv_last_error(self._h) or b"").decode()
+            raise PcvError(status, msg)
+
+    def _outputs(self, grad, with_msd, close):
+        import torch
+        key = (grad, with_msd, close)
+        if key not in self._out:
+            dev = self.device
+            o = {"sz": torch.empty(2, dtype=torch.float64, device=dev)}
+            if grad:
+                o["ds_dx"] = torch.empty(self.n_atoms, 3, dtype=self.dtype, device=dev)
+                o["dz_dx"] = torch.empty(self.n_atoms, 3, dtype=self.dtype, device=dev)
+            if with_msd:
+                o["msd"] = torch.empty(self.n_landmarks, dtype=torch.float64, device=dev)
+            if close:
+                o["recomputed"] = torch.empty(1, dtype=torch.int32, device=dev)
+            self._out[key] = o
+        return self._out[key]
+
+    def _check_x(self, x):
+        if not (x.is_cuda and x.dtype == self.dtype and tuple(x.shape) == (self.n_atoms, 3) and x.is_contiguous()):
+            raise ValueError(f"x must be a contiguous CUDA {self.dtype} tensor of shape ({self.n_atoms}, 3)")
+
+    # -- Algorithm 1 ----------------------------------------------------
+    def eval(self, x, *, grad: bool = True, msd: bool = False, out: dict | None = None) -> dict:
+        """Exact s, z (``out['sz']``), gradients and optionally every D_i.
+        Results are written asynchronously on the handle's stream; the
+        returned tensors are reused by later calls unless ``out`` is given."""
+        self._check_x(x)
+        o = out if out is not None else self._outputs(grad, msd, False)
+        self._check(self._L.pcv_eval(self._h, _ptr(x), _ptr(o["sz"]), _ptr(o.get("ds_dx")),
+                                     _ptr(o.get("dz_dx")), _ptr(o.get("msd"))))
+        return o
+
+    # -- Algorithm 2 ----------------------------------------------------
+    def eval_close(self, x, *, grad: bool = True, msd: bool = False, out: dict | None = None) -> dict:
+        """One close-structure step; ``out['recomputed']`` is 1 on a
+        reassignment step, 0 on an approximate step."""
+        self._check_x(x)
+        o = out if out is not None else self._outputs(grad, msd, True)
+        self._check(self._L.pcv_eval_close(self._h, _ptr(x), _ptr(o["sz"]), _ptr(o.get("ds_dx")),
+                                           _ptr(o.get("dz_dx")), _ptr(o.get("msd")),
+                                           _ptr(o.get("recomputed"))))
+        return o
+
+    def update_close(self, x):
+        self._check_x(x)
+        self._check(self._L.pcv_update_close(self._h, _ptr(x)))
+
+    def force_reassign(self):
+        self._check(self._L.pcv_force_reassign(self._h))
+
+    def stats(self) -> dict:
+        st = _Stats()
+        self._check(self._L.pcv_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+    def reset_stats(self):
+        self._check(self._L.pcv_reset_stats(self._h))
+
+    def check(self):
+        """Synchronise and raise PcvError(-4) if a non-finite input was seen."""
+        self._check(self._L.pcv_check(self._h))
+
+    @property
+    def plan(self) -> dict:
+        v = [ctypes.c_int() for _ in range(5)]
+        self._check(self._L.pcv_get_plan(self._h, *[ctypes.byref(a) for a in v]))
+        return dict(zip(("wg", "apt", "team", "grid", "items"), (a.value for a in v)))
+
+    def set_plan(self, wg: int, apt: int, team: int, items: int = 0):
+        self._check(self._L.pcv_set_plan(self._h, wg, apt, team, items))
+
+    def set_kernel_timing(self, enable: bool):
+        """Record HIP events around every landmark-kernel launch (calls run
+        eagerly while enabled)."""
+        self._check(self._L.pcv_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self) -> tuple[float, int]:
+        """(summed landmark-kernel milliseconds, launches) since enabling."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        self._check(self._L.pcv_get_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._L.pcv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPathCV:
+    """Many independent walkers (structure + landmark set each, uneven sizes)
+    evaluated exactly by one persistent engine launch.
+
+    ``landmarks``: list of CUDA tensors ``[L_w][n_w][3]`` (same dtype);
+    ``lams``: one sharpness per walker.
+    """
+
+    def __init__(self, landmarks, lams, *, use_graph: bool = True, tune: bool = False,
+                 cache_path: str | None = None, stream=None):
+        import torch
+        L = load_library()
+        self._L = L
+        self.dtype = landmarks[0].dtype
+        self.device = landmarks[0].device
+        self.n = [int(t.shape[1]) for t in landmarks]
+        self.Ls = [int(t.shape[0]) for t in landmarks]
+        self.W = len(landmarks)
+        self.atom_off = [0]
+        for v in self.n:
+            self.atom_off.append(self.atom_off[-1] + v)
+        opt = _Options()
+        L.pcv_default_options(ctypes.byref(opt))
+        opt.device = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        opt.stream = _stream_ptr(stream).value
+        opt.precision = FP64 if self.dtype == torch.float64 else FP32
+        opt.use_graph = 1 if use_graph else 0
+        b = ctypes.c_void_p()
+        st = L.pcv_batch_create(ctypes.byref(b), ctypes.byref(opt))
+        if st != 0:
+            raise PcvError(st, "pcv_batch_create")
+        self._b = b
+        flat = torch.cat([t.contiguous().reshape(-1) for t in landmarks])
+        na = (ctypes.c_int * self.W)(*self.n)
+        nl = (ctypes.c_int * self.W)(*self.Ls)
+        lm = (ctypes.c_double * self.W)(*[float(v) for v in lams])
+        self._check(L.pcv_batch_load(b, self.W, na, nl, _ptr(flat), lm))
+        del flat
+        cp = cache_path.encode() if cache_path else None
+        self._check(L.pcv_batch_plan(b, 1 if tune else 0, cp))
+        self.sz = torch.empty(self.W, 2, dtype=torch.float64, device=self.device)
+        self.ds = torch.empty(self.atom_off[-1], 3, dtype=self.dtype, device=self.device)
+        self.dz = torch.empty(self.atom_off[-1], 3, dtype=self.dtype, device=self.device)
+
+    def _check(self, status):
+        if status != 0:
+            raise PcvError(status, (self._L.pcv_batch_last_error(self._b) or b"").decode())
+
+    @property
+    def plan(self) -> str:
+        return (self._L.pcv_batch_plan_string(self._b) or b"").decode()
+
+    def eval(self, x_all, *, grad: bool = True):
+        """``x_all``: CUDA tensor ``[sum n_w][3]``.  Returns (sz [W][2], ds, dz)."""
+        if not (x_all.is_cuda and x_all.dtype == self.dtype and tuple(x_all.shape) == (self.atom_off[-1], 3)
+                and x_all.is_contiguous()):
+            raise ValueError("x_all must be a contiguous CUDA tensor [sum n_w][3] of the landmark dtype")
+        self._check(self._L.pcv_batch_eval(self._b, _ptr(x_all), _ptr(self.sz),
+                                           _ptr(self.ds) if grad else None, _ptr(self.dz) if grad else None))
+        return self.sz, self.ds, self.dz
+
+    def close(self):
+        if getattr(self, "_b", None) is not None:
+            self._L.pcv_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,596 @@
+// C ABI of the path-CV library (include/pcv.h): handle, planning, Algorithm 1
+// and Algorithm 2 entry points, batched walkers.  Host code only; kernels
+// live in pcv_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcv.h"
+#include "pcv_host_util.h"
+#include "pcv_internal.h"
+
+using namespace pcv;
+
+namespace {
+
+constexpr int kMaxAtomsF32 = 512 * 16;
+constexpr int kMaxAtomsF64 = 256 * 8;
+constexpr int kMaxCloseSlots = 2048;
+
+struct Plan {
+  EngineCfg cfg{256, 1};
+  int ts = 16;
+  int grid = 0;
+  int n_items = 0;
+  size_t lds = 0;
+};
+
+}  // namespace
+
+// ============================================================ single handle
+struct pcv_handle {
+  pcv_options opt{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool fp64 = false;
+  int n = 0, n_pad = 0, L = 0;
+  double lam = 0.0;
+  int cus = 256;
+  DevMem mem;      // landmark-sized buffers (reallocated on load)
+  DevMem pmem;     // plan-sized buffers (partials, descriptors)
+  // landmarks
+  void* A = nullptr;
+  double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr;
+  // frame
+  double* xw = nullptr;
+  void* xc = nullptr;
+  double* Gx = nullptr;
+  int* status = nullptr;
+  // close structure
+  double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
+         *Rxy = nullptr, *Dxy = nullptr, *Rsave = nullptr, *gtmp = nullptr, *scratch_sz = nullptr;
+  void* yT = nullptr;
+  int *flag = nullptr, *init = nullptr, *force = nullptr;
+  long long* counters = nullptr;
+  // plan
+  Plan plan;
+  bool user_plan = false;
+  double* hdr = nullptr;
+  void* vec = nullptr;
+  Problem* d_prob = nullptr;    // [3]: EXACT, EXACT_SAVE, APPROX
+  Item* d_items = nullptr;
+  int* d_wgoff = nullptr;
+  PrepArgs* d_prep = nullptr;   // Algorithm 1 prep arguments (one problem)
+  int plan_version = 0;
+  // graphs
+  struct GraphEntry {
+    const void* key[7];
+    int version;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  double timed_ms = 0.0;
+  long long timed_launches = 0;
+  std::string err;
+};
+
+static pcv_status fail(pcv_handle* h, pcv_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+static pcv_status hip_fail(pcv_handle* h, hipError_t e, const char* where) {
+  return fail(h, e == hipErrorOutOfMemory ? PCV_ENOMEM : PCV_EHIP,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr)                                  \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail((h), _e, #expr); \
+  } while (0)
+
+static void collect_timing(pcv_handle* h);
+
+static void drop_graphs(pcv_handle* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
+extern "C" void pcv_default_options(pcv_options* opt) {
+  if (!opt) return;
+  opt->device = 0;
+  opt->stream = nullptr;
+  opt->precision = PCV_FP32;
+  opt->eps = 0.01;
+  opt->use_graph = 1;
+}
+
+extern "C" int pcv_max_atoms(int precision) {
+  return precision == PCV_FP64 ? kMaxAtomsF64 : kMaxAtomsF32;
+}
+
+extern "C" pcv_status pcv_create(pcv_handle** out, const pcv_options* opt) {
+  if (!out) return PCV_EINVAL;
+  *out = nullptr;
+  pcv_options o;
+  pcv_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != PCV_FP32 && o.precision != PCV_FP64) return PCV_EINVAL;
+  if (std::isnan(o.eps)) return PCV_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) return PCV_EHIP;
+  if (hipSetDevice(o.device) != hipSuccess) return PCV_EHIP;
+  pcv_handle* h = new pcv_handle();
+  h->opt = o;
+  h->fp64 = (o.precision == PCV_FP64);
+  h->stream = (hipStream_t)o.stream;
+  h->cus = num_cus(o.device);
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return PCV_EHIP;
+  }
+  if (engine_init_attributes() != hipSuccess) {
+    (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+    return PCV_EHIP;
+  }
+  *out = h;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_destroy(pcv_handle* h) {
+  if (!h) return PCV_OK;
+  (void)hipSetDevice(h->opt.device);
+  (void)hipStreamSynchronize(h->stream);
+  collect_timing(h);
+  drop_graphs(h);
+  h->pmem.release();
+  h->mem.release();
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+  return PCV_OK;
+}
+
+// Build (or rebuild) work items and problem descriptors for the current plan.
+static pcv_status build_plan(pcv_handle* h) {
+  Plan& p = h->plan;
+  const size_t acc = h->fp64 ? 8 : 4;
+  const int teams = p.cfg.wg / p.ts;
+  if (!h->user_plan || p.n_items <= 0) {
+    int want = (h->L + teams - 1) / teams;
+    const int cap = (p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
+    p.n_items = std::max(1, std::min(want, cap));
+  }
+  p.n_items = std::min(p.n_items, h->L);
+  p.n_items = std::min(p.n_items, kMaxCloseSlots);
+  p.grid = p.n_items;
+  p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
+  h->pmem.release();
+  HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, (size_t)p.n_items * 4 * sizeof(double)));
+  HIP_TRY(h, h->pmem.alloc(&h->vec, (size_t)p.n_items * 6 * h->n_pad * acc));
+  HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 3 * sizeof(Problem)));
+  HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
+  HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
+  HIP_TRY(h, h->pmem.alloc((void**)&h->d_prep, sizeof(PrepArgs)));
+  PrepArgs pa{0, h->w, h->xw, h->xc, h->Gx, h->status, h->counters, h->n, h->n_pad, h->L};
+  HIP_TRY(h, hipMemcpy(h->d_prep, &pa, sizeof(pa), hipMemcpyHostToDevice));
+  std::vector<Item> items(p.n_items);
+  std::vector<int> wgoff(p.grid + 1);
+  for (int k = 0; k < p.n_items; ++k) {
+    items[k].prob = 0;
+    items[k].i0 = (int)((long long)k * h->L / p.n_items);
+    items[k].i1 = (int)((long long)(k + 1) * h->L / p.n_items);
+    items[k].slot = k;
+    wgoff[k] = k;
+  }
+  wgoff[p.grid] = p.n_items;
+  Problem base{};
+  base.A = h->A;
+  base.ca = h->ca;
+  base.Ga = h->Ga;
+  base.q = h->q;
+  base.w = h->w;
+  base.xw = h->xw;
+  base.xg = h->xc;
+  base.Gx = h->Gx;
+  base.Rxy = h->Rxy;
+  base.Rsave = h->Rsave;
+  base.hdr = h->hdr;
+  base.vec = h->vec;
+  base.fallbacks = h->counters + CNT_FALLBACK;
+  base.n = h->n;
+  base.n_pad = h->n_pad;
+  base.L = h->L;
+  base.ts = p.ts;
+  base.n_slots = p.n_items;
+  base.out_off = 0;
+  base.out_idx = 0;
+  base.lam = h->lam;
+  Problem probs[3] = {base, base, base};
+  probs[2].xg = h->yT;   // approximate step measures residuals against y
+  HIP_TRY(h, hipMemcpy(h->d_prob, probs, sizeof(probs), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->plan_version++;
+  drop_graphs(h);
+  return PCV_OK;
+}
+
+static void default_plan(pcv_handle* h) {
+  EngineCfg menu[16];
+  int cnt = 0;
+  engine_configs(h->fp64, menu, &cnt);
+  double best = 1e300;
+  for (int k = 0; k < cnt; ++k) {
+    const int ts = team_size(h->n, menu[k]);
+    if (ts == 0) continue;
+    const double c = landmark_cost(h->n, menu[k], ts);
+    if (c < best) {
+      best = c;
+      h->plan.cfg = menu[k];
+      h->plan.ts = ts;
+    }
+  }
+  h->plan.n_items = 0;
+  h->user_plan = false;
+}
+
+extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landmarks, const void* coords,
+                                         const double* q, const double* w, double lambda) {
+  if (!h) return PCV_EINVAL;
+  if (!coords || n_atoms < 1 || n_landmarks < 1) return fail(h, PCV_EINVAL, "bad sizes or null coords");
+  if (n_atoms > pcv_max_atoms(h->opt.precision))
+    return fail(h, PCV_ESHAPE, "n_atoms exceeds pcv_max_atoms()");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(h, PCV_EINVAL, "lambda must be positive and finite");
+  std::vector<double> hw(n_atoms, 1.0);
+  if (w) {
+    double s = 0.0;
+    for (int j = 0; j < n_atoms; ++j) {
+      if (!(w[j] >= 0.0) || !std::isfinite(w[j])) return fail(h, PCV_EINVAL, "weights must be finite and >= 0");
+      s += w[j];
+    }
+    if (!(s > 0.0)) return fail(h, PCV_EINVAL, "weights must have a positive sum");
+    for (int j = 0; j < n_atoms; ++j) hw[j] = w[j] / s;
+  } else {
+    for (int j = 0; j < n_atoms; ++j) hw[j] = 1.0 / n_atoms;
+  }
+  std::vector<double> hq(n_landmarks);
+  for (int i = 0; i < n_landmarks; ++i) {
+    hq[i] = q ? q[i] : (double)(i + 1);
+    if (!std::isfinite(hq[i])) return fail(h, PCV_EINVAL, "properties must be finite");
+  }
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  drop_graphs(h);
+  h->pmem.release();
+  h->mem.release();
+  h->n = n_atoms;
+  h->n_pad = round_up(n_atoms, 64);
+  h->L = n_landmarks;
+  h->lam = lambda;
+  const size_t tsz = h->fp64 ? 8 : 4;
+  const size_t np = h->n_pad, L = h->L;
+  DevMem& m = h->mem;
+  HIP_TRY(h, m.alloc(&h->A, L * 3 * np * tsz));
+  HIP_TRY(h, m.alloc((void**)&h->ca, L * 3 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Ga, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->q, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->w, np * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->xw, 3 * np * sizeof(double)));
+  HIP_TRY(h, m.alloc(&h->xc, 3 * np * tsz));
+  HIP_TRY(h, m.alloc((void**)&h->Gx, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
+  HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
+  HIP_TRY(h, m.alloc(&h->yT, 3 * np * tsz));
+  HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Fxy, 10 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->lamxy, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->qxy, 4 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rxy, 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Dxy, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rsave, L * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->gtmp, 12 * np * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->scratch_sz, 2 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->flag, sizeof(int)));
+  HIP_TRY(h, m.alloc((void**)&h->init, sizeof(int)));
+  HIP_TRY(h, m.alloc((void**)&h->force, sizeof(int)));
+  HIP_TRY(h, m.alloc((void**)&h->counters, CNT_N * sizeof(long long)));
+  std::vector<double> wpad(np, 0.0);
+  std::copy(hw.begin(), hw.end(), wpad.begin());
+  HIP_TRY(h, hipMemcpy(h->w, wpad.data(), np * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->q, hq.data(), L * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemset(h->init, 0, sizeof(int)));
+  HIP_TRY(h, hipMemset(h->force, 0, sizeof(int)));
+  HIP_TRY(h, hipMemset(h->flag, 0, sizeof(int)));
+  HIP_TRY(h, hipMemset(h->status, 0, sizeof(int)));
+  HIP_TRY(h, hipMemset(h->counters, 0, CNT_N * sizeof(long long)));
+  HIP_TRY(h, hipMemset(h->y64, 0, 3 * np * sizeof(double)));
+  HIP_TRY(h, hipMemset(h->yT, 0, 3 * np * tsz));
+  HIP_TRY(h, hipMemset(h->Rsave, 0, L * 9 * sizeof(double)));
+  hipError_t e = h->fp64 ? launch_load_landmarks<double>((const double*)coords, (double*)h->A, h->ca, h->Ga,
+                                                         h->w, h->n, h->n_pad, h->L, h->stream)
+                         : launch_load_landmarks<float>((const float*)coords, (float*)h->A, h->ca, h->Ga,
+                                                        h->w, h->n, h->n_pad, h->L, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "load_landmarks");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  default_plan(h);
+  return build_plan(h);
+}
+
+extern "C" pcv_status pcv_set_lambda(pcv_handle* h, double lambda) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(h, PCV_EINVAL, "lambda must be positive and finite");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->lam = lambda;
+  HIP_TRY(h, hipMemset(h->init, 0, sizeof(int)));
+  return build_plan(h);
+}
+
+extern "C" pcv_status pcv_path_lambda(pcv_handle* h, double factor, double* lambda_out) {
+  if (!h || !lambda_out) return PCV_EINVAL;
+  if (h->L < 2) return fail(h, PCV_ESTATE, "needs at least two landmarks");
+  double* d = nullptr;
+  HIP_TRY(h, hipMalloc((void**)&d, (h->L - 1) * sizeof(double)));
+  hipError_t e = h->fp64 ? launch_pair_msd<double>((const double*)h->A, h->ca, h->Ga, h->w, h->n, h->n_pad,
+                                                   h->L, d, h->stream)
+                         : launch_pair_msd<float>((const float*)h->A, h->ca, h->Ga, h->w, h->n, h->n_pad,
+                                                  h->L, d, h->stream);
+  std::vector<double> hd(h->L - 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(hd.data(), d, hd.size() * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(h, e, "pair_msd");
+  double s = 0.0;
+  for (double v : hd) s += v;
+  const double mean = s / hd.size();
+  if (!(mean > 0.0)) return fail(h, PCV_EINVAL, "consecutive landmarks coincide; lambda undefined");
+  *lambda_out = factor / mean;
+  return PCV_OK;
+}
+
+// ---------------------------------------------------------------- Algorithm 1
+// Engine launch bracketed by events when kernel timing is on.
+template <typename T>
+static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, st);
+  }
+  hipError_t e = launch_engine<T>(h->plan.cfg, h->plan.grid, h->plan.lds, h->d_prob + mode, h->d_items,
+                                  h->d_wgoff, mode, flag, run_if, msd, st);
+  if (h->timing) {
+    (void)hipEventRecord(e1, st);
+    h->ev_pending.emplace_back(e0, e1);
+  }
+  return e;
+}
+
+template <typename T>
+static hipError_t enqueue_exact(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
+                                void* dz, double* msd, PrepArgs* d_pa) {
+  hipError_t e = launch_prep<T>(d_pa, x, 1, st);
+  if (e != hipSuccess) return e;
+  e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, msd);
+  if (e != hipSuccess) return e;
+  Outs o{ds, dz, sz, nullptr};
+  return launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+}
+
+template <typename T>
+static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
+                                void* dz, double* msd, int* rec) {
+  PrepArgs pa{0, h->w, h->xw, h->xc, h->Gx, h->status, nullptr, h->n, h->n_pad, h->L};
+  CloseArgs ca{h->y64, h->yT, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+  Outs o{ds, dz, sz, rec};
+  hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
+  if (e != hipSuccess) return e;
+  e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, msd);
+  if (e != hipSuccess) return e;
+  e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, msd);
+  if (e != hipSuccess) return e;
+  e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+  if (e != hipSuccess) return e;
+  return launch_merge_close<T>(h->d_prob + MODE_APPROX, o, ca, h->gtmp, st);
+}
+
+// Run an enqueue function directly or through a cached hipGraph keyed on the
+// call's pointers.
+template <typename F>
+static pcv_status run_maybe_graph(pcv_handle* h, const void* const key[7], F&& enqueue) {
+  if (!h->opt.use_graph || h->timing) {
+    hipError_t e = enqueue(h->stream);
+    return e == hipSuccess ? PCV_OK : hip_fail(h, e, "enqueue");
+  }
+  for (auto& g : h->graphs) {
+    if (g.version == h->plan_version && std::equal(key, key + 7, g.key)) {
+      HIP_TRY(h, hipGraphLaunch(g.exec, h->stream));
+      return PCV_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue(h->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(h, e, "capture");
+  }
+  if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+  if (h->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(h->graphs.front().exec);
+    h->graphs.erase(h->graphs.begin());
+  }
+  pcv_handle::GraphEntry ge;
+  std::copy(key, key + 7, ge.key);
+  ge.version = h->plan_version;
+  ge.exec = exec;
+  h->graphs.push_back(ge);
+  HIP_TRY(h, hipGraphLaunch(exec, h->stream));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx, double* msd) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
+  PrepArgs* d_pa = h->d_prep;
+  const void* key[7] = {x, sz, ds_dx, dz_dx, msd, nullptr, (const void*)1};
+  return run_maybe_graph(h, key, [&](hipStream_t st) {
+    return h->fp64 ? enqueue_exact<double>(h, st, x, sz, ds_dx, dz_dx, msd, d_pa)
+                   : enqueue_exact<float>(h, st, x, sz, ds_dx, dz_dx, msd, d_pa);
+  });
+}
+
+// ---------------------------------------------------------------- Algorithm 2
+extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx,
+                                     double* msd, int* recomputed) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
+  const void* key[7] = {x, sz, ds_dx, dz_dx, msd, recomputed, (const void*)2};
+  return run_maybe_graph(h, key, [&](hipStream_t st) {
+    return h->fp64 ? enqueue_close<double>(h, st, x, sz, ds_dx, dz_dx, msd, recomputed)
+                   : enqueue_close<float>(h, st, x, sz, ds_dx, dz_dx, msd, recomputed);
+  });
+}
+
+extern "C" pcv_status pcv_force_reassign(pcv_handle* h) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  hipError_t e = launch_set_int(h->force, 1, h->stream);
+  return e == hipSuccess ? PCV_OK : hip_fail(h, e, "force");
+}
+
+extern "C" pcv_status pcv_update_close(pcv_handle* h, const void* x) {
+  pcv_status s = pcv_force_reassign(h);
+  if (s != PCV_OK) return s;
+  return pcv_eval_close(h, x, h->scratch_sz, nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out) {
+  if (!h || !out) return PCV_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  if (h->L == 0) return PCV_OK;
+  long long c[CNT_N];
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(c, h->counters, sizeof(c), hipMemcpyDeviceToHost));
+  out->frames = c[CNT_FRAMES];
+  out->recomputes = c[CNT_RECOMPUTES];
+  out->expensive_msd = c[CNT_EXPENSIVE];
+  out->approx_frames = c[CNT_APPROX];
+  out->exact_evals = c[CNT_EVALS];
+  out->eigen_fallbacks = c[CNT_FALLBACK];
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_reset_stats(pcv_handle* h) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return PCV_OK;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemset(h->counters, 0, CNT_N * sizeof(long long)));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_check(pcv_handle* h) {
+  if (!h) return PCV_EINVAL;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (h->L == 0) return PCV_OK;
+  int st = 0;
+  HIP_TRY(h, hipMemcpy(&st, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    HIP_TRY(h, hipMemset(h->status, 0, sizeof(int)));
+    return fail(h, PCV_ENONFINITE, "non-finite coordinates in an input structure");
+  }
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_get_plan(pcv_handle* h, int* wg, int* apt, int* team, int* grid, int* items) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (wg) *wg = h->plan.cfg.wg;
+  if (apt) *apt = h->plan.cfg.apt;
+  if (team) *team = h->plan.ts;
+  if (grid) *grid = h->plan.grid;
+  if (items) *items = h->plan.n_items;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_set_plan(pcv_handle* h, int wg, int apt, int team, int items) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  EngineCfg c{wg, apt};
+  if (!engine_supported(c, h->fp64)) return fail(h, PCV_EUNSUPPORTED, "tiling not compiled in");
+  if (team < 16 || team > wg || (team & (team - 1)) || (long long)team * apt < h->n)
+    return fail(h, PCV_EINVAL, "team must be a power of two in [16, wg] with team*apt >= n");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->plan.cfg = c;
+  h->plan.ts = team;
+  h->plan.n_items = items;
+  h->user_plan = true;
+  return build_plan(h);
+}
+
+static void collect_timing(pcv_handle* h) {
+  for (auto& pr : h->ev_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      h->timed_ms += ms;
+      h->timed_launches += 1;
+    }
+    hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  h->ev_pending.clear();
+}
+
+extern "C" pcv_status pcv_set_kernel_timing(pcv_handle* h, int enable) {
+  if (!h) return PCV_EINVAL;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  collect_timing(h);
+  h->timing = enable != 0;
+  h->timed_ms = 0.0;
+  h->timed_launches = 0;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_get_kernel_timing(pcv_handle* h, double* engine_ms, int64_t* engine_launches) {
+  if (!h || !engine_ms || !engine_launches) return PCV_EINVAL;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  collect_timing(h);
+  *engine_ms = h->timed_ms;
+  *engine_launches = h->timed_launches;
+  return PCV_OK;
+}
+
+extern "C" const char* pcv_status_string(pcv_status s) {
+  switch (s) {
+    case PCV_OK: return "ok";
+    case PCV_EINVAL: return "invalid argument";
+    case PCV_ESTATE: return "invalid call order";
+    case PCV_ESHAPE: return "unsupported size";
+    case PCV_ENONFINITE: return "non-finite input";
+    case PCV_EHIP: return "HIP runtime error";
+    case PCV_ENOMEM: return "out of device memory";
+    case PCV_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* pcv_last_error(const pcv_handle* h) { return h ? h->err.c_str() : "null handle"; }

@@ -1,0 +1,552 @@
+// Batched walkers: many independent (structure, landmark set) problems of
+// uneven size in one persistent launch of the landmark engine (Algorithm 1
+// per walker), a static longest-processing-time schedule of work items over
+// the workgroups, hipGraph replay, and an autotuner over tilings and
+// schedules whose candidates must reproduce the heuristic plan's results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "pcv.h"
+#include "pcv_host_util.h"
+#include "pcv_internal.h"
+
+using namespace pcv;
+
+namespace {
+
+struct BatchPlan {
+  EngineCfg cfg{256, 8};
+  int per_team = 4;     // landmarks per team per work item
+  int grid_mult = 2;    // workgroups = grid_mult * CUs
+  int lpt = 1;          // 1: longest-processing-time schedule, 0: round robin
+  std::string str() const {
+    std::ostringstream o;
+    o << "wg=" << cfg.wg << " apt=" << cfg.apt << " per_team=" << per_team << " grid_mult=" << grid_mult
+      << " schedule=" << (lpt ? "lpt" : "rr");
+    return o.str();
+  }
+};
+
+}  // namespace
+
+struct pcv_batch {
+  pcv_options opt{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool fp64 = false;
+  int cus = 256;
+  int W = 0;
+  std::vector<int> n, L, n_pad, atom_off, lm_off, pad_off;
+  std::vector<double> lam;
+  long long total_pairs = 0;
+  DevMem mem, pmem;
+  void* A = nullptr;
+  double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr, *xw = nullptr, *Gx = nullptr;
+  void* xc = nullptr;
+  int* status = nullptr;
+  PrepArgs* d_prep = nullptr;
+  // plan
+  BatchPlan plan;
+  bool planned = false;
+  int grid = 0, n_items = 0;
+  size_t lds = 0;
+  Problem* d_prob = nullptr;
+  Item* d_items = nullptr;
+  int* d_wgoff = nullptr;
+  double* hdr = nullptr;
+  void* vec = nullptr;
+  int max_n_pad = 0;
+  int plan_version = 0;
+  struct GraphEntry {
+    const void* key[4];
+    int version;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  std::string plan_str, err;
+};
+
+static pcv_status bfail(pcv_batch* b, pcv_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+static pcv_status bhip(pcv_batch* b, hipError_t e, const char* where) {
+  return bfail(b, e == hipErrorOutOfMemory ? PCV_ENOMEM : PCV_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define BHIP_TRY(b, expr)                                 \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return bhip((b), _e, #expr);     \
+  } while (0)
+
+static void bdrop_graphs(pcv_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
+extern "C" pcv_status pcv_batch_create(pcv_batch** out, const pcv_options* opt) {
+  if (!out) return PCV_EINVAL;
+  *out = nullptr;
+  pcv_options o;
+  pcv_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != PCV_FP32 && o.precision != PCV_FP64) return PCV_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) return PCV_EHIP;
+  if (hipSetDevice(o.device) != hipSuccess) return PCV_EHIP;
+  pcv_batch* b = new pcv_batch();
+  b->opt = o;
+  b->fp64 = o.precision == PCV_FP64;
+  b->stream = (hipStream_t)o.stream;
+  b->cus = num_cus(o.device);
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      engine_init_attributes() != hipSuccess) {
+    delete b;
+    return PCV_EHIP;
+  }
+  *out = b;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_batch_destroy(pcv_batch* b) {
+  if (!b) return PCV_OK;
+  (void)hipSetDevice(b->opt.device);
+  (void)hipStreamSynchronize(b->stream);
+  bdrop_graphs(b);
+  b->pmem.release();
+  b->mem.release();
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, const int* n_landmarks,
+                                     const void* coords, const double* lambdas) {
+  if (!b) return PCV_EINVAL;
+  if (W < 1 || !n_atoms || !n_landmarks || !coords || !lambdas) return bfail(b, PCV_EINVAL, "bad arguments");
+  const int maxn = pcv_max_atoms(b->opt.precision);
+  for (int i = 0; i < W; ++i) {
+    if (n_atoms[i] < 1 || n_landmarks[i] < 1) return bfail(b, PCV_EINVAL, "walker sizes must be >= 1");
+    if (n_atoms[i] > maxn) return bfail(b, PCV_ESHAPE, "walker n_atoms exceeds pcv_max_atoms()");
+    if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i])) return bfail(b, PCV_EINVAL, "lambda must be positive");
+  }
+  BHIP_TRY(b, hipSetDevice(b->opt.device));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  bdrop_graphs(b);
+  b->pmem.release();
+  b->mem.release();
+  b->planned = false;
+  b->W = W;
+  b->n.assign(n_atoms, n_atoms + W);
+  b->L.assign(n_landmarks, n_landmarks + W);
+  b->lam.assign(lambdas, lambdas + W);
+  b->n_pad.resize(W);
+  b->atom_off.resize(W + 1);
+  b->lm_off.resize(W + 1);
+  b->pad_off.resize(W + 1);
+  b->atom_off[0] = b->lm_off[0] = b->pad_off[0] = 0;
+  b->total_pairs = 0;
+  b->max_n_pad = 0;
+  size_t a_elems = 0;
+  std::vector<size_t> a_off(W + 1, 0), in_off(W + 1, 0);
+  for (int i = 0; i < W; ++i) {
+    b->n_pad[i] = round_up(b->n[i], 64);
+    b->max_n_pad = std::max(b->max_n_pad, b->n_pad[i]);
+    b->atom_off[i + 1] = b->atom_off[i] + b->n[i];
+    b->lm_off[i + 1] = b->lm_off[i] + b->L[i];
+    b->pad_off[i + 1] = b->pad_off[i] + b->n_pad[i];
+    a_off[i + 1] = a_off[i] + (size_t)b->L[i] * 3 * b->n_pad[i];
+    in_off[i + 1] = in_off[i] + (size_t)b->L[i] * b->n[i] * 3;
+    b->total_pairs += (long long)b->n[i] * b->L[i];
+  }
+  a_elems = a_off[W];
+  const size_t tsz = b->fp64 ? 8 : 4;
+  const size_t Ltot = b->lm_off[W], Ptot = b->pad_off[W];
+  DevMem& m = b->mem;
+  BHIP_TRY(b, m.alloc(&b->A, a_elems * tsz));
+  BHIP_TRY(b, m.alloc((void**)&b->ca, Ltot * 3 * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->Ga, Ltot * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->q, Ltot * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->w, Ptot * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->xw, 3 * Ptot * sizeof(double)));
+  BHIP_TRY(b, m.alloc(&b->xc, 3 * Ptot * tsz));
+  BHIP_TRY(b, m.alloc((void**)&b->Gx, W * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->status, W * sizeof(int)));
+  BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
+  std::vector<double> hw(Ptot, 0.0), hq(Ltot);
+  std::vector<PrepArgs> pa(W);
+  for (int i = 0; i < W; ++i) {
+    for (int j = 0; j < b->n[i]; ++j) hw[b->pad_off[i] + j] = 1.0 / b->n[i];
+    for (int k = 0; k < b->L[i]; ++k) hq[b->lm_off[i] + k] = k + 1;
+    const size_t po = b->pad_off[i];
+    pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po,
+                     (char*)b->xc + 3 * po * tsz, b->Gx + i, b->status + i, nullptr,
+                     b->n[i], b->n_pad[i], b->L[i]};
+  }
+  BHIP_TRY(b, hipMemcpy(b->w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->q, hq.data(), hq.size() * sizeof(double), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_prep, pa.data(), W * sizeof(PrepArgs), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemset(b->status, 0, W * sizeof(int)));
+  for (int i = 0; i < W; ++i) {
+    const size_t lo = b->lm_off[i], po = b->pad_off[i];
+    hipError_t e = b->fp64
+        ? launch_load_landmarks<double>((const double*)coords + in_off[i], (double*)b->A + a_off[i], b->ca + 3 * lo,
+                                        b->Ga + lo, b->w + po, b->n[i], b->n_pad[i], b->L[i], b->stream)
+        : launch_load_landmarks<float>((const float*)coords + in_off[i], (float*)b->A + a_off[i], b->ca + 3 * lo,
+                                       b->Ga + lo, b->w + po, b->n[i], b->n_pad[i], b->L[i], b->stream);
+    if (e != hipSuccess) return bhip(b, e, "load_landmarks");
+  }
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return PCV_OK;
+}
+
+// Lay out items and partial slots for a plan and upload the descriptors.
+static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
+  const size_t tsz = b->fp64 ? 8 : 4;
+  std::vector<int> ts(b->W);
+  for (int i = 0; i < b->W; ++i) {
+    ts[i] = team_size(b->n[i], p.cfg);
+    if (ts[i] == 0) return bfail(b, PCV_ESHAPE, "tiling cannot hold a walker");
+  }
+  struct It {
+    Item it;
+    double cost;
+  };
+  std::vector<It> items;
+  std::vector<int> slots(b->W, 0), slot_base(b->W + 1, 0);
+  size_t vec_elems = 0;
+  std::vector<size_t> vec_off(b->W);
+  for (int i = 0; i < b->W; ++i) {
+    const int teams = p.cfg.wg / ts[i];
+    const int chunk = std::max(1, teams * p.per_team);
+    const int cnt = (b->L[i] + chunk - 1) / chunk;
+    const double per_lm = landmark_cost(b->n[i], p.cfg, ts[i]);
+    for (int k = 0; k < cnt; ++k) {
+      Item it;
+      it.prob = i;
+      it.i0 = k * chunk;
+      it.i1 = std::min(b->L[i], (k + 1) * chunk);
+      it.slot = k;
+      const int iters = (it.i1 - it.i0 + teams - 1) / teams;
+      items.push_back({it, per_lm * iters * teams / (double)p.cfg.wg + 2000.0});
+    }
+    slots[i] = cnt;
+    slot_base[i + 1] = slot_base[i] + cnt;
+    vec_off[i] = vec_elems;
+    vec_elems += (size_t)cnt * 6 * b->n_pad[i];
+  }
+  const int G = std::max(1, std::min((int)items.size(), p.grid_mult * b->cus));
+  std::vector<std::vector<int>> per_wg(G);
+  std::vector<int> order(items.size());
+  std::iota(order.begin(), order.end(), 0);
+  if (p.lpt) {
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return items[a].cost > items[c].cost; });
+    std::vector<double> load(G, 0.0);
+    for (int k : order) {
+      int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      per_wg[best].push_back(k);
+      load[best] += items[k].cost;
+    }
+  } else {
+    for (size_t k = 0; k < items.size(); ++k) per_wg[k % G].push_back((int)k);
+  }
+  std::vector<Item> flat;
+  std::vector<int> wgoff(G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    wgoff[g] = (int)flat.size();
+    for (int k : per_wg[g]) flat.push_back(items[k].it);
+  }
+  wgoff[G] = (int)flat.size();
+  size_t lds = 0;
+  for (int i = 0; i < b->W; ++i) lds = std::max(lds, engine_lds_bytes(p.cfg, ts[i], b->fp64));
+
+  bdrop_graphs(b);
+  b->pmem.release();
+  BHIP_TRY(b, b->pmem.alloc((void**)&b->hdr, (size_t)slot_base[b->W] * 4 * sizeof(double)));
+  BHIP_TRY(b, b->pmem.alloc(&b->vec, vec_elems * tsz));
+  BHIP_TRY(b, b->pmem.alloc((void**)&b->d_prob, b->W * sizeof(Problem)));
+  BHIP_TRY(b, b->pmem.alloc((void**)&b->d_items, flat.size() * sizeof(Item)));
+  BHIP_TRY(b, b->pmem.alloc((void**)&b->d_wgoff, (G + 1) * sizeof(int)));
+  std::vector<Problem> probs(b->W);
+  size_t a_off = 0;
+  for (int i = 0; i < b->W; ++i) {
+    const size_t lo = b->lm_off[i], po = b->pad_off[i];
+    Problem P{};
+    P.A = (const char*)b->A + a_off * tsz;
+    P.ca = b->ca + 3 * lo;
+    P.Ga = b->Ga + lo;
+    P.q = b->q + lo;
+    P.w = b->w + po;
+    P.xw = b->xw + 3 * po;
+    P.xg = (const char*)b->xc + 3 * po * tsz;
+    P.Gx = b->Gx + i;
+    P.Rxy = nullptr;
+    P.Rsave = nullptr;
+    P.hdr = b->hdr + (size_t)slot_base[i] * 4;
+    P.vec = (char*)b->vec + vec_off[i] * tsz;
+    P.fallbacks = nullptr;
+    P.n = b->n[i];
+    P.n_pad = b->n_pad[i];
+    P.L = b->L[i];
+    P.ts = ts[i];
+    P.n_slots = slots[i];
+    P.out_off = b->atom_off[i];
+    P.out_idx = i;
+    P.lam = b->lam[i];
+    probs[i] = P;
+    a_off += (size_t)b->L[i] * 3 * b->n_pad[i];
+  }
+  BHIP_TRY(b, hipMemcpy(b->d_prob, probs.data(), probs.size() * sizeof(Problem), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_items, flat.data(), flat.size() * sizeof(Item), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
+  b->plan = p;
+  b->grid = G;
+  b->n_items = (int)flat.size();
+  b->lds = lds;
+  b->planned = true;
+  b->plan_version++;
+  b->plan_str = p.str() + " items=" + std::to_string(b->n_items) + " grid=" + std::to_string(G);
+  return PCV_OK;
+}
+
+template <typename T>
+static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, double* sz, void* ds, void* dz) {
+  hipError_t e = launch_prep<T>(b->d_prep, x, b->W, st);
+  if (e != hipSuccess) return e;
+  e = launch_engine<T>(b->plan.cfg, b->grid, b->lds, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0,
+                       nullptr, st);
+  if (e != hipSuccess) return e;
+  Outs o{ds, dz, sz, nullptr};
+  return launch_merge_exact<T>(b->d_prob, o, b->W, b->max_n_pad, nullptr, 0, st);
+}
+
+static pcv_status batch_run(pcv_batch* b, const void* x, double* sz, void* ds, void* dz, bool allow_graph) {
+  auto enq = [&](hipStream_t st) {
+    return b->fp64 ? batch_enqueue<double>(b, st, x, sz, ds, dz) : batch_enqueue<float>(b, st, x, sz, ds, dz);
+  };
+  if (!b->opt.use_graph || !allow_graph) {
+    hipError_t e = enq(b->stream);
+    return e == hipSuccess ? PCV_OK : bhip(b, e, "batch enqueue");
+  }
+  const void* key[4] = {x, sz, ds, dz};
+  for (auto& g : b->graphs)
+    if (g.version == b->plan_version && std::equal(key, key + 4, g.key)) {
+      BHIP_TRY(b, hipGraphLaunch(g.exec, b->stream));
+      return PCV_OK;
+    }
+  hipGraph_t graph = nullptr;
+  BHIP_TRY(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enq(b->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return bhip(b, e, "capture");
+  }
+  if (e2 != hipSuccess) return bhip(b, e2, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return bhip(b, e, "hipGraphInstantiate");
+  if (b->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(b->graphs.front().exec);
+    b->graphs.erase(b->graphs.begin());
+  }
+  pcv_batch::GraphEntry ge;
+  std::copy(key, key + 4, ge.key);
+  ge.version = b->plan_version;
+  ge.exec = exec;
+  b->graphs.push_back(ge);
+  BHIP_TRY(b, hipGraphLaunch(exec, b->stream));
+  return PCV_OK;
+}
+
+static BatchPlan heuristic_plan(const pcv_batch* b) {
+  EngineCfg menu[16];
+  int cnt = 0;
+  engine_configs(b->fp64, menu, &cnt);
+  const int maxn = *std::max_element(b->n.begin(), b->n.end());
+  BatchPlan best;
+  double best_cost = 1e300;
+  for (int k = 0; k < cnt; ++k) {
+    if (team_size(maxn, menu[k]) == 0) continue;
+    double c = 0.0;
+    for (int i = 0; i < b->W; ++i) c += b->L[i] * landmark_cost(b->n[i], menu[k], team_size(b->n[i], menu[k]));
+    if (c < best_cost) {
+      best_cost = c;
+      best.cfg = menu[k];
+    }
+  }
+  best.per_team = 4;
+  best.grid_mult = best.cfg.wg >= 512 ? 1 : 2;
+  best.lpt = 1;
+  return best;
+}
+
+static std::string shape_key(const pcv_batch* b) {
+  unsigned long long hsh = 1469598103934665603ull;
+  for (int i = 0; i < b->W; ++i) {
+    hsh = (hsh ^ (unsigned long long)b->n[i]) * 1099511628211ull;
+    hsh = (hsh ^ (unsigned long long)b->L[i]) * 1099511628211ull;
+  }
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, b->opt.device) == hipSuccess) dev = prop.gcnArchName;
+  std::ostringstream o;
+  o << dev << ":" << (b->fp64 ? "f64" : "f32") << ":W" << b->W << ":" << std::hex << hsh;
+  return o.str();
+}
+
+// Minimal JSON cache: one line per entry, "key": "wg apt per_team grid_mult lpt".
+static bool cache_lookup(const char* path, const std::string& key, BatchPlan* p) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    const std::string k = "\"" + key + "\": \"";
+    const size_t at = line.find(k);
+    if (at == std::string::npos) continue;
+    std::istringstream v(line.substr(at + k.size()));
+    BatchPlan q;
+    if (v >> q.cfg.wg >> q.cfg.apt >> q.per_team >> q.grid_mult >> q.lpt) {
+      *p = q;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void cache_store(const char* path, const std::string& key, const BatchPlan& p) {
+  if (!path) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line))
+      if (line.find("\"" + key + "\"") == std::string::npos && line.find("\": \"") != std::string::npos)
+        lines.push_back(line);
+  }
+  std::ofstream f(path);
+  f << "{\n";
+  for (auto& l : lines) {
+    std::string t = l;
+    while (!t.empty() && (t.back() == ',' || t.back() == ' ')) t.pop_back();
+    f << t << ",\n";
+  }
+  f << "  \"" << key << "\": \"" << p.cfg.wg << " " << p.cfg.apt << " " << p.per_team << " " << p.grid_mult << " "
+    << p.lpt << "\"\n}\n";
+}
+
+extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path) {
+  if (!b) return PCV_EINVAL;
+  if (b->W == 0) return bfail(b, PCV_ESTATE, "no walkers loaded");
+  BHIP_TRY(b, hipSetDevice(b->opt.device));
+  const BatchPlan base = heuristic_plan(b);
+  const std::string key = shape_key(b);
+  BatchPlan cached;
+  if (tune && cache_lookup(cache_path, key, &cached)) {
+    if (batch_apply(b, cached) == PCV_OK) return PCV_OK;
+  }
+  pcv_status s = batch_apply(b, base);
+  if (s != PCV_OK || !tune) return s;
+
+  // Autotune: reference outputs from the heuristic plan, then every candidate.
+  const size_t tsz = b->fp64 ? 8 : 4;
+  const int natoms = b->atom_off[b->W];
+  void *x = nullptr, *ds = nullptr, *ds_ref = nullptr;
+  double *sz = nullptr, *sz_ref = nullptr;
+  DevMem tmp;
+  BHIP_TRY(b, tmp.alloc(&x, (size_t)natoms * 3 * tsz));
+  BHIP_TRY(b, tmp.alloc(&ds, (size_t)natoms * 3 * tsz));
+  BHIP_TRY(b, tmp.alloc(&ds_ref, (size_t)natoms * 3 * tsz));
+  BHIP_TRY(b, tmp.alloc((void**)&sz, (size_t)b->W * 2 * sizeof(double)));
+  BHIP_TRY(b, tmp.alloc((void**)&sz_ref, (size_t)b->W * 2 * sizeof(double)));
+  {
+    // Probe structures: the first landmark of every walker (as stored).
+    size_t a_off = 0;
+    std::vector<char> host((size_t)natoms * 3 * tsz);
+    for (int i = 0; i < b->W; ++i) {
+      std::vector<char> soa((size_t)3 * b->n_pad[i] * tsz);
+      BHIP_TRY(b, hipMemcpy(soa.data(), (const char*)b->A + a_off * tsz, soa.size(), hipMemcpyDeviceToHost));
+      for (int j = 0; j < b->n[i]; ++j)
+        for (int d = 0; d < 3; ++d)
+          std::memcpy(&host[((size_t)(b->atom_off[i] + j) * 3 + d) * tsz],
+                      &soa[((size_t)d * b->n_pad[i] + j) * tsz], tsz);
+      a_off += (size_t)b->L[i] * 3 * b->n_pad[i];
+    }
+    BHIP_TRY(b, hipMemcpy(x, host.data(), host.size(), hipMemcpyHostToDevice));
+  }
+  s = batch_run(b, x, sz_ref, ds_ref, nullptr, false);
+  if (s != PCV_OK) return s;
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  std::vector<double> hsz_ref(2 * b->W), hsz(2 * b->W);
+  BHIP_TRY(b, hipMemcpy(hsz_ref.data(), sz_ref, hsz_ref.size() * sizeof(double), hipMemcpyDeviceToHost));
+
+  EngineCfg menu[16];
+  int cnt = 0;
+  engine_configs(b->fp64, menu, &cnt);
+  const int maxn = *std::max_element(b->n.begin(), b->n.end());
+  hipEvent_t e0, e1;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  BHIP_TRY(b, hipEventCreate(&e1));
+  BatchPlan best = base;
+  float best_ms = 1e30f;
+  for (int k = 0; k < cnt; ++k) {
+    if (team_size(maxn, menu[k]) == 0) continue;
+    for (int per_team : {1, 2, 4, 8, 16})
+      for (int gm : {1, 2, 4})
+        for (int lpt : {1, 0}) {
+          BatchPlan c;
+          c.cfg = menu[k];
+          c.per_team = per_team;
+          c.grid_mult = gm;
+          c.lpt = lpt;
+          if (batch_apply(b, c) != PCV_OK) continue;
+          if (batch_run(b, x, sz, ds, nullptr, false) != PCV_OK) continue;
+          if (hipStreamSynchronize(b->stream) != hipSuccess) continue;
+          if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) continue;
+          bool ok = true;
+          for (int i = 0; i < 2 * b->W && ok; ++i) ok = std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i]));
+          if (!ok) continue;
+          (void)hipEventRecord(e0, b->stream);
+          for (int r = 0; r < 3; ++r) batch_run(b, x, sz, ds, nullptr, false);
+          (void)hipEventRecord(e1, b->stream);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
+        }
+  }
+  hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tmp.release();
+  cache_store(cache_path, key, best);
+  return batch_apply(b, best);
+}
+
+extern "C" pcv_status pcv_batch_eval(pcv_batch* b, const void* x_all, double* sz_all, void* ds_all, void* dz_all) {
+  if (!b) return PCV_EINVAL;
+  if (b->W == 0) return bfail(b, PCV_ESTATE, "no walkers loaded");
+  if (!x_all || !sz_all) return bfail(b, PCV_EINVAL, "x_all and sz_all are required");
+  if (!b->planned) {
+    pcv_status s = batch_apply(b, heuristic_plan(b));
+    if (s != PCV_OK) return s;
+  }
+  return batch_run(b, x_all, sz_all, ds_all, dz_all, true);
+}
+
+extern "C" const char* pcv_batch_plan_string(const pcv_batch* b) { return b ? b->plan_str.c_str() : ""; }
+extern "C" const char* pcv_batch_last_error(const pcv_batch* b) { return b ? b->err.c_str() : "null batch"; }

@@ -1,0 +1,59 @@
+// Host-side helpers shared by the single-structure and batched entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pcv_internal.h"
+
+namespace pcv {
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Owner of a set of device allocations released together.
+struct DevMem {
+  std::vector<void*> ptrs;
+  hipError_t alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+inline int num_cus(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
+  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
+// Lanes per landmark for a tiling, or 0 if it cannot hold n atoms.
+inline int team_size(int n, EngineCfg c) {
+  const int ts = std::max(16, next_pow2((n + c.apt - 1) / c.apt));
+  return ts > c.wg ? 0 : ts;
+}
+
+// Per-landmark cost model (lane-instructions) used to rank tilings: lanes per
+// landmark times (per-atom work + reduction + solve).
+inline double landmark_cost(int n, EngineCfg c, int ts) {
+  (void)n;
+  const double red = 9.0 * 3.0 * std::log2((double)std::min(ts, 64)) + (ts > 64 ? 60.0 : 0.0);
+  const double regs_penalty = (c.wg == 512) ? 1.15 : 1.0;
+  return ts * (c.apt * 30.0 + red + 320.0) * regs_penalty;
+}
+
+}  // namespace pcv

@@ -1,0 +1,123 @@
+// Internal descriptors shared by the kernels and the C ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcv {
+
+// Engine modes (the per-landmark step of the landmark streaming kernel).
+enum Mode : int {
+  MODE_EXACT = 0,       // Algorithm 1: solve every landmark's rotation (Eq. 3)
+  MODE_EXACT_SAVE = 1,  // Algorithm 2, reassignment: as EXACT and save R_{a_i y}
+  MODE_APPROX = 2,      // Algorithm 2, usual step: R_xy R_{a_i y} (Eq. 5)
+};
+
+// One (structure, landmark set) problem as the engine sees it.  Landmark
+// coordinates are SoA [L][3][n_pad] exactly as the caller gave them (not
+// re-rounded); their weighted centroids and Ga = sum_j w_j |a_j - c|^2 are
+// FP64.  xw = w_j * x_c,j in FP64 (SoA [3][n_pad]) feeds the correlation;
+// xg (SoA, coordinate type) is the structure the gradient phase measures
+// residuals against: the centred current structure for the exact modes and
+// the centred close structure y for the approximate mode.
+struct Problem {
+  const void* A;
+  const double* ca;     // [L][3]
+  const double* Ga;     // [L]
+  const double* q;      // [L]
+  const double* w;      // [n_pad], normalised, zero padded
+  const double* xw;     // [3][n_pad]
+  const void* xg;       // [3][n_pad]
+  const double* Gx;     // [1]
+  const double* Rxy;    // [9] (APPROX)
+  double* Rsave;        // [L][9]: read in APPROX, written in EXACT_SAVE
+  double* hdr;          // [n_slots][4]: m, Z, S, q0 per item
+  void* vec;            // [n_slots][6][n_pad] accumulators (U then V)
+  long long* fallbacks; // counter of Jacobi fallbacks (may be null)
+  int n, n_pad, L, ts, n_slots;
+  int out_off;          // atom offset of this problem in concatenated inputs/outputs
+  int out_idx;          // index of this problem's (s, z) pair
+  double lam;
+};
+
+struct Item {
+  int prob, i0, i1, slot;
+};
+
+// Output base pointers of one call (problem p writes at atom offset
+// out_off and (s, z) pair out_idx).
+struct Outs {
+  void* ds;     // [n][3] coordinate type, or null
+  void* dz;     // [n][3] or null
+  double* sz;   // [2] per problem
+  int* rec;     // close step: 1 reassigned, 0 approximate, -1 bad input (or null)
+};
+
+struct PrepArgs {
+  long long x_off;  // atom offset of this structure in the caller's AoS input
+  const double* w;  // [n_pad]
+  double* xw;       // [3][n_pad]
+  void* xc;         // [3][n_pad] coordinate type
+  double* Gx;       // [1]
+  int* status;      // [1]: sticky, set to 1 on non-finite input
+  long long* counters;  // optional: CNT_EVALS / CNT_EXPENSIVE for Algorithm 1
+  int n, n_pad, L;
+};
+
+// Device-resident close-structure state (Algorithm 2).
+struct CloseArgs {
+  double* y64;      // [3][n_pad] centred close structure
+  void* yT;         // [3][n_pad] same, coordinate type
+  double* Gy;       // [1]
+  double* Fxy;      // [10] quaternion matrix of y onto x
+  double* lamxy;    // [1]
+  double* qxy;      // [4]
+  double* Rxy;      // [9]
+  double* Dxy;      // [1]
+  int* flag;        // [1]: 1 reassign, 0 approximate, -1 skip (bad input)
+  int* init;        // [1]
+  int* force;       // [1]
+  long long* counters;  // [8]: frames, recomputes, expensive_msd, approx_frames
+  double eps;
+  int L;
+};
+
+enum Counter { CNT_FRAMES = 0, CNT_RECOMPUTES = 1, CNT_EXPENSIVE = 2, CNT_APPROX = 3,
+               CNT_EVALS = 4, CNT_FALLBACK = 5, CNT_N = 8 };
+
+struct EngineCfg {
+  int wg;    // threads per workgroup
+  int apt;   // atoms per thread
+};
+
+// ---- launchers (pcv_kernels.hip) -------------------------------------------
+// All return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_load_landmarks(const T* in, T* A, double* ca, double* Ga, const double* w,
+                                 int n, int n_pad, int L, hipStream_t st);
+template <typename T>
+hipError_t launch_pair_msd(const T* A, const double* ca, const double* Ga, const double* w,
+                           int n, int n_pad, int L, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, hipStream_t st);
+template <typename T>
+hipError_t launch_prep_close(PrepArgs pa, const void* x, CloseArgs ca, Outs outs, hipStream_t st);
+template <typename T>
+hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds_bytes, const Problem* probs,
+                         const Item* items, const int* wg_off, int mode, const int* flag,
+                         int run_if, double* dout, hipStream_t st);
+template <typename T>
+hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
+                              const int* flag, int run_if, hipStream_t st);
+template <typename T>
+hipError_t launch_merge_close(const Problem* prob, Outs outs, CloseArgs ca, double* gtmp,
+                              hipStream_t st);
+hipError_t launch_set_int(int* p, int v, hipStream_t st);
+hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);
+
+bool engine_supported(EngineCfg cfg, bool fp64);
+void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu
+hipError_t engine_init_attributes();
+size_t engine_lds_bytes(EngineCfg cfg, int ts, bool fp64);
+
+}  // namespace pcv

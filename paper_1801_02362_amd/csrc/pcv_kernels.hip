@@ -1,0 +1,896 @@
+// HIP kernels for path collective variables with a floating close structure
+// (arXiv:1801.02362), written for gfx950 (CDNA4, wave64).
+//
+// Data flow of one evaluation:
+//   prep        centre x with the weights (FP64), Gx, and for Algorithm 2 the
+//               exact superposition of the close structure y onto x, the
+//               reassignment decision D(x, y) > epsilon and the y <- x update.
+//   engine      stream every landmark once: FP64 correlation (Eq. 3 via the
+//               top quaternion eigenvalue), or the composed rotation of
+//               Eq. 5; fold exp(-lambda D_i) weights into per-atom
+//               accumulators of residuals with a running minimum (online
+//               log-sum-exp), so that the derivatives (Eq. 4 / Eq. 6) need no
+//               second read of the landmarks.
+//   merge       combine the per-item partials into s, z (Eq. 2) and the atom
+//               gradients; the close-structure merge also applies the
+//               derivative of R_xy.
+#include "pcv_internal.h"
+#include "pcv_math.h"
+
+namespace pcv {
+
+template <typename T> struct AccT { using type = float; };
+template <> struct AccT<double> { using type = double; };
+
+// ----------------------------------------------------------------- reductions
+template <int NV>
+__device__ __forceinline__ void wave_sum(double v[NV], int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  }
+}
+
+// Sum NV doubles over the whole block; every thread receives the result.
+// sh must hold (BS/64)*NV doubles.
+template <int NV, int BS>
+__device__ void block_sum(double v[NV], double* sh) {
+  wave_sum<NV>(v, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += sh[w * NV + k];
+    v[k] = s;
+  }
+}
+
+template <int BS>
+__device__ double block_min(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double m = sh[0];
+  for (int w = 1; w < BS / 64; ++w) m = fmin(m, sh[w]);
+  return m;
+}
+
+// Sum NV doubles over a team of ts lanes (ts a power of two, 16..WG).  Teams
+// of up to 64 lanes reduce inside the wave; wider teams finish through LDS
+// (red holds (WG/64)*NV doubles).  Must be reached by the whole workgroup
+// when ts > 64.
+template <int NV>
+__device__ __forceinline__ void team_sum(double v[NV], int ts, double* red) {
+  wave_sum<NV>(v, ts < 64 ? ts : 64);
+  if (ts > 64) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    }
+    __syncthreads();
+    const int wpt = ts >> 6;
+    const int w0 = (wave / wpt) * wpt;
+    double s = 0.0;
+    if (lane < NV)
+      for (int w = 0; w < wpt; ++w) s += red[(w0 + w) * NV + lane];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = __shfl(s, k, 64);
+  }
+}
+
+__device__ __forceinline__ double scale_to(double m_from, double m_to, double lam) {
+  return (m_from == INFINITY) ? 0.0 : exp(-lam * (m_from - m_to));
+}
+
+// ------------------------------------------------------------ landmark load
+// One workgroup per landmark: FP64 weighted centroid and Ga, and the AoS to
+// SoA copy (values unchanged, atom axis zero padded to n_pad).
+template <typename T>
+__global__ __launch_bounds__(256) void load_kernel(const T* __restrict__ in, T* __restrict__ A,
+                                                   double* __restrict__ ca, double* __restrict__ Ga,
+                                                   const double* __restrict__ w, int n, int n_pad) {
+  __shared__ double sh[4 * 3];
+  const int i = blockIdx.x;
+  const T* src = in + (size_t)i * n * 3;
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double wj = w[j];
+    c[0] = fma(wj, (double)src[3 * j + 0], c[0]);
+    c[1] = fma(wj, (double)src[3 * j + 1], c[1]);
+    c[2] = fma(wj, (double)src[3 * j + 2], c[2]);
+  }
+  block_sum<3, 256>(c, sh);
+  double g[1] = {0.0};
+  T* dst = A + (size_t)i * 3 * n_pad;
+  for (int j = threadIdx.x; j < n_pad; j += 256) {
+    if (j < n) {
+      const double wj = w[j];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T v = src[3 * j + d];
+        const double dv = (double)v - c[d];
+        g[0] = fma(wj * dv, dv, g[0]);
+        dst[(size_t)d * n_pad + j] = v;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dst[(size_t)d * n_pad + j] = T(0);
+    }
+  }
+  block_sum<1, 256>(g, sh);
+  if (threadIdx.x == 0) {
+    ca[3 * i + 0] = c[0];
+    ca[3 * i + 1] = c[1];
+    ca[3 * i + 2] = c[2];
+    Ga[i] = g[0];
+  }
+}
+
+// Exact distance between consecutive landmarks (for the sharpness lambda).
+template <typename T>
+__global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, const double* __restrict__ ca,
+                                                       const double* __restrict__ Ga,
+                                                       const double* __restrict__ w, int n, int n_pad,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[4 * 9];
+  const int i = blockIdx.x;
+  const T* a = A + (size_t)i * 3 * n_pad;
+  const T* x = A + (size_t)(i + 1) * 3 * n_pad;
+  double M[9] = {0.0};
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double wj = w[j];
+    double av[3], xv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      av[d] = (double)a[(size_t)d * n_pad + j] - ca[3 * i + d];
+      xv[d] = wj * ((double)x[(size_t)d * n_pad + j] - ca[3 * (i + 1) + d]);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) M[r * 3 + c] = fma(av[r], xv[c], M[r * 3 + c]);
+  }
+  block_sum<9, 256>(M, sh);
+  if (threadIdx.x == 0) {
+    double F[10], lam, q[4];
+    const double G = Ga[i] + Ga[i + 1];
+    top_eigenpair(M, 0.5 * G, F, lam, q);
+    out[i] = fmax(G - 2.0 * lam, 0.0);
+  }
+}
+
+// ------------------------------------------------------------ frame prep
+template <typename T, int BS>
+__device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& Gx, bool& finite,
+                             double c[3]) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < a.n; j += BS) {
+    const double wj = a.w[j];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double xv = (double)x[3 * j + d];
+      if (!isfinite(xv)) v[3] += 1.0;
+      v[d] = fma(wj, xv, v[d]);
+    }
+  }
+  block_sum<4, BS>(v, sh);
+  finite = (v[3] == 0.0);
+  c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
+  double g[1] = {0.0};
+  T* xc = (T*)a.xc;
+  for (int j = threadIdx.x; j < a.n_pad; j += BS) {
+    if (j < a.n) {
+      const double wj = a.w[j];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double xv = (double)x[3 * j + d] - c[d];
+        a.xw[(size_t)d * a.n_pad + j] = wj * xv;
+        xc[(size_t)d * a.n_pad + j] = (T)xv;
+        g[0] = fma(wj * xv, xv, g[0]);
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.xw[(size_t)d * a.n_pad + j] = 0.0;
+        xc[(size_t)d * a.n_pad + j] = T(0);
+      }
+    }
+  }
+  block_sum<1, BS>(g, sh);
+  Gx = g[0];
+}
+
+// One workgroup per problem (the batched path and Algorithm 1).
+template <typename T>
+__global__ __launch_bounds__(256) void prep_kernel(const PrepArgs* __restrict__ args,
+                                                   const void* __restrict__ x_base) {
+  __shared__ double sh[4 * 4];
+  const PrepArgs a = args[blockIdx.x];
+  const T* x = (const T*)x_base + 3 * a.x_off;
+  double Gx, c[3];
+  bool finite;
+  centre_frame<T, 256>(a, x, sh, Gx, finite, c);
+  if (threadIdx.x == 0) {
+    *a.Gx = Gx;
+    if (!finite) *a.status = 1;
+    if (a.counters) {
+      a.counters[CNT_EVALS] += 1;
+      a.counters[CNT_EXPENSIVE] += a.L;
+    }
+  }
+}
+
+// Algorithm 2, first part: centre x, superpose the close structure y onto x
+// exactly (D_xy, R_xy and the eigen-system kept for the derivative of R_xy),
+// decide the reassignment (strict D_xy > epsilon; always on the first frame or
+// when forced), move y <- x when reassigning, update the counters.
+template <typename T>
+__global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* __restrict__ x,
+                                                          CloseArgs cs, Outs nan_outs) {
+  constexpr int BS = 1024;
+  __shared__ double sh[16 * 9];
+  __shared__ int s_flag;
+  double Gx, c[3];
+  bool finite;
+  centre_frame<T, BS>(a, x, sh, Gx, finite, c);
+  const int init = *cs.init;
+  double Dxy = NAN;
+  if (init) {
+    double M[9] = {0.0};
+    for (int j = threadIdx.x; j < a.n; j += BS) {
+      double yv[3], xv[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        yv[d] = cs.y64[(size_t)d * a.n_pad + j];
+        xv[d] = a.xw[(size_t)d * a.n_pad + j];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = fma(yv[r], xv[cc], M[r * 3 + cc]);
+    }
+    block_sum<9, BS>(M, sh);
+    if (threadIdx.x == 0) {
+      double F[10], lam, q[4], R[9];
+      const double G = Gx + *cs.Gy;
+      top_eigenpair(M, 0.5 * G, F, lam, q);
+      Dxy = fmax(G - 2.0 * lam, 0.0);
+      quat_to_rot(q, R);
+      for (int k = 0; k < 10; ++k) cs.Fxy[k] = F[k];
+      for (int k = 0; k < 4; ++k) cs.qxy[k] = q[k];
+      for (int k = 0; k < 9; ++k) cs.Rxy[k] = R[k];
+      *cs.lamxy = lam;
+    }
+  }
+  if (threadIdx.x == 0) {
+    int flag;
+    if (!finite) flag = -1;
+    else if (!init || *cs.force || Dxy > cs.eps) flag = 1;
+    else flag = 0;
+    *cs.Dxy = Dxy;
+    *cs.flag = flag;
+    *cs.force = 0;
+    *a.Gx = Gx;
+    if (!finite) *a.status = 1;
+    if (nan_outs.rec) *nan_outs.rec = flag;
+    s_flag = flag;
+    if (flag >= 0) {
+      cs.counters[CNT_FRAMES] += 1;
+      if (init) cs.counters[CNT_EXPENSIVE] += 1;
+      if (flag == 1) {
+        cs.counters[CNT_RECOMPUTES] += 1;
+        cs.counters[CNT_EXPENSIVE] += cs.L;
+        *cs.Gy = Gx;
+        *cs.init = 1;
+      } else {
+        cs.counters[CNT_APPROX] += 1;
+      }
+    }
+  }
+  __syncthreads();
+  const int flag = s_flag;
+  if (flag == 1) {
+    T* yT = (T*)cs.yT;
+    for (int j = threadIdx.x; j < a.n_pad; j += BS) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double v = (j < a.n) ? (double)x[3 * j + d] - c[d] : 0.0;
+        cs.y64[(size_t)d * a.n_pad + j] = v;
+        yT[(size_t)d * a.n_pad + j] = (T)v;
+      }
+    }
+  } else if (flag == -1) {
+    T* ds = (T*)nan_outs.ds;
+    T* dz = (T*)nan_outs.dz;
+    for (int j = threadIdx.x; j < 3 * a.n; j += BS) {
+      if (ds) ds[j] = T(NAN);
+      if (dz) dz[j] = T(NAN);
+    }
+    if (threadIdx.x == 0) {
+      nan_outs.sz[0] = NAN;
+      nan_outs.sz[1] = NAN;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ engine
+// Landmark streaming engine.  A workgroup of WG threads splits into teams of
+// ts lanes (per problem); a team owns one landmark at a time and each lane
+// owns atoms lane + ts*k (k < APT), so every landmark is read exactly once,
+// coalesced, straight from HBM into registers (with the next landmark
+// prefetched).  Per landmark:
+//   * FP64 correlation M = sum_j a_j (w_j x_j)^T from FP32 (or FP64)
+//     coordinates; x is centred in FP64, so the landmark translation drops
+//     out without re-rounding the landmark;
+//   * EXACT: top eigenvalue of the quaternion matrix -> D = Gx + Ga - 2 lambda
+//     and R (Eq. 3); APPROX: D~ = Gx + Ga - 2 tr((R_xy R_{a_i y}) M) (Eq. 5);
+//   * online log-sum-exp: e_i = exp(-lambda (D_i - m)) against the running
+//     minimum m, accumulators rescaled when m drops;
+//   * per-atom accumulators U = sum e_i (q_i - q0) d_i, V = sum e_i d_i with
+//     residuals d_i = xg - R (a_i - c_i) (Eq. 4 / Eq. 6 explicit terms).
+// Each work item (a landmark range of one problem) ends with a tree merge of
+// the teams through LDS and writes one partial (m, Z, S, q0, U, V).
+template <typename T, int WG, int APT>
+__global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ probs,
+                                                    const Item* __restrict__ items,
+                                                    const int* __restrict__ wg_off, int mode,
+                                                    const int* __restrict__ flag, int run_if,
+                                                    double* __restrict__ dout) {
+  using acc = typename AccT<T>::type;
+  if (flag != nullptr && *flag != run_if) return;
+  extern __shared__ double smem[];
+  double* red = smem;                       // (WG/64)*9
+  double* mh = smem + (WG / 64) * 9;        // (WG/32)*3
+  acc* mv = (acc*)(mh + (WG / 32) * 3);     // (WG/2)*6*APT
+  const int tid = threadIdx.x;
+  const int it_end = wg_off[blockIdx.x + 1];
+  for (int it = wg_off[blockIdx.x]; it < it_end; ++it) {
+    const Item item = items[it];
+    const Problem& P = probs[item.prob];
+    const int ts = P.ts;
+    const int teams = WG / ts;
+    const int team = tid / ts;
+    const int lane = tid - team * ts;
+    const int n_pad = P.n_pad;
+    const T* __restrict__ A = (const T*)P.A;
+    const T* __restrict__ xgp = (const T*)P.xg;
+    const double lam = P.lam;
+    const double Gx = *P.Gx;
+
+    double xw[3][APT];
+    T xg[3][APT];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const int j = lane + ts * k;
+      const bool in = j < n_pad;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xw[d][k] = in ? P.xw[(size_t)d * n_pad + j] : 0.0;
+        xg[d][k] = in ? xgp[(size_t)d * n_pad + j] : T(0);
+      }
+    }
+    acc U[3][APT], V[3][APT];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < APT; ++k) { U[d][k] = acc(0); V[d][k] = acc(0); }
+    double m = INFINITY, Z = 0.0, S = 0.0;
+    const double q0 = P.q[item.i0];
+
+    T ac[3][APT], an[3][APT];
+    auto load = [&](T (&dst)[3][APT], int i) {
+      const T* src = A + (size_t)i * 3 * n_pad;
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        const int j = lane + ts * k;
+        const bool in = j < n_pad;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dst[d][k] = in ? src[(size_t)d * n_pad + j] : T(0);
+      }
+    };
+    const int len = item.i1 - item.i0;
+    const int iters = (len + teams - 1) / teams;
+    int i = item.i0 + team;
+    if (i < item.i1) load(ac, i);
+    else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < APT; ++k) ac[d][k] = T(0);
+    }
+    for (int r = 0; r < iters; ++r, i += teams) {
+      const bool active = i < item.i1;
+      if (i + teams < item.i1) load(an, i + teams);
+      // FP64 correlation partial over this lane's atoms.
+      double M[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) M[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        const double a0 = (double)ac[0][k], a1 = (double)ac[1][k], a2 = (double)ac[2][k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          M[0 * 3 + c] = fma(a0, xw[c][k], M[0 * 3 + c]);
+          M[1 * 3 + c] = fma(a1, xw[c][k], M[1 * 3 + c]);
+          M[2 * 3 + c] = fma(a2, xw[c][k], M[2 * 3 + c]);
+        }
+      }
+      team_sum<9>(M, ts, red);
+      if (active) {
+        const double Ga = P.Ga[i];
+        double D, R[9];
+        if (mode == MODE_APPROX) {
+          const double* Rs = P.Rsave + (size_t)i * 9;
+          const double* Rx = P.Rxy;
+          double Rt[9];
+#pragma unroll
+          for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+            for (int c0 = 0; c0 < 3; ++c0)
+              Rt[r0 * 3 + c0] = Rx[r0 * 3 + 0] * Rs[0 * 3 + c0] + Rx[r0 * 3 + 1] * Rs[1 * 3 + c0] +
+                                Rx[r0 * 3 + 2] * Rs[2 * 3 + c0];
+          double tr = 0.0;
+#pragma unroll
+          for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+            for (int c0 = 0; c0 < 3; ++c0) tr = fma(Rt[c0 * 3 + r0], M[r0 * 3 + c0], tr);
+          D = fmax(Gx + Ga - 2.0 * tr, 0.0);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) R[k] = Rs[k];
+        } else {
+          double F[10], lmax, qv[4];
+          const int fb = top_eigenpair(M, 0.5 * (Gx + Ga), F, lmax, qv);
+          if (fb && lane == 0 && P.fallbacks) atomicAdd((unsigned long long*)P.fallbacks, 1ull);
+          D = fmax(Gx + Ga - 2.0 * lmax, 0.0);
+          quat_to_rot(qv, R);
+          if (mode == MODE_EXACT_SAVE && lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) P.Rsave[(size_t)i * 9 + k] = R[k];
+          }
+        }
+        if (dout != nullptr && lane == 0) dout[i] = D;
+        if (D < m) {
+          const double sc = scale_to(m, D, lam);
+          const acc sca = (acc)sc;
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int k = 0; k < APT; ++k) { U[d][k] *= sca; V[d][k] *= sca; }
+          Z *= sc;
+          S *= sc;
+          m = D;
+        }
+        const double e = exp(-lam * (D - m));
+        const double qi = P.q[i];
+        Z += e;
+        S = fma(e, qi, S);
+        const acc al = (acc)(e * (qi - q0));
+        const acc be = (acc)e;
+        const double* cap = P.ca + (size_t)i * 3;
+        T ch[3], cl[3], Rg[9];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          ch[d] = (T)cap[d];
+          cl[d] = (T)(cap[d] - (double)ch[d]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rg[k] = (T)R[k];
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+          const T a0 = (ac[0][k] - ch[0]) - cl[0];
+          const T a1 = (ac[1][k] - ch[1]) - cl[1];
+          const T a2 = (ac[2][k] - ch[2]) - cl[2];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const T rr = fma(Rg[d * 3 + 0], a0, fma(Rg[d * 3 + 1], a1, Rg[d * 3 + 2] * a2));
+            const acc dd = (acc)(xg[d][k] - rr);
+            U[d][k] = fma(al, dd, U[d][k]);
+            V[d][k] = fma(be, dd, V[d][k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < APT; ++k) ac[d][k] = an[d][k];
+    }
+
+    // Tree merge of the teams of this workgroup.
+    for (int stride = teams >> 1; stride >= 1; stride >>= 1) {
+      __syncthreads();
+      if (team >= stride && team < 2 * stride) {
+        const int sl = team - stride;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int k = 0; k < APT; ++k) {
+            mv[((size_t)(sl * 6 + d) * APT + k) * ts + lane] = U[d][k];
+            mv[((size_t)(sl * 6 + 3 + d) * APT + k) * ts + lane] = V[d][k];
+          }
+        if (lane == 0) {
+          mh[sl * 3 + 0] = m;
+          mh[sl * 3 + 1] = Z;
+          mh[sl * 3 + 2] = S;
+        }
+      }
+      __syncthreads();
+      if (team < stride) {
+        const double m2 = mh[team * 3 + 0], Z2 = mh[team * 3 + 1], S2 = mh[team * 3 + 2];
+        const double mn = fmin(m, m2);
+        const double f1 = scale_to(m, mn, lam), f2 = scale_to(m2, mn, lam);
+        const acc f1a = (acc)f1, f2a = (acc)f2;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int k = 0; k < APT; ++k) {
+            U[d][k] = U[d][k] * f1a + mv[((size_t)(team * 6 + d) * APT + k) * ts + lane] * f2a;
+            V[d][k] = V[d][k] * f1a + mv[((size_t)(team * 6 + 3 + d) * APT + k) * ts + lane] * f2a;
+          }
+        Z = Z * f1 + Z2 * f2;
+        S = S * f1 + S2 * f2;
+        m = mn;
+      }
+    }
+    if (team == 0) {
+      acc* vec = (acc*)P.vec + (size_t)item.slot * 6 * n_pad;
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        const int j = lane + ts * k;
+        if (j < n_pad) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            vec[(size_t)d * n_pad + j] = U[d][k];
+            vec[(size_t)(3 + d) * n_pad + j] = V[d][k];
+          }
+        }
+      }
+      if (lane == 0) {
+        double* h = P.hdr + (size_t)item.slot * 4;
+        h[0] = m;
+        h[1] = Z;
+        h[2] = S;
+        h[3] = q0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ merges
+// Global (m, Z, S) of one problem from its item headers.
+template <int BS>
+__device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, double& S) {
+  double ml = INFINITY;
+  for (int g = threadIdx.x; g < P.n_slots; g += BS) ml = fmin(ml, P.hdr[(size_t)g * 4]);
+  m = block_min<BS>(ml, sh);
+  double v[2] = {0.0, 0.0};
+  for (int g = threadIdx.x; g < P.n_slots; g += BS) {
+    const double f = scale_to(P.hdr[(size_t)g * 4], m, P.lam);
+    v[0] = fma(f, P.hdr[(size_t)g * 4 + 1], v[0]);
+    v[1] = fma(f, P.hdr[(size_t)g * 4 + 2], v[1]);
+  }
+  block_sum<2, BS>(v, sh);
+  Z = v[0];
+  S = v[1];
+}
+
+// Algorithm 1 merge: s, z (Eq. 2) and ds/dx = -2 lambda w_k / Z * sum_g f_g
+// (U_g + (q0_g - s) V_g), dz/dx = 2 w_k / Z * sum_g f_g V_g.
+// Grid (atom blocks of 256, 3 coordinates, problems).
+template <typename T>
+__global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restrict__ probs, Outs o,
+                                                          const int* __restrict__ flag, int run_if) {
+  using acc = typename AccT<T>::type;
+  if (flag != nullptr && *flag != run_if) return;
+  __shared__ double sh[8];
+  __shared__ double fq[2][256];
+  const Problem& P = probs[blockIdx.z];
+  if ((int)blockIdx.x * 256 >= P.n) return;
+  double m, Z, S;
+  global_lse<256>(P, sh, m, Z, S);
+  const double s = S / Z;
+  const int c = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int n_pad = P.n_pad;
+  const acc* vec = (const acc*)P.vec;
+  double gs = 0.0, gz = 0.0;
+  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
+    __syncthreads();
+    const int g = g0 + threadIdx.x;
+    if (g < P.n_slots) {
+      fq[0][threadIdx.x] = scale_to(P.hdr[(size_t)g * 4], m, P.lam);
+      fq[1][threadIdx.x] = P.hdr[(size_t)g * 4 + 3] - s;
+    }
+    __syncthreads();
+    const int gn = min(256, P.n_slots - g0);
+    if (j < n_pad) {
+      const acc* base = vec + (size_t)g0 * 6 * n_pad;
+#pragma unroll 4
+      for (int t = 0; t < gn; ++t) {
+        const double u = (double)base[((size_t)t * 6 + c) * n_pad + j];
+        const double v = (double)base[((size_t)t * 6 + 3 + c) * n_pad + j];
+        const double f = fq[0][t];
+        gs = fma(f, fma(fq[1][t], v, u), gs);
+        gz = fma(f, v, gz);
+      }
+    }
+  }
+  if (j < P.n) {
+    const double wj = P.w[j];
+    const size_t at = 3 * ((size_t)P.out_off + j) + c;
+    if (o.ds) ((T*)o.ds)[at] = (T)(-2.0 * P.lam * wj * gs / Z);
+    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * wj * gz / Z);
+  }
+  if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
+    o.sz[2 * P.out_idx + 0] = s;
+    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+  }
+}
+
+// Algorithm 2 merge for the approximate step (single workgroup).  With
+// b_ik = R_{a_i y} a_ik and delta_ik = y_k - b_ik the partials give
+//   beta_k  = sum_i c_i b_ik = (lambda/Z) sum_g f_g (U_g + (q0_g - s) V_g),
+//   betaz_k = sum_i p_i b_ik = y_k - (1/Z) sum_g f_g V_g,
+// the explicit Eq. 6 terms ds/dx_k = -2 w_k R_xy beta_k and
+// dz/dx_k = 2 (w_k x_k - w_k R_xy betaz_k), and the rotation term: with
+// G = -2 sum_j w_j x_j beta_j^T (the symmetric part of Eq. 6's contraction
+// has no tangent component), Gamma = d(G:R_xy)/dM_xy and the contribution
+// w_k sum_a Gamma_ac y_k[a].
+template <typename T>
+__global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __restrict__ prob, Outs o,
+                                                           CloseArgs cs, double* __restrict__ gtmp) {
+  using acc = typename AccT<T>::type;
+  constexpr int BS = 1024;
+  if (*cs.flag != 0) return;
+  __shared__ double sh[16 * 18];
+  __shared__ double fq[2][2048];
+  __shared__ double part[8][128][2];
+  __shared__ double gam[18];
+  const Problem& P = *prob;
+  double m, Z, S;
+  global_lse<BS>(P, sh, m, Z, S);
+  const double s = S / Z;
+  const double lam = P.lam;
+  const int n = P.n, n_pad = P.n_pad;
+  const int ns = P.n_slots;  // <= 2048 (host guarantees)
+  for (int g = threadIdx.x; g < ns; g += BS) {
+    fq[0][g] = scale_to(P.hdr[(size_t)g * 4], m, lam);
+    fq[1][g] = P.hdr[(size_t)g * 4 + 3] - s;
+  }
+  __syncthreads();
+  // beta (rows 0..2) and betaz (rows 3..5) for every (coordinate, atom) column.
+  const acc* vec = (const acc*)P.vec;
+  const int ncol = 3 * n_pad;
+  const int cl = threadIdx.x & 127, grp = threadIdx.x >> 7;
+  for (int col0 = 0; col0 < ncol; col0 += 128) {
+    const int col = col0 + cl;
+    double su = 0.0, sv = 0.0;
+    if (col < ncol) {
+      const int c = col / n_pad, j = col - c * n_pad;
+      for (int g = grp; g < ns; g += 8) {
+        const acc* base = vec + (size_t)g * 6 * n_pad;
+        const double u = (double)base[(size_t)c * n_pad + j];
+        const double v = (double)base[(size_t)(3 + c) * n_pad + j];
+        su = fma(fq[0][g], fma(fq[1][g], v, u), su);
+        sv = fma(fq[0][g], v, sv);
+      }
+    }
+    part[grp][cl][0] = su;
+    part[grp][cl][1] = sv;
+    __syncthreads();
+    if (grp == 0 && col < ncol) {
+      double a = 0.0, b = 0.0;
+      for (int k = 0; k < 8; ++k) { a += part[k][cl][0]; b += part[k][cl][1]; }
+      gtmp[col] = lam / Z * a;                        // beta
+      gtmp[ncol + col] = cs.y64[col] - b / Z;         // betaz
+    }
+    __syncthreads();
+  }
+  // Explicit terms and the rotation-gradient contraction.
+  const double* Rx = cs.Rxy;
+  double G[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) G[k] = 0.0;
+  for (int j = threadIdx.x; j < n; j += BS) {
+    double be[3], bz[3], xw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      be[d] = gtmp[(size_t)d * n_pad + j];
+      bz[d] = gtmp[ncol + (size_t)d * n_pad + j];
+      xw[d] = P.xw[(size_t)d * n_pad + j];
+    }
+    const double wj = P.w[j];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double rb = Rx[d * 3 + 0] * be[0] + Rx[d * 3 + 1] * be[1] + Rx[d * 3 + 2] * be[2];
+      const double rz = Rx[d * 3 + 0] * bz[0] + Rx[d * 3 + 1] * bz[1] + Rx[d * 3 + 2] * bz[2];
+      gtmp[2 * ncol + (size_t)d * n_pad + j] = -2.0 * wj * rb;
+      gtmp[3 * ncol + (size_t)d * n_pad + j] = 2.0 * (xw[d] - wj * rz);
+    }
+#pragma unroll
+    for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+      for (int c0 = 0; c0 < 3; ++c0) {
+        G[r0 * 3 + c0] = fma(-2.0 * xw[r0], be[c0], G[r0 * 3 + c0]);
+        G[9 + r0 * 3 + c0] = fma(-2.0 * xw[r0], bz[c0], G[9 + r0 * 3 + c0]);
+      }
+  }
+  block_sum<18, BS>(G, sh);
+  if (threadIdx.x == 0) {
+    double Gs[9], Gz[9];
+    rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G, Gs);
+    rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G + 9, Gz);
+    for (int k = 0; k < 9; ++k) { gam[k] = Gs[k]; gam[9 + k] = Gz[k]; }
+  }
+  __syncthreads();
+  T* ds = (T*)o.ds;
+  T* dz = (T*)o.dz;
+  for (int j = threadIdx.x; j < n; j += BS) {
+    double y[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] = cs.y64[(size_t)d * n_pad + j];
+    const double wj = P.w[j];
+#pragma unroll
+    for (int c0 = 0; c0 < 3; ++c0) {
+      const double rs = wj * (gam[0 * 3 + c0] * y[0] + gam[1 * 3 + c0] * y[1] + gam[2 * 3 + c0] * y[2]);
+      const double rz = wj * (gam[9 + 0 * 3 + c0] * y[0] + gam[9 + 1 * 3 + c0] * y[1] + gam[9 + 2 * 3 + c0] * y[2]);
+      if (ds) ds[3 * j + c0] = (T)(gtmp[2 * ncol + (size_t)c0 * n_pad + j] + rs);
+      if (dz) dz[3 * j + c0] = (T)(gtmp[3 * ncol + (size_t)c0 * n_pad + j] + rz);
+    }
+  }
+  if (threadIdx.x == 0) {
+    o.sz[0] = s;
+    o.sz[1] = m - log(Z) / lam;
+  }
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+__global__ void count_kernel(long long* c, int which, long long add) { c[which] += add; }
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+hipError_t launch_load_landmarks(const T* in, T* A, double* ca, double* Ga, const double* w,
+                                 int n, int n_pad, int L, hipStream_t st) {
+  if (L <= 0) return hipSuccess;
+  hipLaunchKernelGGL((load_kernel<T>), dim3(L), dim3(256), 0, st, in, A, ca, Ga, w, n, n_pad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pair_msd(const T* A, const double* ca, const double* Ga, const double* w,
+                           int n, int n_pad, int L, double* out, hipStream_t st) {
+  if (L < 2) return hipSuccess;
+  hipLaunchKernelGGL((pair_msd_kernel<T>), dim3(L - 1), dim3(256), 0, st, A, ca, Ga, w, n, n_pad, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, hipStream_t st) {
+  hipLaunchKernelGGL((prep_kernel<T>), dim3(n_prob), dim3(256), 0, st, d_args, x_base);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prep_close(PrepArgs pa, const void* x, CloseArgs ca, Outs outs, hipStream_t st) {
+  hipLaunchKernelGGL((prep_close_kernel<T>), dim3(1), dim3(1024), 0, st, pa, (const T*)x, ca, outs);
+  return hipGetLastError();
+}
+
+size_t engine_lds_bytes(EngineCfg cfg, int ts, bool fp64) {
+  size_t b = (size_t)(cfg.wg / 64) * 9 * 8 + (size_t)(cfg.wg / 32) * 3 * 8;
+  if (cfg.wg / ts > 1) b += (size_t)(cfg.wg / 2) * 6 * cfg.apt * (fp64 ? 8 : 4);
+  return b;
+}
+
+#define PCV_ENGINE_CASES_F32(X) X(256, 1) X(256, 2) X(256, 4) X(256, 8) X(512, 8) X(512, 10) X(512, 16)
+#define PCV_ENGINE_CASES_F64(X) X(256, 1) X(256, 2) X(256, 4) X(256, 8)
+
+bool engine_supported(EngineCfg cfg, bool fp64) {
+#define PCV_CASE(W, P) if (cfg.wg == W && cfg.apt == P) return true;
+  if (fp64) { PCV_ENGINE_CASES_F64(PCV_CASE) }
+  else { PCV_ENGINE_CASES_F32(PCV_CASE) }
+#undef PCV_CASE
+  return false;
+}
+
+void engine_configs(bool fp64, EngineCfg* out, int* count) {
+  int k = 0;
+#define PCV_CASE(W, P) out[k++] = EngineCfg{W, P};
+  if (fp64) { PCV_ENGINE_CASES_F64(PCV_CASE) }
+  else { PCV_ENGINE_CASES_F32(PCV_CASE) }
+#undef PCV_CASE
+  *count = k;
+}
+
+hipError_t engine_init_attributes() {
+  hipError_t e = hipSuccess;
+#define PCV_CASE_T(T, W, P)                                                                   \
+  {                                                                                           \
+    hipError_t r = hipFuncSetAttribute((const void*)engine_kernel<T, W, P>,                  \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
+    if (r != hipSuccess) e = r;                                                               \
+  }
+#define PCV_CASE_F(W, P) PCV_CASE_T(float, W, P)
+#define PCV_CASE_D(W, P) PCV_CASE_T(double, W, P)
+  PCV_ENGINE_CASES_F32(PCV_CASE_F)
+  PCV_ENGINE_CASES_F64(PCV_CASE_D)
+#undef PCV_CASE_F
+#undef PCV_CASE_D
+#undef PCV_CASE_T
+  return e;
+}
+
+template <typename T, int WG, int APT>
+static hipError_t launch_engine_inst(int grid, size_t lds, const Problem* probs, const Item* items,
+                                     const int* wg_off, int mode, const int* flag, int run_if,
+                                     double* dout, hipStream_t st) {
+  hipLaunchKernelGGL((engine_kernel<T, WG, APT>), dim3(grid), dim3(WG), lds, st, probs, items,
+                     wg_off, mode, flag, run_if, dout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds, const Problem* probs, const Item* items,
+                         const int* wg_off, int mode, const int* flag, int run_if, double* dout,
+                         hipStream_t st) {
+#define PCV_CASE(W, P)                                                                        \
+  if (cfg.wg == W && cfg.apt == P)                                                            \
+    return launch_engine_inst<T, W, P>(grid, lds, probs, items, wg_off, mode, flag, run_if,  \
+                                       dout, st);
+  if constexpr (sizeof(T) == 8) { PCV_ENGINE_CASES_F64(PCV_CASE) }
+  else { PCV_ENGINE_CASES_F32(PCV_CASE) }
+#undef PCV_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
+                              const int* flag, int run_if, hipStream_t st) {
+  dim3 grid((max_n_pad + 255) / 256, 3, n_prob);
+  hipLaunchKernelGGL((merge_exact_kernel<T>), grid, dim3(256), 0, st, probs, outs, flag, run_if);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_merge_close(const Problem* prob, Outs outs, CloseArgs ca, double* gtmp,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((merge_close_kernel<T>), dim3(1), dim3(1024), 0, st, prob, outs, ca, gtmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) {
+  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1), 0, st, c, which, add);
+  return hipGetLastError();
+}
+
+#define PCV_INST(T)                                                                                  \
+  template hipError_t launch_load_landmarks<T>(const T*, T*, double*, double*, const double*, int, \
+                                               int, int, hipStream_t);                             \
+  template hipError_t launch_pair_msd<T>(const T*, const double*, const double*, const double*,    \
+                                         int, int, int, double*, hipStream_t);                     \
+  template hipError_t launch_prep<T>(const PrepArgs*, const void*, int, hipStream_t);              \
+  template hipError_t launch_prep_close<T>(PrepArgs, const void*, CloseArgs, Outs, hipStream_t);   \
+  template hipError_t launch_engine<T>(EngineCfg, int, size_t, const Problem*, const Item*,        \
+                                       const int*, int, const int*, int, double*, hipStream_t);    \
+  template hipError_t launch_merge_exact<T>(const Problem*, Outs, int, int, const int*, int,       \
+                                            hipStream_t);                                          \
+  template hipError_t launch_merge_close<T>(const Problem*, Outs, CloseArgs, double*, hipStream_t);
+PCV_INST(float)
+PCV_INST(double)
+
+}  // namespace pcv

@@ -1,0 +1,109 @@
+"""GPU parity of Algorithm 2 (floating close structure, Eq. 5 / Eq. 6) against
+the FP64 oracle state machine, frame by frame along a random walk."""
+import copy
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.close import CloseStructure
+from oracle.path import landmark_lambda, path_cv
+from oracle.msd import superpose
+
+pytestmark = pytest.mark.gpu
+
+
+def _walk(torch, lm, frames, lam, eps, *, dtype, tol, name, every=1):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import check_cv, dev, host, say
+    say(f"[close] {name}: L={lm.shape[0]} n={lm.shape[1]} frames={len(frames)} eps={eps}")
+    cv = pcv.PathCV(dev(lm, dtype), lam, eps=eps)
+    orc = CloseStructure(lm.astype(np.float64), lam, eps)
+    x = torch.empty(lm.shape[1], 3, dtype=dtype, device="cuda")
+    ambiguous = 0
+    n_re = 0
+    for t, f in enumerate(frames):
+        x.copy_(torch.as_tensor(f, dtype=dtype))
+        o = cv.eval_close(x, grad=True, msd=True)
+        rec = int(host(o["recomputed"])[0])
+        force = None
+        if orc.y is not None:
+            Dxy = float(superpose(f.astype(np.float64), orc.y).D)
+            if abs(Dxy - eps) < 1e-6 * abs(eps):
+                force = bool(rec)
+                ambiguous += 1
+        st = orc.step(f.astype(np.float64), force=force)
+        assert rec == int(st.recomputed), f"{name}[{t}]: decision gpu={rec} oracle={st.recomputed} D_xy={st.D_xy}"
+        n_re += rec
+        if t % every == 0 or rec:
+            check_cv(f"{name}[{t}]", tol, host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"]),
+                     st.result)
+    stats = cv.stats()
+    assert stats["recomputes"] == orc.recomputes == n_re
+    assert stats["frames"] == len(frames)
+    assert stats["expensive_msd"] == orc.expensive_msd
+    assert stats["approx_frames"] == len(frames) - n_re
+    say(f"[close] {name}: recomputes={n_re} ambiguous={ambiguous}")
+    cv.close()
+    return n_re
+
+
+def test_cfg1_walk_fp32():
+    import torch
+    from gpu_util import TOL32
+    sysm, frames = wl.cfg1(1500)
+    lam = landmark_lambda(sysm.landmarks)
+    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float32, tol=TOL32, name="cfg1",
+                 every=5)
+    assert n_re >= 2
+
+
+def test_cfg0_walk_fp64():
+    import torch
+    from gpu_util import TOL64
+    sysm, frames = wl.cfg0(1000)
+    lam = landmark_lambda(sysm.landmarks)
+    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float64, tol=TOL64, name="cfg0")
+    assert n_re >= 2
+
+
+def test_threshold_extremes():
+    import torch
+    from gpu_util import TOL32
+    sysm, frames = wl.cfg1(40)
+    lam = landmark_lambda(sysm.landmarks)
+    assert _walk(torch, sysm.landmarks, frames, lam, -1.0, dtype=torch.float32, tol=TOL32, name="eps<0") == 40
+    assert _walk(torch, sysm.landmarks, frames, lam, float("inf"), dtype=torch.float32, tol=TOL32,
+                 name="eps=inf") == 1
+
+
+def test_forced_reassignment_and_nonfinite_keep_state():
+    import paper_1801_02362_amd as pcv
+    import torch
+    from gpu_util import dev, host
+    sysm, frames = wl.cfg1(30)
+    lam = landmark_lambda(sysm.landmarks)
+    cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), lam, eps=0.01)
+    x = torch.empty(300, 3, dtype=torch.float32, device="cuda")
+    outs = []
+    for t in range(20):
+        if t == 10:
+            bad = torch.as_tensor(frames[t], device="cuda").clone()
+            bad[0, 0] = float("inf")
+            o = cv.eval_close(bad)
+            assert int(host(o["recomputed"])[0]) == -1
+            with pytest.raises(pcv.PcvError):
+                cv.check()
+        x.copy_(torch.as_tensor(frames[t]))
+        o = cv.eval_close(x)
+        outs.append(host(o["sz"]).copy())
+    st = cv.stats()
+    assert st["frames"] == 20 and st["recomputes"] == 1
+    cv.update_close(x)
+    assert cv.stats()["recomputes"] == 2
+    cv.force_reassign()
+    o = cv.eval_close(x)
+    assert int(host(o["recomputed"])[0]) == 1
+    ref = path_cv(frames[19].astype(np.float64), sysm.landmarks.astype(np.float64), lam, grad=False)
+    assert abs(host(o["sz"])[0] - ref.s) < 1e-6
+    cv.close()

@@ -1,0 +1,160 @@
+"""GPU parity of Algorithm 1 (exact MSD, s, z, gradients) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.path import landmark_lambda, path_cv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _run_exact(torch, lm, frames, lam, *, dtype, tol, name, q=None, w=None, plan=None, use_graph=True):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import check_cv, dev, host, say
+    say(f"[exact] {name}: L={lm.shape[0]} n={lm.shape[1]} frames={len(frames)} plan={plan}")
+    cv = pcv.PathCV(dev(lm, dtype), lam, q=q, w=w, use_graph=use_graph)
+    if plan is not None:
+        cv.set_plan(*plan)
+    x = torch.empty(lm.shape[1], 3, dtype=dtype, device="cuda")
+    for t, f in enumerate(frames):
+        x.copy_(torch.as_tensor(f, dtype=dtype))
+        o = cv.eval(x, grad=True, msd=True)
+        ref = path_cv(f.astype(np.float64), lm.astype(np.float64), lam, q=q, w=w)
+        check_cv(f"{name}[{t}]", tol, host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"]), ref)
+    cv.check()
+    st = cv.stats()
+    assert st["exact_evals"] == len(frames)
+    assert st["expensive_msd"] == len(frames) * lm.shape[0]
+    cv.close()
+
+
+def test_cfg0_fp64(torch):
+    from gpu_util import TOL64
+    sysm, frames = wl.cfg0(1000)
+    lam = landmark_lambda(sysm.landmarks)
+    _run_exact(torch, sysm.landmarks, frames[::50], lam, dtype=torch.float64, tol=TOL64, name="cfg0")
+
+
+def test_cfg1_fp32_near_and_far_frames(torch):
+    from gpu_util import TOL32
+    sysm, frames = wl.cfg1(100_000)
+    lam = landmark_lambda(sysm.landmarks)
+    pick = [0, 1, 100, 1000, 5000, 20000, 50000, 99999]
+    _run_exact(torch, sysm.landmarks, frames[pick], lam, dtype=torch.float32, tol=TOL32, name="cfg1")
+
+
+@pytest.mark.parametrize("n,L,seed", [(1, 3, 1), (2, 4, 2), (3, 1, 3), (5, 2, 4), (17, 37, 5), (63, 64, 6),
+                                      (64, 65, 7), (65, 129, 8), (257, 33, 9), (1000, 40, 10), (2049, 23, 11),
+                                      (5000, 19, 12), (8192, 5, 13)])
+def test_ragged_shapes_fp32(torch, n, L, seed):
+    from gpu_util import TOL32
+    s = wl.small_path(n, L, seed, dtype=np.float32)
+    rng = np.random.default_rng(seed)
+    frames = (s.waypoints[0] + rng.normal(0, 0.02, (2, n, 3))).astype(np.float32)
+    lam = landmark_lambda(s.landmarks) if L > 1 and n > 1 else 100.0
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name=f"ragged{n}x{L}")
+
+
+@pytest.mark.parametrize("n,L,seed", [(1, 2, 21), (22, 20, 22), (130, 70, 23), (2048, 9, 24)])
+def test_ragged_shapes_fp64(torch, n, L, seed):
+    from gpu_util import TOL64
+    s = wl.small_path(n, L, seed, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    frames = s.waypoints[0] + rng.normal(0, 0.02, (2, n, 3))
+    lam = landmark_lambda(s.landmarks) if n > 1 else 100.0
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float64, tol=TOL64, name=f"ragged64_{n}x{L}")
+
+
+def test_weights_and_properties(torch):
+    from gpu_util import TOL32
+    s = wl.small_path(150, 60, 31, dtype=np.float32)
+    rng = np.random.default_rng(32)
+    w = rng.uniform(0.1, 2.0, 150)
+    q = rng.normal(size=60)
+    frames = (s.waypoints[0] + rng.normal(0, 0.02, (2, 150, 3))).astype(np.float32)
+    lam = landmark_lambda(s.landmarks, w=w)
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name="weights", q=q, w=w)
+
+
+def _plans(n, wg_apt):
+    out = []
+    for wg, apt in wg_apt:
+        ts = 16
+        while ts * apt < n:
+            ts *= 2
+        while ts <= wg:
+            out.append((wg, apt, ts, 0))
+            ts *= 4
+    return out
+
+
+@pytest.mark.parametrize("plan", _plans(300, [(256, 1), (256, 2), (256, 4), (256, 8), (512, 8), (512, 10), (512, 16)]))
+def test_every_tiling_matches(torch, plan):
+    from gpu_util import TOL32
+    sysm, frames = wl.cfg1(3000)
+    lam = landmark_lambda(sysm.landmarks)
+    _run_exact(torch, sysm.landmarks, frames[[0, 2999]], lam, dtype=torch.float32, tol=TOL32,
+               name="tiling", plan=plan)
+
+
+def test_item_counts_and_graph_replay_are_bitwise_stable(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev, host
+    sysm, frames = wl.cfg1(50)
+    lam = landmark_lambda(sysm.landmarks)
+    res = []
+    for use_graph in (False, True):
+        cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), lam, use_graph=use_graph)
+        x = dev(frames[10], torch.float32)
+        for _ in range(3):
+            o = cv.eval(x)
+            res.append(np.concatenate([host(o["sz"]), host(o["ds_dx"]).ravel(), host(o["dz_dx"]).ravel()]))
+        cv.close()
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
+def test_path_lambda_matches_oracle(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev
+    sysm, _ = wl.cfg1(1)
+    cv = pcv.PathCV(dev(sysm.landmarks, torch.float32))
+    ref = landmark_lambda(sysm.landmarks)
+    assert abs(cv.lam - ref) <= 1e-9 * ref
+    cv.close()
+
+
+def test_nonfinite_input_is_reported(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev, host
+    sysm, frames = wl.cfg0(5)
+    cv = pcv.PathCV(dev(sysm.landmarks, torch.float64), 500.0)
+    x = dev(frames[1], torch.float64)
+    x[3, 1] = float("nan")
+    o = cv.eval(x)
+    assert np.isnan(host(o["sz"])).all()
+    with pytest.raises(pcv.PcvError) as ei:
+        cv.check()
+    assert ei.value.status == -4
+    cv.check()   # cleared
+    cv.close()
+
+
+def test_argument_errors(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev
+    sysm, _ = wl.cfg0(1)
+    with pytest.raises(pcv.PcvError) as ei:
+        pcv.PathCV(dev(np.zeros((2, 9000, 3)), torch.float32), 1.0)
+    assert ei.value.status == -3
+    with pytest.raises(pcv.PcvError) as ei:
+        pcv.PathCV(dev(sysm.landmarks, torch.float64), -1.0)
+    assert ei.value.status == -1
+    with pytest.raises(pcv.PcvError):
+        pcv.PathCV(dev(sysm.landmarks, torch.float64), 1.0, w=-np.ones(22))
