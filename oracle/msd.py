@@ -168,6 +168,11 @@ def rotation_adjoint(sp_evals, sp_evecs, G) -> np.ndarray:
     ``g_q = sum_ab G_ab dR_ab/dq`` this is ``mu . dF q`` where
     ``mu = sum_{m>0} v_m (v_m . g_q) / (lambda_0 - lambda_m)``, and since F
     is linear in M, ``Gamma_ab = mu^T F(E_ab) q``.  Batched over leading axes.
+
+    Reading at an exactly degenerate top eigenvalue (zero gap, e.g. a single
+    atom or collinear atoms): the sum is a pseudo-inverse, so a zero gap
+    contributes nothing (the paper is silent; the rotation is not unique
+    there and the distance does not depend on the choice).
     """
     lam = np.asarray(sp_evals)
     V = np.asarray(sp_evecs)
@@ -177,7 +182,10 @@ def rotation_adjoint(sp_evals, sp_evecs, G) -> np.ndarray:
     mu = 0.0
     for m in range(1, 4):
         v = V[..., :, m]
-        mu = mu + v * (np.einsum("...k,...k->...", v, g_q) / (lam[..., 0] - lam[..., m]))[..., None]
+        gap = lam[..., 0] - lam[..., m]
+        num = np.einsum("...k,...k->...", v, g_q)
+        coef = np.divide(num, gap, out=np.zeros(np.broadcast(num, gap).shape), where=gap > 0)
+        mu = mu + v * coef[..., None]
     Gamma = np.empty(G.shape)
     for a in range(3):
         for b in range(3):

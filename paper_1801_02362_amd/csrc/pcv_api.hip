@@ -48,13 +48,11 @@ struct pcv_handle {
   double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr;
   // frame
   double* xw = nullptr;
-  void* xc = nullptr;
   double* Gx = nullptr;
   int* status = nullptr;
   // close structure
   double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
          *Rxy = nullptr, *Dxy = nullptr, *Rsave = nullptr, *gtmp = nullptr, *scratch_sz = nullptr;
-  void* yT = nullptr;
   int *flag = nullptr, *init = nullptr, *force = nullptr;
   long long* counters = nullptr;
   // plan
@@ -181,7 +179,7 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prep, sizeof(PrepArgs)));
-  PrepArgs pa{0, h->w, h->xw, h->xc, h->Gx, h->status, h->counters, h->n, h->n_pad, h->L};
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->status, h->counters, h->n, h->n_pad, h->L};
   HIP_TRY(h, hipMemcpy(h->d_prep, &pa, sizeof(pa), hipMemcpyHostToDevice));
   std::vector<Item> items(p.n_items);
   std::vector<int> wgoff(p.grid + 1);
@@ -200,7 +198,6 @@ static pcv_status build_plan(pcv_handle* h) {
   base.q = h->q;
   base.w = h->w;
   base.xw = h->xw;
-  base.xg = h->xc;
   base.Gx = h->Gx;
   base.Rxy = h->Rxy;
   base.Rsave = h->Rsave;
@@ -216,7 +213,6 @@ static pcv_status build_plan(pcv_handle* h) {
   base.out_idx = 0;
   base.lam = h->lam;
   Problem probs[3] = {base, base, base};
-  probs[2].xg = h->yT;   // approximate step measures residuals against y
   HIP_TRY(h, hipMemcpy(h->d_prob, probs, sizeof(probs), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -286,11 +282,9 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->q, L * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->w, np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->xw, 3 * np * sizeof(double)));
-  HIP_TRY(h, m.alloc(&h->xc, 3 * np * tsz));
   HIP_TRY(h, m.alloc((void**)&h->Gx, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
   HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
-  HIP_TRY(h, m.alloc(&h->yT, 3 * np * tsz));
   HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Fxy, 10 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->lamxy, sizeof(double)));
@@ -314,7 +308,6 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, hipMemset(h->status, 0, sizeof(int)));
   HIP_TRY(h, hipMemset(h->counters, 0, CNT_N * sizeof(long long)));
   HIP_TRY(h, hipMemset(h->y64, 0, 3 * np * sizeof(double)));
-  HIP_TRY(h, hipMemset(h->yT, 0, 3 * np * tsz));
   HIP_TRY(h, hipMemset(h->Rsave, 0, L * 9 * sizeof(double)));
   hipError_t e = h->fp64 ? launch_load_landmarks<double>((const double*)coords, (double*)h->A, h->ca, h->Ga,
                                                          h->w, h->n, h->n_pad, h->L, h->stream)
@@ -391,8 +384,8 @@ static hipError_t enqueue_exact(pcv_handle* h, hipStream_t st, const void* x, do
 template <typename T>
 static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
                                 void* dz, double* msd, int* rec) {
-  PrepArgs pa{0, h->w, h->xw, h->xc, h->Gx, h->status, nullptr, h->n, h->n_pad, h->L};
-  CloseArgs ca{h->y64, h->yT, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->status, nullptr, h->n, h->n_pad, h->L};
+  CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
                h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
   Outs o{ds, dz, sz, rec};
   hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);

@@ -52,7 +52,6 @@ struct pcv_batch {
   DevMem mem, pmem;
   void* A = nullptr;
   double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr, *xw = nullptr, *Gx = nullptr;
-  void* xc = nullptr;
   int* status = nullptr;
   PrepArgs* d_prep = nullptr;
   // plan
@@ -179,7 +178,6 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
   BHIP_TRY(b, m.alloc((void**)&b->q, Ltot * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->w, Ptot * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->xw, 3 * Ptot * sizeof(double)));
-  BHIP_TRY(b, m.alloc(&b->xc, 3 * Ptot * tsz));
   BHIP_TRY(b, m.alloc((void**)&b->Gx, W * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->status, W * sizeof(int)));
   BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
@@ -189,9 +187,8 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
     for (int j = 0; j < b->n[i]; ++j) hw[b->pad_off[i] + j] = 1.0 / b->n[i];
     for (int k = 0; k < b->L[i]; ++k) hq[b->lm_off[i] + k] = k + 1;
     const size_t po = b->pad_off[i];
-    pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po,
-                     (char*)b->xc + 3 * po * tsz, b->Gx + i, b->status + i, nullptr,
-                     b->n[i], b->n_pad[i], b->L[i]};
+    pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po, b->Gx + i, b->status + i,
+                     nullptr, b->n[i], b->n_pad[i], b->L[i]};
   }
   BHIP_TRY(b, hipMemcpy(b->w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->q, hq.data(), hq.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -288,7 +285,6 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.q = b->q + lo;
     P.w = b->w + po;
     P.xw = b->xw + 3 * po;
-    P.xg = (const char*)b->xc + 3 * po * tsz;
     P.Gx = b->Gx + i;
     P.Rxy = nullptr;
     P.Rsave = nullptr;

@@ -16,10 +16,8 @@ enum Mode : int {
 // One (structure, landmark set) problem as the engine sees it.  Landmark
 // coordinates are SoA [L][3][n_pad] exactly as the caller gave them (not
 // re-rounded); their weighted centroids and Ga = sum_j w_j |a_j - c|^2 are
-// FP64.  xw = w_j * x_c,j in FP64 (SoA [3][n_pad]) feeds the correlation;
-// xg (SoA, coordinate type) is the structure the gradient phase measures
-// residuals against: the centred current structure for the exact modes and
-// the centred close structure y for the approximate mode.
+// FP64.  xw = w_j * x_c,j in FP64 (SoA [3][n_pad]) feeds the correlation
+// and, in the merges, the residuals x_c - R a.
 struct Problem {
   const void* A;
   const double* ca;     // [L][3]
@@ -27,7 +25,6 @@ struct Problem {
   const double* q;      // [L]
   const double* w;      // [n_pad], normalised, zero padded
   const double* xw;     // [3][n_pad]
-  const void* xg;       // [3][n_pad]
   const double* Gx;     // [1]
   const double* Rxy;    // [9] (APPROX)
   double* Rsave;        // [L][9]: read in APPROX, written in EXACT_SAVE
@@ -57,7 +54,6 @@ struct PrepArgs {
   long long x_off;  // atom offset of this structure in the caller's AoS input
   const double* w;  // [n_pad]
   double* xw;       // [3][n_pad]
-  void* xc;         // [3][n_pad] coordinate type
   double* Gx;       // [1]
   int* status;      // [1]: sticky, set to 1 on non-finite input
   long long* counters;  // optional: CNT_EVALS / CNT_EXPENSIVE for Algorithm 1
@@ -67,7 +63,6 @@ struct PrepArgs {
 // Device-resident close-structure state (Algorithm 2).
 struct CloseArgs {
   double* y64;      // [3][n_pad] centred close structure
-  void* yT;         // [3][n_pad] same, coordinate type
   double* Gy;       // [1]
   double* Fxy;      // [10] quaternion matrix of y onto x
   double* lamxy;    // [1]

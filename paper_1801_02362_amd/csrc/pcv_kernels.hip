@@ -187,7 +187,6 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
   double g[1] = {0.0};
-  T* xc = (T*)a.xc;
   for (int j = threadIdx.x; j < a.n_pad; j += BS) {
     if (j < a.n) {
       const double wj = a.w[j];
@@ -195,15 +194,11 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
       for (int d = 0; d < 3; ++d) {
         const double xv = (double)x[3 * j + d] - c[d];
         a.xw[(size_t)d * a.n_pad + j] = wj * xv;
-        xc[(size_t)d * a.n_pad + j] = (T)xv;
         g[0] = fma(wj * xv, xv, g[0]);
       }
     } else {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        a.xw[(size_t)d * a.n_pad + j] = 0.0;
-        xc[(size_t)d * a.n_pad + j] = T(0);
-      }
+      for (int d = 0; d < 3; ++d) a.xw[(size_t)d * a.n_pad + j] = 0.0;
     }
   }
   block_sum<1, BS>(g, sh);
@@ -300,14 +295,9 @@ __global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* _
   __syncthreads();
   const int flag = s_flag;
   if (flag == 1) {
-    T* yT = (T*)cs.yT;
     for (int j = threadIdx.x; j < a.n_pad; j += BS) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double v = (j < a.n) ? (double)x[3 * j + d] - c[d] : 0.0;
-        cs.y64[(size_t)d * a.n_pad + j] = v;
-        yT[(size_t)d * a.n_pad + j] = (T)v;
-      }
+      for (int d = 0; d < 3; ++d) cs.y64[(size_t)d * a.n_pad + j] = (j < a.n) ? (double)x[3 * j + d] - c[d] : 0.0;
     }
   } else if (flag == -1) {
     T* ds = (T*)nan_outs.ds;
@@ -329,15 +319,19 @@ __global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* _
 // owns atoms lane + ts*k (k < APT), so every landmark is read exactly once,
 // coalesced, straight from HBM into registers (with the next landmark
 // prefetched).  Per landmark:
-//   * FP64 correlation M = sum_j a_j (w_j x_j)^T from FP32 (or FP64)
-//     coordinates; x is centred in FP64, so the landmark translation drops
-//     out without re-rounding the landmark;
+//   * FP64 correlation M = sum_j a_j (w_j x_j)^T from the stored coordinates;
+//     x is centred in FP64, so the landmark translation drops out without
+//     re-rounding the landmark;
 //   * EXACT: top eigenvalue of the quaternion matrix -> D = Gx + Ga - 2 lambda
-//     and R (Eq. 3); APPROX: D~ = Gx + Ga - 2 tr((R_xy R_{a_i y}) M) (Eq. 5);
+//     and R (Eq. 3); APPROX: D~ = Gx + Ga - 2 tr((R_xy R_{a_i y}) M) (Eq. 5)
+//     with R = R_{a_i y};
 //   * online log-sum-exp: e_i = exp(-lambda (D_i - m)) against the running
 //     minimum m, accumulators rescaled when m drops;
-//   * per-atom accumulators U = sum e_i (q_i - q0) d_i, V = sum e_i d_i with
-//     residuals d_i = xg - R (a_i - c_i) (Eq. 4 / Eq. 6 explicit terms).
+//   * per-atom FP64 accumulators of the rotated, centred landmark
+//     r_i = R (a_i - c_i):  U = sum e_i (q_i - q0) r_i,  V = sum e_i r_i.
+//     The residuals x - r_i of Eq. 4 / Eq. 6 are formed in the merge, where
+//     the x part cancels exactly (sum_i p_i (q_i - s) = 0), so no FP32
+//     rounding of a large residual enters the gradient.
 // Each work item (a landmark range of one problem) ends with a tree merge of
 // the teams through LDS and writes one partial (m, Z, S, q0, U, V).
 template <typename T, int WG, int APT>
@@ -346,12 +340,12 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
                                                     const int* __restrict__ wg_off, int mode,
                                                     const int* __restrict__ flag, int run_if,
                                                     double* __restrict__ dout) {
-  using acc = typename AccT<T>::type;
+  using part_t = typename AccT<T>::type;
   if (flag != nullptr && *flag != run_if) return;
   extern __shared__ double smem[];
   double* red = smem;                       // (WG/64)*9
   double* mh = smem + (WG / 64) * 9;        // (WG/32)*3
-  acc* mv = (acc*)(mh + (WG / 32) * 3);     // (WG/2)*6*APT
+  double* mv = mh + (WG / 32) * 3;          // (WG/2)*6
   const int tid = threadIdx.x;
   const int it_end = wg_off[blockIdx.x + 1];
   for (int it = wg_off[blockIdx.x]; it < it_end; ++it) {
@@ -363,27 +357,23 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
     const int lane = tid - team * ts;
     const int n_pad = P.n_pad;
     const T* __restrict__ A = (const T*)P.A;
-    const T* __restrict__ xgp = (const T*)P.xg;
     const double lam = P.lam;
     const double Gx = *P.Gx;
 
     double xw[3][APT];
-    T xg[3][APT];
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       const int j = lane + ts * k;
       const bool in = j < n_pad;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xw[d][k] = in ? P.xw[(size_t)d * n_pad + j] : 0.0;
-        xg[d][k] = in ? xgp[(size_t)d * n_pad + j] : T(0);
-      }
+      for (int d = 0; d < 3; ++d) xw[d][k] = in ? P.xw[(size_t)d * n_pad + j] : 0.0;
     }
-    acc U[3][APT], V[3][APT];
+    double U[3][APT], V[3][APT];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int k = 0; k < APT; ++k) { U[d][k] = acc(0); V[d][k] = acc(0); }
+      for (int k = 0; k < APT; ++k) { U[d][k] = 0.0; V[d][k] = 0.0; }
+    double tU[3] = {0.0, 0.0, 0.0}, tV[3] = {0.0, 0.0, 0.0};   // sum e (q - q0) R c, sum e R c
     double m = INFINITY, Z = 0.0, S = 0.0;
     const double q0 = P.q[item.i0];
 
@@ -432,18 +422,16 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
         if (mode == MODE_APPROX) {
           const double* Rs = P.Rsave + (size_t)i * 9;
           const double* Rx = P.Rxy;
-          double Rt[9];
-#pragma unroll
-          for (int r0 = 0; r0 < 3; ++r0)
-#pragma unroll
-            for (int c0 = 0; c0 < 3; ++c0)
-              Rt[r0 * 3 + c0] = Rx[r0 * 3 + 0] * Rs[0 * 3 + c0] + Rx[r0 * 3 + 1] * Rs[1 * 3 + c0] +
-                                Rx[r0 * 3 + 2] * Rs[2 * 3 + c0];
           double tr = 0.0;
 #pragma unroll
           for (int r0 = 0; r0 < 3; ++r0)
 #pragma unroll
-            for (int c0 = 0; c0 < 3; ++c0) tr = fma(Rt[c0 * 3 + r0], M[r0 * 3 + c0], tr);
+            for (int c0 = 0; c0 < 3; ++c0) {
+              // (R_xy R_{a_i y})[c0][r0] contracted with M[r0][c0]
+              const double rt = Rx[c0 * 3 + 0] * Rs[0 * 3 + r0] + Rx[c0 * 3 + 1] * Rs[1 * 3 + r0] +
+                                Rx[c0 * 3 + 2] * Rs[2 * 3 + r0];
+              tr = fma(rt, M[r0 * 3 + c0], tr);
+            }
           D = fmax(Gx + Ga - 2.0 * tr, 0.0);
 #pragma unroll
           for (int k = 0; k < 9; ++k) R[k] = Rs[k];
@@ -461,11 +449,13 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
         if (dout != nullptr && lane == 0) dout[i] = D;
         if (D < m) {
           const double sc = scale_to(m, D, lam);
-          const acc sca = (acc)sc;
 #pragma unroll
-          for (int d = 0; d < 3; ++d)
+          for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int k = 0; k < APT; ++k) { U[d][k] *= sca; V[d][k] *= sca; }
+            for (int k = 0; k < APT; ++k) { U[d][k] *= sc; V[d][k] *= sc; }
+            tU[d] *= sc;
+            tV[d] *= sc;
+          }
           Z *= sc;
           S *= sc;
           m = D;
@@ -474,28 +464,22 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
         const double qi = P.q[i];
         Z += e;
         S = fma(e, qi, S);
-        const acc al = (acc)(e * (qi - q0));
-        const acc be = (acc)e;
+        const double al = e * (qi - q0);
         const double* cap = P.ca + (size_t)i * 3;
-        T ch[3], cl[3], Rg[9];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          ch[d] = (T)cap[d];
-          cl[d] = (T)(cap[d] - (double)ch[d]);
+          const double rc = R[d * 3 + 0] * cap[0] + R[d * 3 + 1] * cap[1] + R[d * 3 + 2] * cap[2];
+          tU[d] = fma(al, rc, tU[d]);
+          tV[d] = fma(e, rc, tV[d]);
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Rg[k] = (T)R[k];
-#pragma unroll
         for (int k = 0; k < APT; ++k) {
-          const T a0 = (ac[0][k] - ch[0]) - cl[0];
-          const T a1 = (ac[1][k] - ch[1]) - cl[1];
-          const T a2 = (ac[2][k] - ch[2]) - cl[2];
+          const double a0 = (double)ac[0][k], a1 = (double)ac[1][k], a2 = (double)ac[2][k];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const T rr = fma(Rg[d * 3 + 0], a0, fma(Rg[d * 3 + 1], a1, Rg[d * 3 + 2] * a2));
-            const acc dd = (acc)(xg[d][k] - rr);
-            U[d][k] = fma(al, dd, U[d][k]);
-            V[d][k] = fma(be, dd, V[d][k]);
+            const double rr = fma(R[d * 3 + 0], a0, fma(R[d * 3 + 1], a1, R[d * 3 + 2] * a2));
+            U[d][k] = fma(al, rr, U[d][k]);
+            V[d][k] = fma(e, rr, V[d][k]);
           }
         }
       }
@@ -504,53 +488,63 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
 #pragma unroll
         for (int k = 0; k < APT; ++k) ac[d][k] = an[d][k];
     }
+    // Centre the rotated landmarks: r = R a - R c.
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < APT; ++k) { U[d][k] -= tU[d]; V[d][k] -= tV[d]; }
 
-    // Tree merge of the teams of this workgroup.
+    // Tree merge of the teams of this workgroup, one atom slot k at a time.
     for (int stride = teams >> 1; stride >= 1; stride >>= 1) {
       __syncthreads();
-      if (team >= stride && team < 2 * stride) {
+      if (team >= stride && team < 2 * stride && lane == 0) {
         const int sl = team - stride;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int k = 0; k < APT; ++k) {
-            mv[((size_t)(sl * 6 + d) * APT + k) * ts + lane] = U[d][k];
-            mv[((size_t)(sl * 6 + 3 + d) * APT + k) * ts + lane] = V[d][k];
-          }
-        if (lane == 0) {
-          mh[sl * 3 + 0] = m;
-          mh[sl * 3 + 1] = Z;
-          mh[sl * 3 + 2] = S;
-        }
+        mh[sl * 3 + 0] = m;
+        mh[sl * 3 + 1] = Z;
+        mh[sl * 3 + 2] = S;
       }
       __syncthreads();
+      double f1 = 0.0, f2 = 0.0, mn = m;
       if (team < stride) {
-        const double m2 = mh[team * 3 + 0], Z2 = mh[team * 3 + 1], S2 = mh[team * 3 + 2];
-        const double mn = fmin(m, m2);
-        const double f1 = scale_to(m, mn, lam), f2 = scale_to(m2, mn, lam);
-        const acc f1a = (acc)f1, f2a = (acc)f2;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int k = 0; k < APT; ++k) {
-            U[d][k] = U[d][k] * f1a + mv[((size_t)(team * 6 + d) * APT + k) * ts + lane] * f2a;
-            V[d][k] = V[d][k] * f1a + mv[((size_t)(team * 6 + 3 + d) * APT + k) * ts + lane] * f2a;
-          }
-        Z = Z * f1 + Z2 * f2;
-        S = S * f1 + S2 * f2;
-        m = mn;
+        const double m2 = mh[team * 3 + 0];
+        mn = fmin(m, m2);
+        f1 = scale_to(m, mn, lam);
+        f2 = scale_to(m2, mn, lam);
+        Z = Z * f1 + mh[team * 3 + 1] * f2;
+        S = S * f1 + mh[team * 3 + 2] * f2;
       }
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        __syncthreads();
+        if (team >= stride && team < 2 * stride) {
+          const int sl = team - stride;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            mv[(size_t)(sl * 6 + d) * ts + lane] = U[d][k];
+            mv[(size_t)(sl * 6 + 3 + d) * ts + lane] = V[d][k];
+          }
+        }
+        __syncthreads();
+        if (team < stride) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            U[d][k] = U[d][k] * f1 + mv[(size_t)(team * 6 + d) * ts + lane] * f2;
+            V[d][k] = V[d][k] * f1 + mv[(size_t)(team * 6 + 3 + d) * ts + lane] * f2;
+          }
+        }
+      }
+      if (team < stride) m = mn;
     }
     if (team == 0) {
-      acc* vec = (acc*)P.vec + (size_t)item.slot * 6 * n_pad;
+      part_t* vec = (part_t*)P.vec + (size_t)item.slot * 6 * n_pad;
 #pragma unroll
       for (int k = 0; k < APT; ++k) {
         const int j = lane + ts * k;
         if (j < n_pad) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            vec[(size_t)d * n_pad + j] = U[d][k];
-            vec[(size_t)(3 + d) * n_pad + j] = V[d][k];
+            vec[(size_t)d * n_pad + j] = (part_t)U[d][k];
+            vec[(size_t)(3 + d) * n_pad + j] = (part_t)V[d][k];
           }
         }
       }
@@ -584,8 +578,10 @@ __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, d
   S = v[1];
 }
 
-// Algorithm 1 merge: s, z (Eq. 2) and ds/dx = -2 lambda w_k / Z * sum_g f_g
-// (U_g + (q0_g - s) V_g), dz/dx = 2 w_k / Z * sum_g f_g V_g.
+// Algorithm 1 merge: s, z (Eq. 2) and, with r_ik the rotated centred
+// landmarks, ds/dx_k = -2 lambda w_k sum_i p_i (q_i - s)(x_k - r_ik)
+//                    = (2 lambda w_k / Z) sum_g f_g (U_g + (q0_g - s) V_g),
+// dz/dx_k = 2 w_k sum_i p_i (x_k - r_ik) = 2 (w_k x_k - w_k / Z sum_g f_g V_g).
 // Grid (atom blocks of 256, 3 coordinates, problems).
 template <typename T>
 __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restrict__ probs, Outs o,
@@ -628,8 +624,8 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   if (j < P.n) {
     const double wj = P.w[j];
     const size_t at = 3 * ((size_t)P.out_off + j) + c;
-    if (o.ds) ((T*)o.ds)[at] = (T)(-2.0 * P.lam * wj * gs / Z);
-    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * wj * gz / Z);
+    if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * gs / Z);
+    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * gz / Z));
   }
   if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
     o.sz[2 * P.out_idx + 0] = s;
@@ -637,10 +633,10 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   }
 }
 
-// Algorithm 2 merge for the approximate step (single workgroup).  With
-// b_ik = R_{a_i y} a_ik and delta_ik = y_k - b_ik the partials give
-//   beta_k  = sum_i c_i b_ik = (lambda/Z) sum_g f_g (U_g + (q0_g - s) V_g),
-//   betaz_k = sum_i p_i b_ik = y_k - (1/Z) sum_g f_g V_g,
+// Algorithm 2 merge for the approximate step (single workgroup).  The
+// partials accumulate b_ik = R_{a_i y} (a_ik - c_i) (landmarks in y's frame):
+//   beta_k  = sum_i c_i b_ik = -(lambda/Z) sum_g f_g (U_g + (q0_g - s) V_g),
+//   betaz_k = sum_i p_i b_ik = (1/Z) sum_g f_g V_g,
 // the explicit Eq. 6 terms ds/dx_k = -2 w_k R_xy beta_k and
 // dz/dx_k = 2 (w_k x_k - w_k R_xy betaz_k), and the rotation term: with
 // G = -2 sum_j w_j x_j beta_j^T (the symmetric part of Eq. 6's contraction
@@ -649,7 +645,7 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
 template <typename T>
 __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __restrict__ prob, Outs o,
                                                            CloseArgs cs, double* __restrict__ gtmp) {
-  using acc = typename AccT<T>::type;
+  using acc = typename AccT<T>::type;  // partial storage type
   constexpr int BS = 1024;
   if (*cs.flag != 0) return;
   __shared__ double sh[16 * 18];
@@ -691,8 +687,8 @@ __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __rest
     if (grp == 0 && col < ncol) {
       double a = 0.0, b = 0.0;
       for (int k = 0; k < 8; ++k) { a += part[k][cl][0]; b += part[k][cl][1]; }
-      gtmp[col] = lam / Z * a;                        // beta
-      gtmp[ncol + col] = cs.y64[col] - b / Z;         // betaz
+      gtmp[col] = -lam / Z * a;                       // beta
+      gtmp[ncol + col] = b / Z;                       // betaz
     }
     __syncthreads();
   }
@@ -787,8 +783,9 @@ hipError_t launch_prep_close(PrepArgs pa, const void* x, CloseArgs ca, Outs outs
 }
 
 size_t engine_lds_bytes(EngineCfg cfg, int ts, bool fp64) {
+  (void)fp64;
   size_t b = (size_t)(cfg.wg / 64) * 9 * 8 + (size_t)(cfg.wg / 32) * 3 * 8;
-  if (cfg.wg / ts > 1) b += (size_t)(cfg.wg / 2) * 6 * cfg.apt * (fp64 ? 8 : 4);
+  if (cfg.wg / ts > 1) b += (size_t)(cfg.wg / 2) * 6 * 8;
   return b;
 }
 
