@@ -88,6 +88,9 @@ __device__ __forceinline__ void team_sum(double v[NV], int ts, double* red) {
   }
 }
 
+// max(v, 0) that keeps NaN (fmax would return 0 for a NaN distance).
+__device__ __forceinline__ double clamp0(double v) { return v < 0.0 ? 0.0 : v; }
+
 __device__ __forceinline__ double scale_to(double m_from, double m_to, double lam) {
   return (m_from == INFINITY) ? 0.0 : exp(-lam * (m_from - m_to));
 }
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
     double F[10], lam, q[4];
     const double G = Ga[i] + Ga[i + 1];
     top_eigenpair(M, 0.5 * G, F, lam, q);
-    out[i] = fmax(G - 2.0 * lam, 0.0);
+    out[i] = clamp0(G - 2.0 * lam);
   }
 }
 
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* _
       double F[10], lam, q[4], R[9];
       const double G = Gx + *cs.Gy;
       top_eigenpair(M, 0.5 * G, F, lam, q);
-      Dxy = fmax(G - 2.0 * lam, 0.0);
+      Dxy = clamp0(G - 2.0 * lam);
       quat_to_rot(q, R);
       for (int k = 0; k < 10; ++k) cs.Fxy[k] = F[k];
       for (int k = 0; k < 4; ++k) cs.qxy[k] = q[k];
@@ -432,14 +435,14 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
                                 Rx[c0 * 3 + 2] * Rs[2 * 3 + r0];
               tr = fma(rt, M[r0 * 3 + c0], tr);
             }
-          D = fmax(Gx + Ga - 2.0 * tr, 0.0);
+          D = clamp0(Gx + Ga - 2.0 * tr);
 #pragma unroll
           for (int k = 0; k < 9; ++k) R[k] = Rs[k];
         } else {
           double F[10], lmax, qv[4];
           const int fb = top_eigenpair(M, 0.5 * (Gx + Ga), F, lmax, qv);
           if (fb && lane == 0 && P.fallbacks) atomicAdd((unsigned long long*)P.fallbacks, 1ull);
-          D = fmax(Gx + Ga - 2.0 * lmax, 0.0);
+          D = clamp0(Gx + Ga - 2.0 * lmax);
           quat_to_rot(qv, R);
           if (mode == MODE_EXACT_SAVE && lane == 0) {
 #pragma unroll
