@@ -155,13 +155,35 @@ pcv_status pcv_reset_stats(pcv_handle* h);
  * input since the last check), clearing it. */
 pcv_status pcv_check(pcv_handle* h);
 
-/* Engine tiling chosen for the loaded landmarks: threads per workgroup,
- * atoms per thread, lanes per landmark, workgroups, work items. */
-pcv_status pcv_get_plan(pcv_handle* h, int* wg, int* apt, int* team, int* grid, int* items);
+/*
+ * Tiling of the landmark streaming kernel.  Two engines exist:
+ *   engine 1  teams of `team` lanes, one landmark per team at a time, `apt`
+ *             atoms per lane, `wg` threads per workgroup; every lane of a team
+ *             takes part in the per-landmark eigen-solve.  Any n up to
+ *             pcv_max_atoms().
+ *   engine 2  split roles in a 512-thread workgroup: one solver wave, three
+ *             correlation waves reading batches of `batch` landmarks from LDS
+ *             (async copies), four gradient waves owning the atoms; `apt` and
+ *             `aptg` are the compiled atoms per correlation / gradient lane,
+ *             `team` the lanes per landmark in the correlation stage
+ *             (16, 32, 64 or 192).  Needs the landmark batch to fit in LDS.
+ * `grid` is an output; `items` <= 0 selects the default number of work items.
+ */
+typedef struct pcv_plan {
+  int engine;
+  int wg;
+  int apt;
+  int team;
+  int aptg;
+  int batch;
+  int grid;
+  int items;
+} pcv_plan;
 
-/* Override the tiling (must cover n: team * apt >= n, team a power of two
- * dividing wg, 16 <= team); items <= 0 picks the default count. */
-pcv_status pcv_set_plan(pcv_handle* h, int wg, int apt, int team, int items);
+pcv_status pcv_get_plan(pcv_handle* h, pcv_plan* out);
+/* Validate and apply a plan (synchronises the stream; PCV_EUNSUPPORTED if the
+ * tiling is not compiled in or cannot hold the loaded structure). */
+pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* plan);
 
 /*
  * Kernel timing for roofline measurements.  While enabled, calls run eagerly

@@ -34,6 +34,10 @@ class _Options(ctypes.Structure):
                 ("eps", ctypes.c_double), ("use_graph", ctypes.c_int)]
 
 
+class _Plan(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int) for k in ("engine", "wg", "apt", "team", "aptg", "batch", "grid", "items")]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("frames", "recomputes", "expensive_msd", "approx_frames", "exact_evals", "eigen_fallbacks")]
@@ -71,8 +75,8 @@ def load_library():
         "pcv_get_stats": (st, [vp, ctypes.POINTER(_Stats)]),
         "pcv_reset_stats": (st, [vp]),
         "pcv_check": (st, [vp]),
-        "pcv_get_plan": (st, [vp] + [ctypes.POINTER(i)] * 5),
-        "pcv_set_plan": (st, [vp, i, i, i, i]),
+        "pcv_get_plan": (st, [vp, ctypes.POINTER(_Plan)]),
+        "pcv_set_plan": (st, [vp, ctypes.POINTER(_Plan)]),
         "pcv_set_kernel_timing": (st, [vp, i]),
         "pcv_get_kernel_timing": (st, [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)]),
         "pcv_status_string": (ctypes.c_char_p, [st]),
@@ -231,12 +235,15 @@ class PathCV:
 
     @property
     def plan(self) -> dict:
-        v = [ctypes.c_int() for _ in range(5)]
-        self._check(self._L.pcv_get_plan(self._h, *[ctypes.byref(a) for a in v]))
-        return dict(zip(("wg", "apt", "team", "grid", "items"), (a.value for a in v)))
+        """Tiling of the landmark streaming kernel (see ``pcv_plan`` in pcv.h)."""
+        p = _Plan()
+        self._check(self._L.pcv_get_plan(self._h, ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in _Plan._fields_}
 
-    def set_plan(self, wg: int, apt: int, team: int, items: int = 0):
-        self._check(self._L.pcv_set_plan(self._h, wg, apt, team, items))
+    def set_plan(self, engine: int = 1, wg: int = 256, apt: int = 1, team: int = 16, aptg: int = 0,
+                 batch: int = 1, items: int = 0):
+        p = _Plan(engine, wg, apt, team, aptg, batch, 0, items)
+        self._check(self._L.pcv_set_plan(self._h, ctypes.byref(p)))
 
     def set_kernel_timing(self, enable: bool):
         """Record HIP events around every landmark-kernel launch (calls run

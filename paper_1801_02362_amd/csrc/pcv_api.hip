@@ -23,8 +23,11 @@ constexpr int kMaxAtomsF64 = 256 * 8;
 constexpr int kMaxCloseSlots = 2048;
 
 struct Plan {
-  EngineCfg cfg{256, 1};
+  int engine = 1;
+  EngineCfg cfg{256, 1};    // engine 1
   int ts = 16;
+  Engine2Cfg c2{0, 0};      // engine 2
+  int g = 0, B = 1, lbuf = 0;
   int grid = 0;
   int n_items = 0;
   size_t lds = 0;
@@ -49,6 +52,8 @@ struct pcv_handle {
   // frame
   double* xw = nullptr;
   double* Gx = nullptr;
+  double* Gx32 = nullptr;
+  double* xres = nullptr;
   int* status = nullptr;
   // close structure
   double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
@@ -136,7 +141,7 @@ extern "C" pcv_status pcv_create(pcv_handle** out, const pcv_options* opt) {
     delete h;
     return PCV_EHIP;
   }
-  if (engine_init_attributes() != hipSuccess) {
+  if (engine_init_attributes() != hipSuccess || engine2_init_attributes() != hipSuccess) {
     (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return PCV_EHIP;
@@ -162,16 +167,22 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
 static pcv_status build_plan(pcv_handle* h) {
   Plan& p = h->plan;
   const size_t acc = h->fp64 ? 8 : 4;
-  const int teams = p.cfg.wg / p.ts;
+  // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
+  const int unit = (p.engine == 2) ? p.B : p.cfg.wg / p.ts;
+  const int units = (h->L + unit - 1) / unit;
   if (!h->user_plan || p.n_items <= 0) {
-    int want = (h->L + teams - 1) / teams;
-    const int cap = (p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
-    p.n_items = std::max(1, std::min(want, cap));
+    const int cap = (p.engine == 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
+    p.n_items = std::max(1, std::min(units, cap));
   }
-  p.n_items = std::min(p.n_items, h->L);
+  p.n_items = std::min(p.n_items, units);
   p.n_items = std::min(p.n_items, kMaxCloseSlots);
   p.grid = p.n_items;
-  p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
+  if (p.engine == 2) {
+    p.lbuf = p.B * 3 * h->n_pad * (h->fp64 ? 8 : 4);
+    p.lds = engine2_lds_bytes((size_t)p.lbuf, p.B);
+  } else {
+    p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
+  }
   h->pmem.release();
   HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, (size_t)p.n_items * 4 * sizeof(double)));
   HIP_TRY(h, h->pmem.alloc(&h->vec, (size_t)p.n_items * 6 * h->n_pad * acc));
@@ -179,14 +190,16 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prep, sizeof(PrepArgs)));
-  PrepArgs pa{0, h->w, h->xw, h->Gx, h->status, h->counters, h->n, h->n_pad, h->L};
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, h->counters, h->n, h->n_pad, h->L};
   HIP_TRY(h, hipMemcpy(h->d_prep, &pa, sizeof(pa), hipMemcpyHostToDevice));
   std::vector<Item> items(p.n_items);
   std::vector<int> wgoff(p.grid + 1);
   for (int k = 0; k < p.n_items; ++k) {
     items[k].prob = 0;
-    items[k].i0 = (int)((long long)k * h->L / p.n_items);
-    items[k].i1 = (int)((long long)(k + 1) * h->L / p.n_items);
+    const int u0 = (int)((long long)k * units / p.n_items);
+    const int u1 = (int)((long long)(k + 1) * units / p.n_items);
+    items[k].i0 = std::min(h->L, u0 * unit);
+    items[k].i1 = std::min(h->L, u1 * unit);
     items[k].slot = k;
     wgoff[k] = k;
   }
@@ -204,6 +217,10 @@ static pcv_status build_plan(pcv_handle* h) {
   base.hdr = h->hdr;
   base.vec = h->vec;
   base.fallbacks = h->counters + CNT_FALLBACK;
+  base.Gx32 = h->Gx32;
+  base.xres = h->xres;
+  base.bsz = p.B;
+  base.cg = p.g;
   base.n = h->n;
   base.n_pad = h->n_pad;
   base.L = h->L;
@@ -221,7 +238,32 @@ static pcv_status build_plan(pcv_handle* h) {
   return PCV_OK;
 }
 
+static bool default_plan2(pcv_handle* h) {
+  const int B = e2_batch(h->n_pad, h->fp64);
+  if (B == 0) return false;
+  int ac[16], ag[16], cnt = 0;
+  engine2_configs(h->fp64, ac, ag, &cnt);
+  for (int k = 0; k < cnt; ++k) {
+    const Engine2Cfg c{ac[k], ag[k]};
+    if (!e2_fits(h->n_pad, c)) continue;
+    const int g = e2_group(h->n_pad, c.aptc, B);
+    if (g == 0) continue;
+    h->plan.engine = 2;
+    h->plan.c2 = c;
+    h->plan.g = g;
+    h->plan.B = B;
+    h->plan.cfg = EngineCfg{512, c.aptc};
+    h->plan.ts = g;
+    return true;
+  }
+  return false;
+}
+
 static void default_plan(pcv_handle* h) {
+  h->plan.n_items = 0;
+  h->user_plan = false;
+  if (default_plan2(h)) return;
+  h->plan.engine = 1;
   EngineCfg menu[16];
   int cnt = 0;
   engine_configs(h->fp64, menu, &cnt);
@@ -283,6 +325,8 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->w, np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->xw, 3 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gx, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Gx32, sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->xres, 3 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
   HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
@@ -361,8 +405,12 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, st);
   }
-  hipError_t e = launch_engine<T>(h->plan.cfg, h->plan.grid, h->plan.lds, h->d_prob + mode, h->d_items,
-                                  h->d_wgoff, mode, flag, run_if, msd, st);
+  const Plan& p = h->plan;
+  hipError_t e = (p.engine == 2)
+      ? launch_engine2<T>(p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
+                          h->d_wgoff, mode, flag, run_if, msd, st)
+      : launch_engine<T>(p.cfg, p.grid, p.lds, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if,
+                         msd, st);
   if (h->timing) {
     (void)hipEventRecord(e1, st);
     h->ev_pending.emplace_back(e0, e1);
@@ -384,7 +432,7 @@ static hipError_t enqueue_exact(pcv_handle* h, hipStream_t st, const void* x, do
 template <typename T>
 static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
                                 void* dz, double* msd, int* rec) {
-  PrepArgs pa{0, h->w, h->xw, h->Gx, h->status, nullptr, h->n, h->n_pad, h->L};
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, nullptr, h->n, h->n_pad, h->L};
   CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
                h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
   Outs o{ds, dz, sz, rec};
@@ -514,28 +562,56 @@ extern "C" pcv_status pcv_check(pcv_handle* h) {
   return PCV_OK;
 }
 
-extern "C" pcv_status pcv_get_plan(pcv_handle* h, int* wg, int* apt, int* team, int* grid, int* items) {
-  if (!h) return PCV_EINVAL;
+extern "C" pcv_status pcv_get_plan(pcv_handle* h, pcv_plan* out) {
+  if (!h || !out) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
-  if (wg) *wg = h->plan.cfg.wg;
-  if (apt) *apt = h->plan.cfg.apt;
-  if (team) *team = h->plan.ts;
-  if (grid) *grid = h->plan.grid;
-  if (items) *items = h->plan.n_items;
+  const Plan& p = h->plan;
+  out->engine = p.engine;
+  out->wg = p.engine == 2 ? 512 : p.cfg.wg;
+  out->apt = p.engine == 2 ? p.c2.aptc : p.cfg.apt;
+  out->team = p.engine == 2 ? p.g : p.ts;
+  out->aptg = p.engine == 2 ? p.c2.aptg : 0;
+  out->batch = p.engine == 2 ? p.B : 0;
+  out->grid = p.grid;
+  out->items = p.n_items;
   return PCV_OK;
 }
 
-extern "C" pcv_status pcv_set_plan(pcv_handle* h, int wg, int apt, int team, int items) {
-  if (!h) return PCV_EINVAL;
+extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
+  if (!h || !q) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
-  EngineCfg c{wg, apt};
-  if (!engine_supported(c, h->fp64)) return fail(h, PCV_EUNSUPPORTED, "tiling not compiled in");
-  if (team < 16 || team > wg || (team & (team - 1)) || (long long)team * apt < h->n)
-    return fail(h, PCV_EINVAL, "team must be a power of two in [16, wg] with team*apt >= n");
+  Plan p = h->plan;
+  if (q->engine == 1) {
+    const EngineCfg c{q->wg, q->apt};
+    if (!engine_supported(c, h->fp64)) return fail(h, PCV_EUNSUPPORTED, "engine 1 tiling not compiled in");
+    if (q->team < 16 || q->team > q->wg || (q->team & (q->team - 1)) || (long long)q->team * q->apt < h->n)
+      return fail(h, PCV_EINVAL, "team must be a power of two in [16, wg] with team*apt >= n");
+    p.engine = 1;
+    p.cfg = c;
+    p.ts = q->team;
+  } else if (q->engine == 2) {
+    int ac[16], ag[16], cnt = 0;
+    engine2_configs(h->fp64, ac, ag, &cnt);
+    bool found = false;
+    for (int k = 0; k < cnt; ++k) found |= (ac[k] == q->apt && ag[k] == q->aptg);
+    if (!found) return fail(h, PCV_EUNSUPPORTED, "engine 2 tiling not compiled in");
+    const Engine2Cfg c{q->apt, q->aptg};
+    const int g = q->team;
+    if (!(g == 16 || g == 32 || g == 64 || g == 192) || (h->n_pad + g - 1) / g > c.aptc || !e2_fits(h->n_pad, c))
+      return fail(h, PCV_EINVAL, "engine 2 tiling cannot hold the structure");
+    if (!e2_lds_ok(h->n_pad, q->batch, h->fp64)) return fail(h, PCV_EINVAL, "batch does not fit in LDS");
+    p.engine = 2;
+    p.c2 = c;
+    p.g = g;
+    p.B = q->batch;
+    p.cfg = EngineCfg{512, c.aptc};
+    p.ts = g;
+  } else {
+    return fail(h, PCV_EINVAL, "engine must be 1 or 2");
+  }
+  p.n_items = q->items;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  h->plan.cfg = c;
-  h->plan.ts = team;
-  h->plan.n_items = items;
+  h->plan = p;
   h->user_plan = true;
   return build_plan(h);
 }

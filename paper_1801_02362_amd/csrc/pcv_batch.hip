@@ -25,14 +25,19 @@ using namespace pcv;
 namespace {
 
 struct BatchPlan {
-  EngineCfg cfg{256, 8};
-  int per_team = 4;     // landmarks per team per work item
-  int grid_mult = 2;    // workgroups = grid_mult * CUs
-  int lpt = 1;          // 1: longest-processing-time schedule, 0: round robin
+  int engine = 2;
+  EngineCfg cfg{256, 8};   // engine 1 tiling
+  Engine2Cfg c2{16, 8};    // engine 2 tiling
+  int per_team = 4;        // engine 1: landmarks per team per item; engine 2: batches per item
+  int grid_mult = 2;       // workgroups = grid_mult * CUs
+  int lpt = 1;             // 1: longest-processing-time schedule, 0: round robin
   std::string str() const {
     std::ostringstream o;
-    o << "wg=" << cfg.wg << " apt=" << cfg.apt << " per_team=" << per_team << " grid_mult=" << grid_mult
-      << " schedule=" << (lpt ? "lpt" : "rr");
+    if (engine == 2)
+      o << "engine=2 aptc=" << c2.aptc << " aptg=" << c2.aptg;
+    else
+      o << "engine=1 wg=" << cfg.wg << " apt=" << cfg.apt;
+    o << " per_item=" << per_team << " grid_mult=" << grid_mult << " schedule=" << (lpt ? "lpt" : "rr");
     return o.str();
   }
 };
@@ -51,7 +56,8 @@ struct pcv_batch {
   long long total_pairs = 0;
   DevMem mem, pmem;
   void* A = nullptr;
-  double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr, *xw = nullptr, *Gx = nullptr;
+  double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr, *xw = nullptr, *Gx = nullptr,
+         *Gx32 = nullptr, *xres = nullptr;
   int* status = nullptr;
   PrepArgs* d_prep = nullptr;
   // plan
@@ -59,6 +65,7 @@ struct pcv_batch {
   bool planned = false;
   int grid = 0, n_items = 0;
   size_t lds = 0;
+  int lbuf = 0, bmax = 1;
   Problem* d_prob = nullptr;
   Item* d_items = nullptr;
   int* d_wgoff = nullptr;
@@ -179,6 +186,8 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
   BHIP_TRY(b, m.alloc((void**)&b->w, Ptot * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->xw, 3 * Ptot * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->Gx, W * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->Gx32, W * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->xres, 3 * W * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->status, W * sizeof(int)));
   BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
   std::vector<double> hw(Ptot, 0.0), hq(Ltot);
@@ -187,8 +196,8 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
     for (int j = 0; j < b->n[i]; ++j) hw[b->pad_off[i] + j] = 1.0 / b->n[i];
     for (int k = 0; k < b->L[i]; ++k) hq[b->lm_off[i] + k] = k + 1;
     const size_t po = b->pad_off[i];
-    pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po, b->Gx + i, b->status + i,
-                     nullptr, b->n[i], b->n_pad[i], b->L[i]};
+    pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po, b->Gx + i, b->Gx32 + i,
+                     b->xres + 3 * i, b->status + i, nullptr, b->n[i], b->n_pad[i], b->L[i]};
   }
   BHIP_TRY(b, hipMemcpy(b->w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->q, hq.data(), hq.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -210,10 +219,22 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
 // Lay out items and partial slots for a plan and upload the descriptors.
 static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   const size_t tsz = b->fp64 ? 8 : 4;
-  std::vector<int> ts(b->W);
+  std::vector<int> ts(b->W, 0), gsz(b->W, 0), bsz(b->W, 1);
+  int bmax = 1, lbuf = 0;
   for (int i = 0; i < b->W; ++i) {
-    ts[i] = team_size(b->n[i], p.cfg);
-    if (ts[i] == 0) return bfail(b, PCV_ESHAPE, "tiling cannot hold a walker");
+    if (p.engine == 2) {
+      const int B = e2_batch(b->n_pad[i], b->fp64);
+      if (B == 0 || !e2_fits(b->n_pad[i], p.c2)) return bfail(b, PCV_ESHAPE, "engine 2 cannot hold a walker");
+      const int g = e2_group(b->n_pad[i], p.c2.aptc, B);
+      if (g == 0) return bfail(b, PCV_ESHAPE, "engine 2 group cannot hold a walker");
+      gsz[i] = g;
+      bsz[i] = B;
+      bmax = std::max(bmax, B);
+      lbuf = std::max(lbuf, B * 3 * b->n_pad[i] * (int)tsz);
+    } else {
+      ts[i] = team_size(b->n[i], p.cfg);
+      if (ts[i] == 0) return bfail(b, PCV_ESHAPE, "tiling cannot hold a walker");
+    }
   }
   struct It {
     Item it;
@@ -224,18 +245,24 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   size_t vec_elems = 0;
   std::vector<size_t> vec_off(b->W);
   for (int i = 0; i < b->W; ++i) {
-    const int teams = p.cfg.wg / ts[i];
-    const int chunk = std::max(1, teams * p.per_team);
+    int chunk;
+    double per_lm;
+    if (p.engine == 2) {
+      chunk = std::max(1, bsz[i] * p.per_team);
+      per_lm = (double)b->n_pad[i] * 24.0 + 4000.0 / bsz[i];
+    } else {
+      const int teams = p.cfg.wg / ts[i];
+      chunk = std::max(1, teams * p.per_team);
+      per_lm = landmark_cost(b->n[i], p.cfg, ts[i]) / teams;
+    }
     const int cnt = (b->L[i] + chunk - 1) / chunk;
-    const double per_lm = landmark_cost(b->n[i], p.cfg, ts[i]);
     for (int k = 0; k < cnt; ++k) {
       Item it;
       it.prob = i;
       it.i0 = k * chunk;
       it.i1 = std::min(b->L[i], (k + 1) * chunk);
       it.slot = k;
-      const int iters = (it.i1 - it.i0 + teams - 1) / teams;
-      items.push_back({it, per_lm * iters * teams / (double)p.cfg.wg + 2000.0});
+      items.push_back({it, per_lm * (it.i1 - it.i0) + 3000.0});
     }
     slots[i] = cnt;
     slot_base[i + 1] = slot_base[i] + cnt;
@@ -265,7 +292,9 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   }
   wgoff[G] = (int)flat.size();
   size_t lds = 0;
-  for (int i = 0; i < b->W; ++i) lds = std::max(lds, engine_lds_bytes(p.cfg, ts[i], b->fp64));
+  if (p.engine == 2) lds = engine2_lds_bytes((size_t)lbuf, bmax);
+  else
+    for (int i = 0; i < b->W; ++i) lds = std::max(lds, engine_lds_bytes(p.cfg, ts[i], b->fp64));
 
   bdrop_graphs(b);
   b->pmem.release();
@@ -291,6 +320,10 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.hdr = b->hdr + (size_t)slot_base[i] * 4;
     P.vec = (char*)b->vec + vec_off[i] * tsz;
     P.fallbacks = nullptr;
+    P.Gx32 = b->Gx32 + i;
+    P.xres = b->xres + 3 * i;
+    P.bsz = bsz[i];
+    P.cg = gsz[i];
     P.n = b->n[i];
     P.n_pad = b->n_pad[i];
     P.L = b->L[i];
@@ -306,6 +339,8 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   BHIP_TRY(b, hipMemcpy(b->d_items, flat.data(), flat.size() * sizeof(Item), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
   b->plan = p;
+  b->lbuf = lbuf;
+  b->bmax = bmax;
   b->grid = G;
   b->n_items = (int)flat.size();
   b->lds = lds;
@@ -319,8 +354,11 @@ template <typename T>
 static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, double* sz, void* ds, void* dz) {
   hipError_t e = launch_prep<T>(b->d_prep, x, b->W, st);
   if (e != hipSuccess) return e;
-  e = launch_engine<T>(b->plan.cfg, b->grid, b->lds, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0,
-                       nullptr, st);
+  e = (b->plan.engine == 2)
+          ? launch_engine2<T>(b->plan.c2.aptc, b->plan.c2.aptg, b->grid, b->lds, b->lbuf, b->bmax, b->d_prob,
+                              b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st)
+          : launch_engine<T>(b->plan.cfg, b->grid, b->lds, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr,
+                             0, nullptr, st);
   if (e != hipSuccess) return e;
   Outs o{ds, dz, sz, nullptr};
   return launch_merge_exact<T>(b->d_prob, o, b->W, b->max_n_pad, nullptr, 0, st);
@@ -366,12 +404,38 @@ static pcv_status batch_run(pcv_batch* b, const void* x, double* sz, void* ds, v
   return PCV_OK;
 }
 
+static bool heuristic_plan2(const pcv_batch* b, BatchPlan* out) {
+  const int maxpad = *std::max_element(b->n_pad.begin(), b->n_pad.end());
+  int ac[16], ag[16], cnt = 0;
+  engine2_configs(b->fp64, ac, ag, &cnt);
+  for (int k = 0; k < cnt; ++k) {
+    const Engine2Cfg c{ac[k], ag[k]};
+    bool ok = true;
+    for (int i = 0; i < b->W && ok; ++i) {
+      const int B = e2_batch(b->n_pad[i], b->fp64);
+      ok = B > 0 && e2_fits(b->n_pad[i], c) && e2_group(b->n_pad[i], c.aptc, B) > 0;
+    }
+    (void)maxpad;
+    if (!ok) continue;
+    out->engine = 2;
+    out->c2 = c;
+    out->per_team = 4;
+    out->grid_mult = 1;
+    out->lpt = 1;
+    return true;
+  }
+  return false;
+}
+
 static BatchPlan heuristic_plan(const pcv_batch* b) {
+  BatchPlan p2;
+  if (heuristic_plan2(b, &p2)) return p2;
   EngineCfg menu[16];
   int cnt = 0;
   engine_configs(b->fp64, menu, &cnt);
   const int maxn = *std::max_element(b->n.begin(), b->n.end());
   BatchPlan best;
+  best.engine = 1;
   double best_cost = 1e300;
   for (int k = 0; k < cnt; ++k) {
     if (team_size(maxn, menu[k]) == 0) continue;
@@ -414,7 +478,7 @@ static bool cache_lookup(const char* path, const std::string& key, BatchPlan* p)
     if (at == std::string::npos) continue;
     std::istringstream v(line.substr(at + k.size()));
     BatchPlan q;
-    if (v >> q.cfg.wg >> q.cfg.apt >> q.per_team >> q.grid_mult >> q.lpt) {
+    if (v >> q.engine >> q.cfg.wg >> q.cfg.apt >> q.c2.aptc >> q.c2.aptg >> q.per_team >> q.grid_mult >> q.lpt) {
       *p = q;
       return true;
     }
@@ -439,8 +503,8 @@ static void cache_store(const char* path, const std::string& key, const BatchPla
     while (!t.empty() && (t.back() == ',' || t.back() == ' ')) t.pop_back();
     f << t << ",\n";
   }
-  f << "  \"" << key << "\": \"" << p.cfg.wg << " " << p.cfg.apt << " " << p.per_team << " " << p.grid_mult << " "
-    << p.lpt << "\"\n}\n";
+  f << "  \"" << key << "\": \"" << p.engine << " " << p.cfg.wg << " " << p.cfg.apt << " " << p.c2.aptc << " "
+    << p.c2.aptg << " " << p.per_team << " " << p.grid_mult << " " << p.lpt << "\"\n}\n";
 }
 
 extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path) {
@@ -491,42 +555,60 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   EngineCfg menu[16];
   int cnt = 0;
   engine_configs(b->fp64, menu, &cnt);
+  int ac[16], ag[16], cnt2 = 0;
+  engine2_configs(b->fp64, ac, ag, &cnt2);
   const int maxn = *std::max_element(b->n.begin(), b->n.end());
+  std::vector<BatchPlan> cands;
+  for (int k = 0; k < cnt2; ++k)
+    for (int per : {1, 2, 4, 8})
+      for (int gm : {1, 2})
+        for (int lpt : {1, 0}) {
+          BatchPlan c;
+          c.engine = 2;
+          c.c2 = Engine2Cfg{ac[k], ag[k]};
+          c.per_team = per;
+          c.grid_mult = gm;
+          c.lpt = lpt;
+          cands.push_back(c);
+        }
+  for (int k = 0; k < cnt; ++k) {
+    if (team_size(maxn, menu[k]) == 0) continue;
+    for (int per : {1, 4, 16})
+      for (int gm : {1, 2}) {
+        BatchPlan c;
+        c.engine = 1;
+        c.cfg = menu[k];
+        c.per_team = per;
+        c.grid_mult = gm;
+        c.lpt = 1;
+        cands.push_back(c);
+      }
+  }
   hipEvent_t e0, e1;
   BHIP_TRY(b, hipEventCreate(&e0));
   BHIP_TRY(b, hipEventCreate(&e1));
   BatchPlan best = base;
   float best_ms = 1e30f;
-  for (int k = 0; k < cnt; ++k) {
-    if (team_size(maxn, menu[k]) == 0) continue;
-    for (int per_team : {1, 2, 4, 8, 16})
-      for (int gm : {1, 2, 4})
-        for (int lpt : {1, 0}) {
-          BatchPlan c;
-          c.cfg = menu[k];
-          c.per_team = per_team;
-          c.grid_mult = gm;
-          c.lpt = lpt;
-          if (batch_apply(b, c) != PCV_OK) continue;
-          if (batch_run(b, x, sz, ds, nullptr, false) != PCV_OK) continue;
-          if (hipStreamSynchronize(b->stream) != hipSuccess) continue;
-          if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) continue;
-          bool ok = true;
-          for (int i = 0; i < 2 * b->W && ok; ++i) ok = std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i]));
-          if (!ok) continue;
-          (void)hipEventRecord(e0, b->stream);
-          for (int r = 0; r < 3; ++r) batch_run(b, x, sz, ds, nullptr, false);
-          (void)hipEventRecord(e1, b->stream);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
-          }
-        }
+  for (const BatchPlan& c : cands) {
+    if (batch_apply(b, c) != PCV_OK) continue;
+    if (batch_run(b, x, sz, ds, nullptr, false) != PCV_OK) continue;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) continue;
+    if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) continue;
+    bool ok = true;
+    for (int i = 0; i < 2 * b->W && ok; ++i) ok = std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i]));
+    if (!ok) continue;
+    (void)hipEventRecord(e0, b->stream);
+    for (int r = 0; r < 3; ++r) batch_run(b, x, sz, ds, nullptr, false);
+    (void)hipEventRecord(e1, b->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
   }
-  hipEventDestroy(e0);
+  (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   tmp.release();
   cache_store(cache_path, key, best);

@@ -56,4 +56,38 @@ inline double landmark_cost(int n, EngineCfg c, int ts) {
   return ts * (c.apt * 30.0 + red + 320.0) * regs_penalty;
 }
 
+// ---- split-role engine planning
+// Two landmark buffers of one pipeline batch must fit in this much LDS.
+constexpr size_t kE2LdsBudget = 124 * 1024;
+
+// Landmarks per pipeline batch: enough atoms in flight per workgroup
+// (about 4096 per batch), limited by LDS and by the 64 solver lanes.
+inline int e2_batch(int n_pad, bool fp64) {
+  const size_t per = (size_t)3 * n_pad * (fp64 ? 8 : 4);
+  const int bmax = (int)(kE2LdsBudget / (2 * per));
+  if (bmax < 1) return 0;
+  const int want = std::max(1, (4096 + n_pad - 1) / n_pad);
+  return std::min(std::min(want, bmax), 64);
+}
+
+inline bool e2_lds_ok(int n_pad, int B, bool fp64) {
+  return B >= 1 && B <= 64 && (size_t)2 * B * 3 * n_pad * (fp64 ? 8 : 4) <= kE2LdsBudget;
+}
+
+// Lanes per landmark in the correlation stage: the smallest group that holds
+// n_pad atoms within aptc per lane, preferring no more groups than landmarks
+// per batch.  0 if none fits.
+inline int e2_group(int n_pad, int aptc, int B) {
+  const int gs[4] = {16, 32, 64, 192};
+  int first = 0;
+  for (int g : gs) {
+    if ((n_pad + g - 1) / g > aptc) continue;
+    if (first == 0) first = g;
+    if (192 / g <= B) return g;
+  }
+  return first;
+}
+
+inline bool e2_fits(int n_pad, Engine2Cfg c) { return (n_pad + 255) / 256 <= c.aptg; }
+
 }  // namespace pcv

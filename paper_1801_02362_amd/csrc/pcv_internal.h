@@ -31,7 +31,11 @@ struct Problem {
   double* hdr;          // [n_slots][4]: m, Z, S, q0 per item
   void* vec;            // [n_slots][6][n_pad] accumulators (U then V)
   long long* fallbacks; // counter of Jacobi fallbacks (may be null)
+  const double* Gx32;   // [1] sum_j (w_j x_j rounded to T)^2 / w_j - |xres|^2 (split-role engine)
+  const double* xres;   // [3] sum_j (w_j x_j rounded to T): centring residual of that rounding
   int n, n_pad, L, ts, n_slots;
+  int bsz;              // split-role engine: landmarks per pipeline batch
+  int cg;               // split-role engine: lanes per landmark in the correlation stage
   int out_off;          // atom offset of this problem in concatenated inputs/outputs
   int out_idx;          // index of this problem's (s, z) pair
   double lam;
@@ -55,6 +59,8 @@ struct PrepArgs {
   const double* w;  // [n_pad]
   double* xw;       // [3][n_pad]
   double* Gx;       // [1]
+  double* Gx32;     // [1] see Problem::Gx32
+  double* xres;     // [3] see Problem::xres
   int* status;      // [1]: sticky, set to 1 on non-finite input
   long long* counters;  // optional: CNT_EVALS / CNT_EXPENSIVE for Algorithm 1
   int n, n_pad, L;
@@ -85,6 +91,12 @@ struct EngineCfg {
   int apt;   // atoms per thread
 };
 
+// Split-role engine instantiation: atoms per correlation lane / gradient lane.
+struct Engine2Cfg {
+  int aptc;
+  int aptg;
+};
+
 // ---- launchers (pcv_kernels.hip) -------------------------------------------
 // All return hipSuccess or the launch error.
 template <typename T>
@@ -109,6 +121,14 @@ hipError_t launch_merge_close(const Problem* prob, Outs outs, CloseArgs ca, doub
                               hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);
+
+template <typename T>
+hipError_t launch_engine2(int aptc, int aptg, int grid, size_t lds, int lbuf_bytes, int bmax,
+                          const Problem* probs, const Item* items, const int* wg_off, int mode,
+                          const int* flag, int run_if, double* dout, hipStream_t st);
+void engine2_configs(bool fp64, int* aptc, int* aptg, int* count);
+hipError_t engine2_init_attributes();
+size_t engine2_lds_bytes(size_t lbuf, int bmax);
 
 bool engine_supported(EngineCfg cfg, bool fp64);
 void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
 // ------------------------------------------------------------ frame prep
 template <typename T, int BS>
 __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& Gx, bool& finite,
-                             double c[3]) {
+                             double c[3], double g32[4]) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < a.n; j += BS) {
     const double wj = a.w[j];
@@ -189,37 +189,50 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   block_sum<4, BS>(v, sh);
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
-  double g[1] = {0.0};
+  // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x rounded to T.
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < a.n_pad; j += BS) {
     if (j < a.n) {
       const double wj = a.w[j];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const double xv = (double)x[3 * j + d] - c[d];
-        a.xw[(size_t)d * a.n_pad + j] = wj * xv;
+        const double xwv = wj * xv;
+        a.xw[(size_t)d * a.n_pad + j] = xwv;
         g[0] = fma(wj * xv, xv, g[0]);
+        const double r = (double)(T)xwv;
+        if (wj > 0.0) g[1] += r * r / wj;
+        g[2 + d] += r;
       }
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) a.xw[(size_t)d * a.n_pad + j] = 0.0;
     }
   }
-  block_sum<1, BS>(g, sh);
+  block_sum<5, BS>(g, sh);
   Gx = g[0];
+  g32[0] = g[1] - (g[2] * g[2] + g[3] * g[3] + g[4] * g[4]);
+  g32[1] = g[2];
+  g32[2] = g[3];
+  g32[3] = g[4];
 }
 
 // One workgroup per problem (the batched path and Algorithm 1).
 template <typename T>
 __global__ __launch_bounds__(256) void prep_kernel(const PrepArgs* __restrict__ args,
                                                    const void* __restrict__ x_base) {
-  __shared__ double sh[4 * 4];
+  __shared__ double sh[4 * 5];
   const PrepArgs a = args[blockIdx.x];
   const T* x = (const T*)x_base + 3 * a.x_off;
-  double Gx, c[3];
+  double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, 256>(a, x, sh, Gx, finite, c);
+  centre_frame<T, 256>(a, x, sh, Gx, finite, c, g32);
   if (threadIdx.x == 0) {
     *a.Gx = Gx;
+    *a.Gx32 = g32[0];
+    a.xres[0] = g32[1];
+    a.xres[1] = g32[2];
+    a.xres[2] = g32[3];
     if (!finite) *a.status = 1;
     if (a.counters) {
       a.counters[CNT_EVALS] += 1;
@@ -238,9 +251,9 @@ __global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* _
   constexpr int BS = 1024;
   __shared__ double sh[16 * 9];
   __shared__ int s_flag;
-  double Gx, c[3];
+  double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, BS>(a, x, sh, Gx, finite, c);
+  centre_frame<T, BS>(a, x, sh, Gx, finite, c, g32);
   const int init = *cs.init;
   double Dxy = NAN;
   if (init) {
@@ -279,6 +292,10 @@ __global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* _
     *cs.flag = flag;
     *cs.force = 0;
     *a.Gx = Gx;
+    *a.Gx32 = g32[0];
+    a.xres[0] = g32[1];
+    a.xres[1] = g32[2];
+    a.xres[2] = g32[3];
     if (!finite) *a.status = 1;
     if (nan_outs.rec) *nan_outs.rec = flag;
     s_flag = flag;

@@ -21,7 +21,7 @@
 #define PCV_HD __host__ __device__ __forceinline__
 // Rarely taken paths are kept out of line so their registers do not count
 // against the streaming loops that call them.
-#define PCV_COLD __host__ __device__ __noinline__
+#define PCV_COLD __host__ __device__ inline __attribute__((noinline))
 
 namespace pcv {
 

@@ -20,7 +20,7 @@ def _run_exact(torch, lm, frames, lam, *, dtype, tol, name, q=None, w=None, plan
     say(f"[exact] {name}: L={lm.shape[0]} n={lm.shape[1]} frames={len(frames)} plan={plan}")
     cv = pcv.PathCV(dev(lm, dtype), lam, q=q, w=w, use_graph=use_graph)
     if plan is not None:
-        cv.set_plan(*plan)
+        cv.set_plan(**plan)
     x = torch.empty(lm.shape[1], 3, dtype=dtype, device="cuda")
     for t, f in enumerate(frames):
         x.copy_(torch.as_tensor(f, dtype=dtype))
@@ -82,19 +82,26 @@ def test_weights_and_properties(torch):
     _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name="weights", q=q, w=w)
 
 
-def _plans(n, wg_apt):
+def _plans(n, wg_apt, e2):
     out = []
     for wg, apt in wg_apt:
         ts = 16
         while ts * apt < n:
             ts *= 2
         while ts <= wg:
-            out.append((wg, apt, ts, 0))
+            out.append(dict(engine=1, wg=wg, apt=apt, team=ts))
             ts *= 4
+    n_pad = (n + 63) // 64 * 64
+    for aptc, aptg in e2:
+        for g in (16, 32, 64, 192):
+            if -(-n_pad // g) <= aptc and -(-n_pad // 256) <= aptg:
+                for batch in (1, 5, 13):
+                    out.append(dict(engine=2, wg=512, apt=aptc, team=g, aptg=aptg, batch=batch))
     return out
 
 
-@pytest.mark.parametrize("plan", _plans(300, [(256, 1), (256, 2), (256, 4), (256, 8), (512, 8), (512, 10), (512, 16)]))
+@pytest.mark.parametrize("plan", _plans(300, [(256, 1), (256, 2), (256, 4), (256, 8), (512, 8), (512, 10), (512, 16)],
+                                        [(4, 2), (8, 4), (16, 8), (28, 21)]))
 def test_every_tiling_matches(torch, plan):
     from gpu_util import TOL32
     sysm, frames = wl.cfg1(3000)
