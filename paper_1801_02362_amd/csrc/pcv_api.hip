@@ -166,7 +166,6 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
 // Build (or rebuild) work items and problem descriptors for the current plan.
 static pcv_status build_plan(pcv_handle* h) {
   Plan& p = h->plan;
-  const size_t acc = h->fp64 ? 8 : 4;
   // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
   const int unit = (p.engine == 2) ? p.B : p.cfg.wg / p.ts;
   const int units = (h->L + unit - 1) / unit;
@@ -185,7 +184,8 @@ static pcv_status build_plan(pcv_handle* h) {
   }
   h->pmem.release();
   HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, (size_t)p.n_items * 4 * sizeof(double)));
-  HIP_TRY(h, h->pmem.alloc(&h->vec, (size_t)p.n_items * 6 * h->n_pad * acc));
+  HIP_TRY(h, h->pmem.alloc(&h->vec, (size_t)p.n_items * (h->fp64 ? partial_bytes<double>(h->n_pad)
+                                                                  : partial_bytes<float>(h->n_pad))));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 3 * sizeof(Problem)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));

@@ -266,8 +266,8 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     }
     slots[i] = cnt;
     slot_base[i + 1] = slot_base[i] + cnt;
-    vec_off[i] = vec_elems;
-    vec_elems += (size_t)cnt * 6 * b->n_pad[i];
+    vec_off[i] = vec_elems;   // bytes
+    vec_elems += (size_t)cnt * (b->fp64 ? partial_bytes<double>(b->n_pad[i]) : partial_bytes<float>(b->n_pad[i]));
   }
   const int G = std::max(1, std::min((int)items.size(), p.grid_mult * b->cus));
   std::vector<std::vector<int>> per_wg(G);
@@ -299,7 +299,7 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   bdrop_graphs(b);
   b->pmem.release();
   BHIP_TRY(b, b->pmem.alloc((void**)&b->hdr, (size_t)slot_base[b->W] * 4 * sizeof(double)));
-  BHIP_TRY(b, b->pmem.alloc(&b->vec, vec_elems * tsz));
+  BHIP_TRY(b, b->pmem.alloc(&b->vec, vec_elems));
   BHIP_TRY(b, b->pmem.alloc((void**)&b->d_prob, b->W * sizeof(Problem)));
   BHIP_TRY(b, b->pmem.alloc((void**)&b->d_items, flat.size() * sizeof(Item)));
   BHIP_TRY(b, b->pmem.alloc((void**)&b->d_wgoff, (G + 1) * sizeof(int)));
@@ -318,7 +318,7 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.Rxy = nullptr;
     P.Rsave = nullptr;
     P.hdr = b->hdr + (size_t)slot_base[i] * 4;
-    P.vec = (char*)b->vec + vec_off[i] * tsz;
+    P.vec = (char*)b->vec + vec_off[i];
     P.fallbacks = nullptr;
     P.Gx32 = b->Gx32 + i;
     P.xres = b->xres + 3 * i;

@@ -389,15 +389,16 @@ __device__ __forceinline__ void e2_grad(const E2Item<T>& c, int gw, int lane_in)
     __syncthreads();
   }
   __syncthreads();   // item totals published by the solver
-  part_t* vec = (part_t*)c.P->vec + (size_t)c.slot * 6 * n_pad;
+  part_t* pu = partial_u<part_t>(c.P->vec, c.slot, n_pad);
+  double* pv = partial_v<part_t>(c.P->vec, c.slot, n_pad);
 #pragma unroll
   for (int k = 0; k < APTG; ++k) {
     const int j = gidx + 256 * k;
     if (j < n_pad) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        vec[(size_t)d * n_pad + j] = (part_t)((double)U[d][k] - c.misc[3 + d]);
-        vec[(size_t)(3 + d) * n_pad + j] = (part_t)(V[d][k] - c.misc[6 + d]);
+        pu[(size_t)d * n_pad + j] = (part_t)((double)U[d][k] - c.misc[3 + d]);
+        pv[(size_t)d * n_pad + j] = V[d][k] - c.misc[6 + d];
       }
     }
   }

@@ -29,7 +29,7 @@ struct Problem {
   const double* Rxy;    // [9] (APPROX)
   double* Rsave;        // [L][9]: read in APPROX, written in EXACT_SAVE
   double* hdr;          // [n_slots][4]: m, Z, S, q0 per item
-  void* vec;            // [n_slots][6][n_pad] accumulators (U then V)
+  void* vec;            // per slot: U [3][n_pad] (coordinate type), then V [3][n_pad] (FP64)
   long long* fallbacks; // counter of Jacobi fallbacks (may be null)
   const double* Gx32;   // [1] sum_j (w_j x_j rounded to T)^2 / w_j - |xres|^2 (split-role engine)
   const double* xres;   // [3] sum_j (w_j x_j rounded to T): centring residual of that rounding
@@ -44,6 +44,22 @@ struct Problem {
 struct Item {
   int prob, i0, i1, slot;
 };
+
+// Partial accumulators of one work item: U = sum e (q - q0) r in the
+// coordinate type, V = sum e r in FP64 (the merge multiplies V by q0 - s).
+template <typename T>
+__host__ __device__ inline size_t partial_bytes(int n_pad) {
+  return (size_t)3 * n_pad * (sizeof(T) + sizeof(double));
+}
+template <typename T>
+__host__ __device__ inline T* partial_u(void* vec, int slot, int n_pad) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(vec) + (size_t)slot * partial_bytes<T>(n_pad));
+}
+template <typename T>
+__host__ __device__ inline double* partial_v(void* vec, int slot, int n_pad) {
+  return reinterpret_cast<double*>(reinterpret_cast<char*>(partial_u<T>(vec, slot, n_pad)) +
+                                   (size_t)3 * n_pad * sizeof(T));
+}
 
 // Output base pointers of one call (problem p writes at atom offset
 // out_off and (s, z) pair out_idx).

@@ -556,15 +556,16 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
       if (team < stride) m = mn;
     }
     if (team == 0) {
-      part_t* vec = (part_t*)P.vec + (size_t)item.slot * 6 * n_pad;
+      part_t* pu = partial_u<part_t>(P.vec, item.slot, n_pad);
+      double* pv = partial_v<part_t>(P.vec, item.slot, n_pad);
 #pragma unroll
       for (int k = 0; k < APT; ++k) {
         const int j = lane + ts * k;
         if (j < n_pad) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            vec[(size_t)d * n_pad + j] = (part_t)U[d][k];
-            vec[(size_t)(3 + d) * n_pad + j] = (part_t)V[d][k];
+            pu[(size_t)d * n_pad + j] = (part_t)U[d][k];
+            pv[(size_t)d * n_pad + j] = V[d][k];
           }
         }
       }
@@ -618,7 +619,6 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   const int c = blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int n_pad = P.n_pad;
-  const acc* vec = (const acc*)P.vec;
   double gs = 0.0, gz = 0.0;
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
@@ -630,11 +630,10 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
-      const acc* base = vec + (size_t)g0 * 6 * n_pad;
 #pragma unroll 4
       for (int t = 0; t < gn; ++t) {
-        const double u = (double)base[((size_t)t * 6 + c) * n_pad + j];
-        const double v = (double)base[((size_t)t * 6 + 3 + c) * n_pad + j];
+        const double u = (double)partial_u<acc>(P.vec, g0 + t, n_pad)[(size_t)c * n_pad + j];
+        const double v = partial_v<acc>(P.vec, g0 + t, n_pad)[(size_t)c * n_pad + j];
         const double f = fq[0][t];
         gs = fma(f, fma(fq[1][t], v, u), gs);
         gz = fma(f, v, gz);
@@ -685,7 +684,6 @@ __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __rest
   }
   __syncthreads();
   // beta (rows 0..2) and betaz (rows 3..5) for every (coordinate, atom) column.
-  const acc* vec = (const acc*)P.vec;
   const int ncol = 3 * n_pad;
   const int cl = threadIdx.x & 127, grp = threadIdx.x >> 7;
   for (int col0 = 0; col0 < ncol; col0 += 128) {
@@ -694,9 +692,8 @@ __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __rest
     if (col < ncol) {
       const int c = col / n_pad, j = col - c * n_pad;
       for (int g = grp; g < ns; g += 8) {
-        const acc* base = vec + (size_t)g * 6 * n_pad;
-        const double u = (double)base[(size_t)c * n_pad + j];
-        const double v = (double)base[(size_t)(3 + c) * n_pad + j];
+        const double u = (double)partial_u<acc>(P.vec, g, n_pad)[(size_t)c * n_pad + j];
+        const double v = partial_v<acc>(P.vec, g, n_pad)[(size_t)c * n_pad + j];
         su = fma(fq[0][g], fma(fq[1][g], v, u), su);
         sv = fma(fq[0][g], v, sv);
       }
