@@ -241,12 +241,12 @@ static pcv_status build_plan(pcv_handle* h) {
 static bool default_plan2(pcv_handle* h) {
   const int B = e2_batch(h->n_pad, h->fp64);
   if (B == 0) return false;
-  int ac[16], ag[16], cnt = 0;
-  engine2_configs(h->fp64, ac, ag, &cnt);
+  int nw[16], ac[16], ag[16], cnt = 0;
+  engine2_configs(h->fp64, nw, ac, ag, &cnt);
   for (int k = 0; k < cnt; ++k) {
-    const Engine2Cfg c{ac[k], ag[k]};
+    const Engine2Cfg c{nw[k], ac[k], ag[k]};
     if (!e2_fits(h->n_pad, c)) continue;
-    const int g = e2_group(h->n_pad, c.aptc, B);
+    const int g = e2_group(h->n_pad, c, B);
     if (g == 0) continue;
     h->plan.engine = 2;
     h->plan.c2 = c;
@@ -407,7 +407,7 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
   }
   const Plan& p = h->plan;
   hipError_t e = (p.engine == 2)
-      ? launch_engine2<T>(p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
+      ? launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
                           h->d_wgoff, mode, flag, run_if, msd, st)
       : launch_engine<T>(p.cfg, p.grid, p.lds, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if,
                          msd, st);
@@ -590,14 +590,15 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
     p.cfg = c;
     p.ts = q->team;
   } else if (q->engine == 2) {
-    int ac[16], ag[16], cnt = 0;
-    engine2_configs(h->fp64, ac, ag, &cnt);
-    bool found = false;
-    for (int k = 0; k < cnt; ++k) found |= (ac[k] == q->apt && ag[k] == q->aptg);
-    if (!found) return fail(h, PCV_EUNSUPPORTED, "engine 2 tiling not compiled in");
-    const Engine2Cfg c{q->apt, q->aptg};
+    int nw[16], ac[16], ag[16], cnt = 0;
+    engine2_configs(h->fp64, nw, ac, ag, &cnt);
+    int ncw = 0;
+    for (int k = 0; k < cnt; ++k)
+      if (ac[k] == q->apt && ag[k] == q->aptg) ncw = nw[k];
+    if (!ncw) return fail(h, PCV_EUNSUPPORTED, "engine 2 tiling not compiled in");
+    const Engine2Cfg c{ncw, q->apt, q->aptg};
     const int g = q->team;
-    if (!(g == 16 || g == 32 || g == 64 || g == 192) || (h->n_pad + g - 1) / g > c.aptc || !e2_fits(h->n_pad, c))
+    if (!e2_group_ok(g, c) || (h->n_pad + g - 1) / g > c.aptc || !e2_fits(h->n_pad, c))
       return fail(h, PCV_EINVAL, "engine 2 tiling cannot hold the structure");
     if (!e2_lds_ok(h->n_pad, q->batch, h->fp64)) return fail(h, PCV_EINVAL, "batch does not fit in LDS");
     p.engine = 2;

@@ -27,14 +27,14 @@ namespace {
 struct BatchPlan {
   int engine = 2;
   EngineCfg cfg{256, 8};   // engine 1 tiling
-  Engine2Cfg c2{16, 8};    // engine 2 tiling
+  Engine2Cfg c2{3, 16, 8}; // engine 2 tiling
   int per_team = 4;        // engine 1: landmarks per team per item; engine 2: batches per item
   int grid_mult = 2;       // workgroups = grid_mult * CUs
   int lpt = 1;             // 1: longest-processing-time schedule, 0: round robin
   std::string str() const {
     std::ostringstream o;
     if (engine == 2)
-      o << "engine=2 aptc=" << c2.aptc << " aptg=" << c2.aptg;
+      o << "engine=2 ncw=" << c2.ncw << " aptc=" << c2.aptc << " aptg=" << c2.aptg;
     else
       o << "engine=1 wg=" << cfg.wg << " apt=" << cfg.apt;
     o << " per_item=" << per_team << " grid_mult=" << grid_mult << " schedule=" << (lpt ? "lpt" : "rr");
@@ -225,7 +225,7 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     if (p.engine == 2) {
       const int B = e2_batch(b->n_pad[i], b->fp64);
       if (B == 0 || !e2_fits(b->n_pad[i], p.c2)) return bfail(b, PCV_ESHAPE, "engine 2 cannot hold a walker");
-      const int g = e2_group(b->n_pad[i], p.c2.aptc, B);
+      const int g = e2_group(b->n_pad[i], p.c2, B);
       if (g == 0) return bfail(b, PCV_ESHAPE, "engine 2 group cannot hold a walker");
       gsz[i] = g;
       bsz[i] = B;
@@ -355,7 +355,7 @@ static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, dou
   hipError_t e = launch_prep<T>(b->d_prep, x, b->W, st);
   if (e != hipSuccess) return e;
   e = (b->plan.engine == 2)
-          ? launch_engine2<T>(b->plan.c2.aptc, b->plan.c2.aptg, b->grid, b->lds, b->lbuf, b->bmax, b->d_prob,
+          ? launch_engine2<T>(b->plan.c2.ncw, b->plan.c2.aptc, b->plan.c2.aptg, b->grid, b->lds, b->lbuf, b->bmax, b->d_prob,
                               b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st)
           : launch_engine<T>(b->plan.cfg, b->grid, b->lds, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr,
                              0, nullptr, st);
@@ -406,14 +406,14 @@ static pcv_status batch_run(pcv_batch* b, const void* x, double* sz, void* ds, v
 
 static bool heuristic_plan2(const pcv_batch* b, BatchPlan* out) {
   const int maxpad = *std::max_element(b->n_pad.begin(), b->n_pad.end());
-  int ac[16], ag[16], cnt = 0;
-  engine2_configs(b->fp64, ac, ag, &cnt);
+  int nw[16], ac[16], ag[16], cnt = 0;
+  engine2_configs(b->fp64, nw, ac, ag, &cnt);
   for (int k = 0; k < cnt; ++k) {
-    const Engine2Cfg c{ac[k], ag[k]};
+    const Engine2Cfg c{nw[k], ac[k], ag[k]};
     bool ok = true;
     for (int i = 0; i < b->W && ok; ++i) {
       const int B = e2_batch(b->n_pad[i], b->fp64);
-      ok = B > 0 && e2_fits(b->n_pad[i], c) && e2_group(b->n_pad[i], c.aptc, B) > 0;
+      ok = B > 0 && e2_fits(b->n_pad[i], c) && e2_group(b->n_pad[i], c, B) > 0;
     }
     (void)maxpad;
     if (!ok) continue;
@@ -478,7 +478,8 @@ static bool cache_lookup(const char* path, const std::string& key, BatchPlan* p)
     if (at == std::string::npos) continue;
     std::istringstream v(line.substr(at + k.size()));
     BatchPlan q;
-    if (v >> q.engine >> q.cfg.wg >> q.cfg.apt >> q.c2.aptc >> q.c2.aptg >> q.per_team >> q.grid_mult >> q.lpt) {
+    if (v >> q.engine >> q.cfg.wg >> q.cfg.apt >> q.c2.ncw >> q.c2.aptc >> q.c2.aptg >> q.per_team >> q.grid_mult >>
+        q.lpt) {
       *p = q;
       return true;
     }
@@ -503,8 +504,8 @@ static void cache_store(const char* path, const std::string& key, const BatchPla
     while (!t.empty() && (t.back() == ',' || t.back() == ' ')) t.pop_back();
     f << t << ",\n";
   }
-  f << "  \"" << key << "\": \"" << p.engine << " " << p.cfg.wg << " " << p.cfg.apt << " " << p.c2.aptc << " "
-    << p.c2.aptg << " " << p.per_team << " " << p.grid_mult << " " << p.lpt << "\"\n}\n";
+  f << "  \"" << key << "\": \"" << p.engine << " " << p.cfg.wg << " " << p.cfg.apt << " " << p.c2.ncw << " "
+    << p.c2.aptc << " " << p.c2.aptg << " " << p.per_team << " " << p.grid_mult << " " << p.lpt << "\"\n}\n";
 }
 
 extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path) {
@@ -555,8 +556,8 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   EngineCfg menu[16];
   int cnt = 0;
   engine_configs(b->fp64, menu, &cnt);
-  int ac[16], ag[16], cnt2 = 0;
-  engine2_configs(b->fp64, ac, ag, &cnt2);
+  int nw[16], ac[16], ag[16], cnt2 = 0;
+  engine2_configs(b->fp64, nw, ac, ag, &cnt2);
   const int maxn = *std::max_element(b->n.begin(), b->n.end());
   std::vector<BatchPlan> cands;
   for (int k = 0; k < cnt2; ++k)
@@ -565,7 +566,7 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
         for (int lpt : {1, 0}) {
           BatchPlan c;
           c.engine = 2;
-          c.c2 = Engine2Cfg{ac[k], ag[k]};
+          c.c2 = Engine2Cfg{nw[k], ac[k], ag[k]};
           c.per_team = per;
           c.grid_mult = gm;
           c.lpt = lpt;

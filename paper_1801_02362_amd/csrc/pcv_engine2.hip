@@ -9,13 +9,13 @@
 //               mode), and folds the batch into the running log-sum-exp
 //               (m, Z, S); it publishes R_i, e_i (q_i - q0), e_i and the
 //               rescale factor of the batch through LDS.
-//   waves 1-3   correlation: async copies (global_load_lds_dwordx4) bring the
+//   correlation waves (3, or 2 for large structures): async copies (global_load_lds_dwordx4) bring the
 //               next batch of landmarks from HBM into an LDS double buffer
 //               while the current batch is contracted with the centred,
 //               weighted structure held in registers, M = sum_j a_j (w_j x_j)^T
 //               in FP64; groups of g lanes share one landmark and reduce
 //               inside the wave.
-//   waves 4-7   gradient: every lane owns atoms j = lane + 256 k and keeps
+//   gradient waves (the rest): every lane owns atoms j = lane + 64 NGW k and keeps
 //               U = sum_i e_i (q_i - q0) r_i (FP32) and V = sum_i e_i r_i
 //               (FP64) for the rotated centred landmarks r_i = R_i (a_i - c_i),
 //               re-reading the landmark coordinates of two batches ago
@@ -39,9 +39,7 @@ template <typename T> struct UAcc { using type = float; };
 template <> struct UAcc<double> { using type = double; };
 
 constexpr int kWG2 = 512;
-constexpr int kCW = 3;      // correlation waves
-constexpr int kGW = 4;      // gradient waves
-constexpr int kRes = 12;    // doubles per landmark result: R[9], al, be, pad
+constexpr int kRes = 12;    // doubles per landmark result: R[9], al, be, sc
 
 __device__ __forceinline__ double clamp0_2(double v) { return v < 0.0 ? 0.0 : v; }
 __device__ __forceinline__ double scale2(double m_from, double m_to, double lam) {
@@ -86,7 +84,7 @@ struct E2Item {
 // Async copy of batch b (contiguous landmarks) into its LDS buffer: 1 KiB per
 // wave instruction (16 B per lane), then 256 B pieces for the tail (a
 // landmark is 12 n_pad or 24 n_pad bytes with n_pad a multiple of 64).
-template <typename T>
+template <typename T, int NCW>
 __device__ __forceinline__ void e2_issue(const E2Item<T>& c, int b, int cw, int lane) {
   const int i0 = c.i0 + b * c.B;
   const int cnt = min(c.B, c.i1 - i0);
@@ -95,10 +93,10 @@ __device__ __forceinline__ void e2_issue(const E2Item<T>& c, int b, int cw, int 
   const int tails = (int)((bytes - (size_t)chunks * 1024) / 256);
   const char* src = reinterpret_cast<const char*>(c.A + (size_t)i0 * c.lm_elems);
   char* dst = c.lbase + (size_t)(b & 1) * c.lbuf_bytes;
-  for (int ch = cw; ch < chunks; ch += kCW)
+  for (int ch = cw; ch < chunks; ch += NCW)
     __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)ch * 1024 + lane * 16),
                                      (__attribute__((address_space(3))) void*)(dst + (size_t)ch * 1024), 16, 0, 0);
-  for (int tc = cw; tc < tails; tc += kCW) {
+  for (int tc = cw; tc < tails; tc += NCW) {
     const size_t off = (size_t)chunks * 1024 + (size_t)tc * 256;
     __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 4),
                                      (__attribute__((address_space(3))) void*)(dst + off), 4, 0, 0);
@@ -122,13 +120,13 @@ __device__ __forceinline__ T pin(T v) {
   return v;
 }
 
-template <typename T, int APTC>
+template <typename T, int NCW, int APTC>
 __device__ __forceinline__ void e2_corr(const E2Item<T>& c, int cw, int lane_in) {
   const int lane = opaque(lane_in);
   const int g = c.g, n_pad = c.n_pad;
   const int cidx = cw * 64 + lane;
   const int grp = cidx / g, lg = cidx - grp * g;
-  const int ngrp = (kCW * 64) / g;
+  const int ngrp = (NCW * 64) / g;
   T xw[3][APTC];
   for (int t = -1; t < c.nb + 2; ++t) {
     if (t < 0) {
@@ -138,11 +136,11 @@ __device__ __forceinline__ void e2_corr(const E2Item<T>& c, int cw, int lane_in)
         const int j = lg + g * k;
         const bool in = j < n_pad;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xw[d][k] = in ? (T)xwp[(size_t)d * n_pad + j] : T(0);
+        for (int d = 0; d < 3; ++d) xw[d][k] = in ? (T)ldg(xwp + (size_t)d * n_pad + j) : T(0);
       }
-      e2_issue(c, 0, cw, lane);
+      e2_issue<T, NCW>(c, 0, cw, lane);
     } else {
-      if (t + 1 < c.nb) e2_issue(c, t + 1, cw, lane);
+      if (t + 1 < c.nb) e2_issue<T, NCW>(c, t + 1, cw, lane);
       if (t < c.nb) {
         const int i0 = c.i0 + t * c.B;
         const int cnt = min(c.B, c.i1 - i0);
@@ -197,7 +195,7 @@ __device__ __forceinline__ void e2_corr(const E2Item<T>& c, int cw, int lane_in)
 }
 
 // Solver wave: nb + 3 pipeline steps + 1 item-end barrier.
-template <typename T>
+template <typename T, int NCW>
 __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
   const int lane = opaque(lane_in);
   const Problem& P = *c.P;
@@ -210,8 +208,8 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
       const int cnt = min(c.B, c.i1 - i0);
       const double* pt = c.part + (size_t)(tb & 1) * c.bmax * 3 * 9;
       double* rs = c.res + (size_t)(tb % 3) * c.bmax * kRes;
-      const double Gxx = *P.Gx32;
-      const int np = (c.g <= 64) ? 1 : kCW;
+      const double Gxx = ldg(P.Gx32);
+      const int np = (c.g <= 64) ? 1 : NCW;
       for (int b0 = 0; b0 < cnt; b0 += 64) {
         const int b = b0 + lane;
         const bool act = b < cnt;
@@ -224,20 +222,29 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
           double Mc[9];
 #pragma unroll
           for (int k = 0; k < 9; ++k) Mc[k] = pt[((size_t)b * 3 + 0) * 9 + k];
+          double cap[3], xr[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            cap[d] = ldg(P.ca + (size_t)i * 3 + d);
+            xr[d] = ldg(P.xres + d);
+          }
           for (int p = 1; p < np; ++p)
 #pragma unroll
             for (int k = 0; k < 9; ++k) Mc[k] += pt[((size_t)b * 3 + p) * 9 + k];
           // The correlation used w_j x_j rounded to T, whose sum (xres) is not
           // exactly zero; remove its coupling to the landmark centroid.
-          const double* cap = P.ca + (size_t)i * 3;
 #pragma unroll
           for (int r0 = 0; r0 < 3; ++r0)
 #pragma unroll
-            for (int c0 = 0; c0 < 3; ++c0) Mc[r0 * 3 + c0] = fma(-cap[r0], P.xres[c0], Mc[r0 * 3 + c0]);
-          const double Ga = P.Ga[i];
+            for (int c0 = 0; c0 < 3; ++c0) Mc[r0 * 3 + c0] = fma(-cap[r0], xr[c0], Mc[r0 * 3 + c0]);
+          const double Ga = ldg(P.Ga + i);
           if (c.mode == MODE_APPROX) {
-            const double* Rs = P.Rsave + (size_t)i * 9;
-            const double* Rx = P.Rxy;
+            double Rs[9], Rx[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+              Rs[k] = ldg(P.Rsave + (size_t)i * 9 + k);
+              Rx[k] = ldg(P.Rxy + k);
+            }
             double tr = 0.0;
 #pragma unroll
             for (int r0 = 0; r0 < 3; ++r0)
@@ -258,11 +265,11 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
             quat_to_rot(qv, R);
             if (c.mode == MODE_EXACT_SAVE) {
 #pragma unroll
-              for (int k = 0; k < 9; ++k) P.Rsave[(size_t)i * 9 + k] = R[k];
+              for (int k = 0; k < 9; ++k) stg(P.Rsave + (size_t)i * 9 + k, R[k]);
             }
           }
-          if (c.dout != nullptr) c.dout[i] = D;
-          qi = P.q[i];
+          if (c.dout != nullptr) stg(c.dout + i, D);
+          qi = ldg(P.q + i);
           // residual of the centroid split used by the gradient waves: c - (T)c
 #pragma unroll
           for (int d = 0; d < 3; ++d) c3[d] = cap[d] - (double)(T)cap[d];
@@ -313,21 +320,22 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
       c.misc[6 + d] = tV[d];
     }
     double* h = P.hdr + (size_t)c.slot * 4;
-    h[0] = m;
-    h[1] = Z;
-    h[2] = S;
-    h[3] = q0;
+    stg(h + 0, m);
+    stg(h + 1, Z);
+    stg(h + 2, S);
+    stg(h + 3, q0);
   }
   __syncthreads();
 }
 
 // Gradient waves: nb + 3 pipeline steps + 1 item-end barrier, then the partial.
-template <typename T, int APTG>
+template <typename T, int NGW, int APTG>
 __device__ __forceinline__ void e2_grad(const E2Item<T>& c, int gw, int lane_in) {
   const int lane = opaque(lane_in);
   using part_t = typename Part2<T>::type;
   using uacc = typename UAcc<T>::type;
   const int n_pad = c.n_pad;
+  constexpr int kGL = 64 * NGW;   // gradient lanes
   const int gidx = gw * 64 + lane;
   uacc U[3][APTG];
   double V[3][APTG];
@@ -360,29 +368,28 @@ __device__ __forceinline__ void e2_grad(const E2Item<T>& c, int gw, int lane_in)
         const int i = i0 + b;
         const T* la = c.A + (size_t)i * c.lm_elems;
         const double* cap = c.P->ca + (size_t)i * 3;
-        const T ch0 = (T)cap[0], ch1 = (T)cap[1], ch2 = (T)cap[2];
+        const T ch0 = (T)ldg(cap + 0), ch1 = (T)ldg(cap + 1), ch2 = (T)ldg(cap + 2);
         const int gio = opaque(gidx);   // per-landmark address arithmetic, not hoisted
-        // Atoms in chunks of kGC: the scheduling barrier keeps the loads of one
-        // chunk in flight at a time, bounding the registers they occupy.
-        constexpr int kGC = 4;
+        // All of this lane's atoms of the landmark are loaded before use so
+        // their cache round trips overlap.
+        T a[3][APTG];
 #pragma unroll
-        for (int k0 = 0; k0 < APTG; k0 += kGC) {
+        for (int k = 0; k < APTG; ++k) {
+          const int j = gio + kGL * k;
+          const bool in = j < n_pad;
+          a[0][k] = in ? ldg(la + j) : ch0;
+          a[1][k] = in ? ldg(la + n_pad + j) : ch1;
+          a[2][k] = in ? ldg(la + 2 * n_pad + j) : ch2;
+        }
 #pragma unroll
-          for (int k = k0; k < (k0 + kGC < APTG ? k0 + kGC : APTG); ++k) {
-            const int j = gio + 256 * k;
-            if (j < n_pad) {
-              const T a0 = la[j] - ch0;
-              const T a1 = la[n_pad + j] - ch1;
-              const T a2 = la[2 * n_pad + j] - ch2;
+        for (int k = 0; k < APTG; ++k) {
+          const T a0 = a[0][k] - ch0, a1 = a[1][k] - ch1, a2 = a[2][k] - ch2;
 #pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                const T rr = fma(Rt[d * 3 + 0], a0, fma(Rt[d * 3 + 1], a1, Rt[d * 3 + 2] * a2));
-                U[d][k] = fma(alf, (uacc)rr, U[d][k]);
-                V[d][k] = fma(be, (double)rr, V[d][k]);
-              }
-            }
+          for (int d = 0; d < 3; ++d) {
+            const T rr = fma(Rt[d * 3 + 0], a0, fma(Rt[d * 3 + 1], a1, Rt[d * 3 + 2] * a2));
+            U[d][k] = fma(alf, (uacc)rr, U[d][k]);
+            V[d][k] = fma(be, (double)rr, V[d][k]);
           }
-          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -393,18 +400,18 @@ __device__ __forceinline__ void e2_grad(const E2Item<T>& c, int gw, int lane_in)
   double* pv = partial_v<part_t>(c.P->vec, c.slot, n_pad);
 #pragma unroll
   for (int k = 0; k < APTG; ++k) {
-    const int j = gidx + 256 * k;
+    const int j = gidx + kGL * k;
     if (j < n_pad) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        pu[(size_t)d * n_pad + j] = (part_t)((double)U[d][k] - c.misc[3 + d]);
-        pv[(size_t)d * n_pad + j] = V[d][k] - c.misc[6 + d];
+        stg(pu + (size_t)d * n_pad + j, (part_t)((double)U[d][k] - c.misc[3 + d]));
+        stg(pv + (size_t)d * n_pad + j, V[d][k] - c.misc[6 + d]);
       }
     }
   }
 }
 
-template <typename T, int APTC, int APTG>
+template <typename T, int NCW, int APTC, int APTG>
 __global__ __launch_bounds__(kWG2) void engine2_kernel(const Problem* __restrict__ probs,
                                                        const Item* __restrict__ items,
                                                        const int* __restrict__ wg_off, int mode,
@@ -440,19 +447,19 @@ __global__ __launch_bounds__(kWG2) void engine2_kernel(const Problem* __restrict
     c.q0 = c.P->q[item.i0];
     c.lm_elems = (size_t)3 * c.n_pad;
     c.A = (const T*)c.P->A;
-    if (wave == 0) e2_solve<T>(c, lane);
-    else if (wave <= kCW) e2_corr<T, APTC>(c, wave - 1, lane);
-    else e2_grad<T, APTG>(c, wave - 1 - kCW, lane);
+    if (wave == 0) e2_solve<T, NCW>(c, lane);
+    else if (wave <= NCW) e2_corr<T, NCW, APTC>(c, wave - 1, lane);
+    else e2_grad<T, 7 - NCW, APTG>(c, wave - 1 - NCW, lane);
     __syncthreads();   // LDS is reused by the next item
   }
 }
 
-#define PCV_ENGINE2_CASES_F32(X) X(4, 2) X(8, 4) X(16, 8) X(27, 20)
-#define PCV_ENGINE2_CASES_F64(X) X(4, 2) X(8, 4) X(16, 8)
+#define PCV_ENGINE2_CASES_F32(X) X(3, 4, 2) X(3, 8, 4) X(3, 16, 8) X(2, 40, 16)
+#define PCV_ENGINE2_CASES_F64(X) X(3, 4, 2) X(3, 8, 4) X(3, 16, 8)
 
-void engine2_configs(bool fp64, int* aptc, int* aptg, int* count) {
+void engine2_configs(bool fp64, int* ncw, int* aptc, int* aptg, int* count) {
   int k = 0;
-#define PCV_CASE(C, G) { aptc[k] = C; aptg[k] = G; ++k; }
+#define PCV_CASE(W, C, G) { ncw[k] = W; aptc[k] = C; aptg[k] = G; ++k; }
   if (fp64) { PCV_ENGINE2_CASES_F64(PCV_CASE) }
   else { PCV_ENGINE2_CASES_F32(PCV_CASE) }
 #undef PCV_CASE
@@ -461,14 +468,14 @@ void engine2_configs(bool fp64, int* aptc, int* aptg, int* count) {
 
 hipError_t engine2_init_attributes() {
   hipError_t e = hipSuccess;
-#define PCV_CASE_T(T, C, G)                                                                   \
+#define PCV_CASE_T(T, W, C, G)                                                                \
   {                                                                                           \
-    hipError_t r = hipFuncSetAttribute((const void*)engine2_kernel<T, C, G>,                 \
+    hipError_t r = hipFuncSetAttribute((const void*)engine2_kernel<T, W, C, G>,              \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); \
     if (r != hipSuccess) e = r;                                                               \
   }
-#define PCV_CASE_F(C, G) PCV_CASE_T(float, C, G)
-#define PCV_CASE_D(C, G) PCV_CASE_T(double, C, G)
+#define PCV_CASE_F(W, C, G) PCV_CASE_T(float, W, C, G)
+#define PCV_CASE_D(W, C, G) PCV_CASE_T(double, W, C, G)
   PCV_ENGINE2_CASES_F32(PCV_CASE_F)
   PCV_ENGINE2_CASES_F64(PCV_CASE_D)
 #undef PCV_CASE_F
@@ -478,12 +485,12 @@ hipError_t engine2_init_attributes() {
 }
 
 template <typename T>
-hipError_t launch_engine2(int aptc, int aptg, int grid, size_t lds, int lbuf_bytes, int bmax,
+hipError_t launch_engine2(int ncw, int aptc, int aptg, int grid, size_t lds, int lbuf_bytes, int bmax,
                           const Problem* probs, const Item* items, const int* wg_off, int mode,
                           const int* flag, int run_if, double* dout, hipStream_t st) {
-#define PCV_CASE(C, G)                                                                        \
-  if (aptc == C && aptg == G) {                                                               \
-    hipLaunchKernelGGL((engine2_kernel<T, C, G>), dim3(grid), dim3(kWG2), lds, st, probs,     \
+#define PCV_CASE(W, C, G)                                                                     \
+  if (ncw == W && aptc == C && aptg == G) {                                                   \
+    hipLaunchKernelGGL((engine2_kernel<T, W, C, G>), dim3(grid), dim3(kWG2), lds, st, probs,  \
                        items, wg_off, mode, flag, run_if, dout, lbuf_bytes, bmax);            \
     return hipGetLastError();                                                                 \
   }
@@ -493,9 +500,9 @@ hipError_t launch_engine2(int aptc, int aptg, int grid, size_t lds, int lbuf_byt
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_engine2<float>(int, int, int, size_t, int, int, const Problem*, const Item*,
+template hipError_t launch_engine2<float>(int, int, int, int, size_t, int, int, const Problem*, const Item*,
                                           const int*, int, const int*, int, double*, hipStream_t);
-template hipError_t launch_engine2<double>(int, int, int, size_t, int, int, const Problem*, const Item*,
+template hipError_t launch_engine2<double>(int, int, int, int, size_t, int, int, const Problem*, const Item*,
                                            const int*, int, const int*, int, double*, hipStream_t);
 
 }  // namespace pcv

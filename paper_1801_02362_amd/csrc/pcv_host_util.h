@@ -76,18 +76,24 @@ inline bool e2_lds_ok(int n_pad, int B, bool fp64) {
 
 // Lanes per landmark in the correlation stage: the smallest group that holds
 // n_pad atoms within aptc per lane, preferring no more groups than landmarks
-// per batch.  0 if none fits.
-inline int e2_group(int n_pad, int aptc, int B) {
-  const int gs[4] = {16, 32, 64, 192};
+// per batch (64 * ncw = all correlation lanes).  0 if none fits.
+inline int e2_group(int n_pad, Engine2Cfg c, int B) {
+  const int full = 64 * c.ncw;
+  const int gs[4] = {16, 32, 64, full};
   int first = 0;
   for (int g : gs) {
-    if ((n_pad + g - 1) / g > aptc) continue;
+    if ((n_pad + g - 1) / g > c.aptc) continue;
     if (first == 0) first = g;
-    if (192 / g <= B) return g;
+    if (full / g <= B) return g;
   }
   return first;
 }
 
-inline bool e2_fits(int n_pad, Engine2Cfg c) { return (n_pad + 255) / 256 <= c.aptg; }
+inline bool e2_group_ok(int g, Engine2Cfg c) { return g == 16 || g == 32 || g == 64 || g == 64 * c.ncw; }
+
+inline bool e2_fits(int n_pad, Engine2Cfg c) {
+  const int gl = 64 * (7 - c.ncw);
+  return (n_pad + gl - 1) / gl <= c.aptg;
+}
 
 }  // namespace pcv

@@ -45,6 +45,18 @@ struct Item {
   int prob, i0, i1, slot;
 };
 
+// Global-memory access through an explicit address space: descriptor
+// pointers are generic, and without this the compiler emits flat loads, which
+// also occupy the LDS counter and serialise LDS waits behind HBM loads.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *((const __attribute__((address_space(1))) T*)p);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *((__attribute__((address_space(1))) T*)p) = v;
+}
+
 // Partial accumulators of one work item: U = sum e (q - q0) r in the
 // coordinate type, V = sum e r in FP64 (the merge multiplies V by q0 - s).
 template <typename T>
@@ -107,8 +119,10 @@ struct EngineCfg {
   int apt;   // atoms per thread
 };
 
-// Split-role engine instantiation: atoms per correlation lane / gradient lane.
+// Split-role engine instantiation: correlation waves (the other 7 - ncw
+// non-solver waves do gradients), atoms per correlation lane / gradient lane.
 struct Engine2Cfg {
+  int ncw;
   int aptc;
   int aptg;
 };
@@ -139,10 +153,10 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);
 
 template <typename T>
-hipError_t launch_engine2(int aptc, int aptg, int grid, size_t lds, int lbuf_bytes, int bmax,
+hipError_t launch_engine2(int ncw, int aptc, int aptg, int grid, size_t lds, int lbuf_bytes, int bmax,
                           const Problem* probs, const Item* items, const int* wg_off, int mode,
                           const int* flag, int run_if, double* dout, hipStream_t st);
-void engine2_configs(bool fp64, int* aptc, int* aptg, int* count);
+void engine2_configs(bool fp64, int* ncw, int* aptc, int* aptg, int* count);
 hipError_t engine2_init_attributes();
 size_t engine2_lds_bytes(size_t lbuf, int bmax);
 

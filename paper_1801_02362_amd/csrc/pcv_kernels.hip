@@ -586,13 +586,13 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
 template <int BS>
 __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, double& S) {
   double ml = INFINITY;
-  for (int g = threadIdx.x; g < P.n_slots; g += BS) ml = fmin(ml, P.hdr[(size_t)g * 4]);
+  for (int g = threadIdx.x; g < P.n_slots; g += BS) ml = fmin(ml, ldg(P.hdr + (size_t)g * 4));
   m = block_min<BS>(ml, sh);
   double v[2] = {0.0, 0.0};
   for (int g = threadIdx.x; g < P.n_slots; g += BS) {
-    const double f = scale_to(P.hdr[(size_t)g * 4], m, P.lam);
-    v[0] = fma(f, P.hdr[(size_t)g * 4 + 1], v[0]);
-    v[1] = fma(f, P.hdr[(size_t)g * 4 + 2], v[1]);
+    const double f = scale_to(ldg(P.hdr + (size_t)g * 4), m, P.lam);
+    v[0] = fma(f, ldg(P.hdr + (size_t)g * 4 + 1), v[0]);
+    v[1] = fma(f, ldg(P.hdr + (size_t)g * 4 + 2), v[1]);
   }
   block_sum<2, BS>(v, sh);
   Z = v[0];
@@ -632,8 +632,8 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
     if (j < n_pad) {
 #pragma unroll 4
       for (int t = 0; t < gn; ++t) {
-        const double u = (double)partial_u<acc>(P.vec, g0 + t, n_pad)[(size_t)c * n_pad + j];
-        const double v = partial_v<acc>(P.vec, g0 + t, n_pad)[(size_t)c * n_pad + j];
+        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = fq[0][t];
         gs = fma(f, fma(fq[1][t], v, u), gs);
         gz = fma(f, v, gz);
@@ -692,8 +692,8 @@ __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __rest
     if (col < ncol) {
       const int c = col / n_pad, j = col - c * n_pad;
       for (int g = grp; g < ns; g += 8) {
-        const double u = (double)partial_u<acc>(P.vec, g, n_pad)[(size_t)c * n_pad + j];
-        const double v = partial_v<acc>(P.vec, g, n_pad)[(size_t)c * n_pad + j];
+        const double u = (double)ldg(partial_u<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg(partial_v<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + j);
         su = fma(fq[0][g], fma(fq[1][g], v, u), su);
         sv = fma(fq[0][g], v, sv);
       }

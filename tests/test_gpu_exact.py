@@ -92,16 +92,16 @@ def _plans(n, wg_apt, e2):
             out.append(dict(engine=1, wg=wg, apt=apt, team=ts))
             ts *= 4
     n_pad = (n + 63) // 64 * 64
-    for aptc, aptg in e2:
-        for g in (16, 32, 64, 192):
-            if -(-n_pad // g) <= aptc and -(-n_pad // 256) <= aptg:
+    for ncw, aptc, aptg in e2:
+        for g in (16, 32, 64, 64 * ncw):
+            if -(-n_pad // g) <= aptc and -(-n_pad // (64 * (7 - ncw))) <= aptg:
                 for batch in (1, 5, 13):
                     out.append(dict(engine=2, wg=512, apt=aptc, team=g, aptg=aptg, batch=batch))
     return out
 
 
 @pytest.mark.parametrize("plan", _plans(300, [(256, 1), (256, 2), (256, 4), (256, 8), (512, 8), (512, 10), (512, 16)],
-                                        [(4, 2), (8, 4), (16, 8), (27, 20)]))
+                                        [(3, 4, 2), (3, 8, 4), (3, 16, 8), (2, 40, 16)]))
 def test_every_tiling_matches(torch, plan):
     from gpu_util import TOL32
     sysm, frames = wl.cfg1(3000)
