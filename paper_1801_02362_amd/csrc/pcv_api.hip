@@ -21,6 +21,8 @@ namespace {
 constexpr int kMaxAtomsF32 = 512 * 16;
 constexpr int kMaxAtomsF64 = 256 * 8;
 constexpr int kMaxCloseSlots = 2048;
+// Smallest structure (padded atoms) for which engine 3 is the default.
+constexpr int kEngine3MinAtoms = 1024;
 
 struct Plan {
   int engine = 1;
@@ -28,6 +30,7 @@ struct Plan {
   int ts = 16;
   Engine2Cfg c2{0, 0};      // engine 2
   int g = 0, B = 1, lbuf = 0;
+  int bpw = 0;              // engine 3: 256-atom blocks per worker wave
   int grid = 0;
   int n_items = 0;
   size_t lds = 0;
@@ -51,6 +54,8 @@ struct pcv_handle {
   double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr;
   // frame
   double* xw = nullptr;
+  float* xw32 = nullptr;   // FP32 handles: [3][n_x] copy of xw for engine 3
+  int n_x = 0;
   double* Gx = nullptr;
   double* Gx32 = nullptr;
   double* xres = nullptr;
@@ -167,10 +172,10 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
 static pcv_status build_plan(pcv_handle* h) {
   Plan& p = h->plan;
   // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
-  const int unit = (p.engine == 2) ? p.B : p.cfg.wg / p.ts;
+  const int unit = (p.engine == 2) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
   const int units = (h->L + unit - 1) / unit;
   if (!h->user_plan || p.n_items <= 0) {
-    const int cap = (p.engine == 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
+    const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
     p.n_items = std::max(1, std::min(units, cap));
   }
   p.n_items = std::min(p.n_items, units);
@@ -179,6 +184,8 @@ static pcv_status build_plan(pcv_handle* h) {
   if (p.engine == 2) {
     p.lbuf = p.B * 3 * h->n_pad * (h->fp64 ? 8 : 4);
     p.lds = engine2_lds_bytes((size_t)p.lbuf, p.B);
+  } else if (p.engine == 3) {
+    p.lds = 0;   // static LDS
   } else {
     p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
   }
@@ -191,6 +198,8 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prep, sizeof(PrepArgs)));
   PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, h->counters, h->n, h->n_pad, h->L};
+  pa.xw32 = h->xw32;
+  pa.n_x = h->n_x;
   HIP_TRY(h, hipMemcpy(h->d_prep, &pa, sizeof(pa), hipMemcpyHostToDevice));
   std::vector<Item> items(p.n_items);
   std::vector<int> wgoff(p.grid + 1);
@@ -229,6 +238,8 @@ static pcv_status build_plan(pcv_handle* h) {
   base.out_off = 0;
   base.out_idx = 0;
   base.lam = h->lam;
+  base.xw32 = h->xw32;
+  base.n_x = h->n_x;
   Problem probs[3] = {base, base, base};
   HIP_TRY(h, hipMemcpy(h->d_prob, probs, sizeof(probs), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
@@ -259,9 +270,30 @@ static bool default_plan2(pcv_handle* h) {
   return false;
 }
 
+// Engine 3 for large FP32 structures: every worker wave owns at most bpw
+// blocks of 256 atoms.
+static int e3_bpw_for(int n_pad) {
+  const int nblk = (n_pad + 255) / 256;
+  for (int bpw = 1; bpw <= 3; ++bpw)
+    if (nblk <= engine3_max_blocks(bpw)) return bpw;
+  return 0;
+}
+
+static bool default_plan3(pcv_handle* h) {
+  if (h->fp64 || h->n_pad < kEngine3MinAtoms) return false;
+  const int bpw = e3_bpw_for(h->n_pad);
+  if (bpw == 0) return false;
+  h->plan.engine = 3;
+  h->plan.bpw = bpw;
+  h->plan.cfg = EngineCfg{512, 4 * bpw};
+  h->plan.ts = 0;
+  return true;
+}
+
 static void default_plan(pcv_handle* h) {
   h->plan.n_items = 0;
   h->user_plan = false;
+  if (default_plan3(h)) return;
   if (default_plan2(h)) return;
   h->plan.engine = 1;
   EngineCfg menu[16];
@@ -324,6 +356,12 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->q, L * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->w, np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->xw, 3 * np * sizeof(double)));
+  h->n_x = round_up(h->n_pad, 256);
+  h->xw32 = nullptr;
+  if (!h->fp64) {
+    HIP_TRY(h, m.alloc((void**)&h->xw32, 3 * (size_t)h->n_x * sizeof(float)));
+    HIP_TRY(h, hipMemset(h->xw32, 0, 3 * (size_t)h->n_x * sizeof(float)));
+  }
   HIP_TRY(h, m.alloc((void**)&h->Gx, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gx32, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->xres, 3 * sizeof(double)));
@@ -406,10 +444,14 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
     (void)hipEventRecord(e0, st);
   }
   const Plan& p = h->plan;
-  hipError_t e = (p.engine == 2)
-      ? launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
-                          h->d_wgoff, mode, flag, run_if, msd, st)
-      : launch_engine<T>(p.cfg, p.grid, p.lds, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if,
+  hipError_t e;
+  if (p.engine == 3)
+    e = launch_engine3<T>(p.bpw, p.grid, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if, msd, st);
+  else if (p.engine == 2)
+    e = launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
+                          h->d_wgoff, mode, flag, run_if, msd, st);
+  else
+    e = launch_engine<T>(p.cfg, p.grid, p.lds, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if,
                          msd, st);
   if (h->timing) {
     (void)hipEventRecord(e1, st);
@@ -433,6 +475,8 @@ template <typename T>
 static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
                                 void* dz, double* msd, int* rec) {
   PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, nullptr, h->n, h->n_pad, h->L};
+  pa.xw32 = h->xw32;
+  pa.n_x = h->n_x;
   CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
                h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
   Outs o{ds, dz, sz, rec};
@@ -567,9 +611,9 @@ extern "C" pcv_status pcv_get_plan(pcv_handle* h, pcv_plan* out) {
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   const Plan& p = h->plan;
   out->engine = p.engine;
-  out->wg = p.engine == 2 ? 512 : p.cfg.wg;
-  out->apt = p.engine == 2 ? p.c2.aptc : p.cfg.apt;
-  out->team = p.engine == 2 ? p.g : p.ts;
+  out->wg = p.engine >= 2 ? 512 : p.cfg.wg;
+  out->apt = p.engine == 2 ? p.c2.aptc : (p.engine == 3 ? 4 * p.bpw : p.cfg.apt);
+  out->team = p.engine == 2 ? p.g : (p.engine == 3 ? 0 : p.ts);
   out->aptg = p.engine == 2 ? p.c2.aptg : 0;
   out->batch = p.engine == 2 ? p.B : 0;
   out->grid = p.grid;
@@ -607,8 +651,18 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
     p.B = q->batch;
     p.cfg = EngineCfg{512, c.aptc};
     p.ts = g;
+  } else if (q->engine == 3) {
+    if (h->fp64) return fail(h, PCV_EUNSUPPORTED, "engine 3 is FP32 only");
+    const int bpw = q->apt / 4;
+    if (q->apt % 4 != 0 || bpw < 1 || bpw > 3) return fail(h, PCV_EUNSUPPORTED, "engine 3 needs apt = 4, 8 or 12");
+    if ((h->n_pad + 255) / 256 > engine3_max_blocks(bpw))
+      return fail(h, PCV_EINVAL, "engine 3 tiling cannot hold the structure");
+    p.engine = 3;
+    p.bpw = bpw;
+    p.cfg = EngineCfg{512, 4 * bpw};
+    p.ts = 0;
   } else {
-    return fail(h, PCV_EINVAL, "engine must be 1 or 2");
+    return fail(h, PCV_EINVAL, "engine must be 1, 2 or 3");
   }
   p.n_items = q->items;
   HIP_TRY(h, hipStreamSynchronize(h->stream));

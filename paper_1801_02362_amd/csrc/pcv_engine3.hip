@@ -1,0 +1,477 @@
+// Streaming landmark engine for large structures on gfx950 (FP32 coordinates).
+//
+// One 512-thread workgroup per CU: seven worker waves and one solver wave.
+// The atoms are cut into blocks of 256 (64 lanes x 4 atoms); worker wave w
+// owns blocks w, w + 7, w + 14 (at most BPW of them) for every landmark of
+// its work item, so each worker keeps its atoms' share of the centred,
+// weighted structure in registers and streams only its own coordinates:
+//
+//   * a private ring of NS landmark slots in LDS is filled by asynchronous
+//     HBM -> LDS copies (global_load_lds_dwordx4, 16 B per lane); a wave
+//     waits only for the oldest slot (partial vmcnt), so NS - 1 landmarks
+//     stay in flight across the pipeline barriers;
+//   * the landmark is read from its slot into registers once; it feeds the
+//     correlation M = sum_j a_j (w_j x_j)^T (FP64 accumulation) at once and
+//     the gradient one step later, when the rotation is known;
+//   * per step (landmark t): phase A = correlation of t in the workers while
+//     the solver wave solves the quaternion eigenproblem of t - 1 (Section 3)
+//     and folds it into the running log-sum-exp (Eq. 2); phase B = gradient
+//     contributions of t - 1, U += e (q - q0) R (a - c) in FP32 and
+//     V += e R (a - c) in FP64, with R read from LDS.
+//
+// Workers reduce their 9 correlation sums over each 16-lane row with DPP
+// moves; the solver adds the 4 x 7 row sums in a fixed order, so results do
+// not depend on timing.  Each work item writes one partial (m, Z, S, q0, U, V)
+// in the format of the other engines, so the merge kernels are shared.
+//
+// Synchronisation: the copies are the only vector-memory operations the
+// workers issue inside the landmark loop, so "wait until at most k copy
+// instructions are outstanding" is an exact per-slot wait.  Barriers wait on
+// LDS traffic only (the compiler's workgroup barrier would also drain the
+// copies in flight), and slot reads are inline assembly that waits for its
+// own results, so the compiler never adds a full vmcnt wait in front of them.
+#include "pcv_internal.h"
+#include "pcv_math.h"
+
+namespace pcv {
+
+namespace {
+
+constexpr int kWG3 = 512;
+constexpr int kWorkers3 = 7;
+constexpr int kBlk3 = 256;                      // atoms per block: 64 lanes x 4
+constexpr int kBlkFloats3 = 3 * kBlk3;          // one block of one landmark (x, y, z planes)
+
+// Copy-ring depth (block slots per worker wave) for BPW blocks per wave: the
+// ring and the wave's FP32 structure share about 150 KB of LDS.
+constexpr int ring_slots(int bpw) { return bpw >= 3 ? 4 : (bpw == 2 ? 5 : 6); }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__shared__ double e3_part[2][kWorkers3 * 4][9];
+__shared__ double e3_res[16];
+__shared__ double e3_misc[16];
+
+// LDS-only workgroup barrier (the copies in flight are not waited for).
+__device__ __forceinline__ void bar3() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait until at most n vector-memory instructions of this wave are
+// outstanding (n a multiple of 3, at most 15).
+__device__ __forceinline__ void wait_vm(int n) {
+#define PCV_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | 0x0F70)
+  switch (n) {
+    case 0: PCV_VM(0); break;
+    case 3: PCV_VM(3); break;
+    case 6: PCV_VM(6); break;
+    case 9: PCV_VM(9); break;
+    case 12: PCV_VM(12); break;
+    default: PCV_VM(15); break;
+  }
+#undef PCV_VM
+}
+
+// Three 16-byte LDS reads (the x, y, z planes of one block, OFF bytes past
+// addr) that wait for their own data.
+template <int OFF>
+__device__ __forceinline__ void read_block(unsigned addr, f4v& p0, f4v& p1, f4v& p2) {
+  static_assert(OFF >= 0 && OFF + 2048 < 65536, "ds offset field");
+  asm volatile(
+      "ds_read_b128 %0, %3 offset:%4\n\t"
+      "ds_read_b128 %1, %3 offset:%5\n\t"
+      "ds_read_b128 %2, %3 offset:%6\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(p0), "=&v"(p1), "=&v"(p2)   // early clobber: results must not reuse the address register
+      : "v"(addr), "i"(OFF), "i"(OFF + 1024), "i"(OFF + 2048)
+      : "memory");
+}
+
+// Block k of a wave's structure area (k is a constant after unrolling).
+__device__ __forceinline__ void read_xblock(int k, unsigned addr, f4v& p0, f4v& p1, f4v& p2) {
+  switch (k) {
+    case 0: read_block<0>(addr, p0, p1, p2); break;
+    case 1: read_block<kBlkFloats3 * 4>(addr, p0, p1, p2); break;
+    default: read_block<2 * kBlkFloats3 * 4>(addr, p0, p1, p2); break;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over each row of 16 lanes (every lane of the row receives it).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double clamp0_3(double v) { return v < 0.0 ? 0.0 : v; }
+
+struct E3Item {
+  const Problem* P;
+  int i0, nL, slot, n_pad;
+  double lam, q0;
+};
+
+// ------------------------------------------------------------------ worker
+// ring: this wave's RS block slots; xs: this wave's BPW blocks of w_j x_j (FP32).
+template <int BPW>
+__device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, float* ring, float* xs) {
+  constexpr int RS = ring_slots(BPW);
+  const int n_pad = c.n_pad;
+  const int nblk = (n_pad + kBlk3 - 1) / kBlk3;
+  int nbw = 0;
+#pragma unroll
+  for (int k = 0; k < BPW; ++k) nbw += (w + kWorkers3 * k < nblk) ? 1 : 0;
+  const int nL = c.nL;
+  const int NB = nL * nbw;   // blocks streamed by this wave
+  const float* A = (const float*)c.P->A;
+  const unsigned ring_addr = (unsigned)(size_t)((__attribute__((address_space(3))) float*)ring) + lane * 16;
+
+  // Copy stream: block b = t * nbw + k of this wave (landmark t, block w + 7k).
+  int it_t = 0, it_k = 0, it_slot = 0, issued = 0;
+  auto issue_next = [&]() {
+    const int j0 = (w + kWorkers3 * it_k) * kBlk3 + lane * 4;
+    const int jj = j0 < n_pad ? j0 : 0;   // lanes past the structure copy in-bounds data (x = 0 there)
+    const float* src = A + (size_t)(c.i0 + it_t) * 3 * n_pad + jj;
+    float* dst = ring + it_slot * kBlkFloats3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)d * n_pad),
+                                       (__attribute__((address_space(3))) void*)(dst + d * kBlk3), 16, 0, 0);
+    if (++it_k == nbw) { it_k = 0; ++it_t; }
+    if (++it_slot == RS) it_slot = 0;
+    ++issued;
+  };
+  // This lane's atoms j = (w + 7k) * 256 + 4 lane + e of w_j x_c,j (FP32,
+  // zero past the structure) go to the wave's LDS area through registers
+  // before any copy is issued.
+  {
+    const int n_x = c.P->n_x;
+    const float* xsrc = c.P->xw32;
+    f4v xv[BPW][3];
+#pragma unroll
+    for (int k = 0; k < BPW; ++k) {
+      if (k < nbw) {
+        const int j0 = (w + kWorkers3 * k) * kBlk3 + lane * 4;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xv[k][d] = ldg(reinterpret_cast<const f4v*>(xsrc + (size_t)d * n_x + j0));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < BPW; ++k) {
+      if (k < nbw) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) *reinterpret_cast<f4v*>(xs + (k * 3 + d) * kBlk3 + lane * 4) = xv[k][d];
+      }
+    }
+  }
+  const unsigned xs_addr = (unsigned)(size_t)((__attribute__((address_space(3))) float*)xs) + lane * 16;
+  for (int b = 0; b < RS && b < NB; ++b) issue_next();
+
+  float U[BPW][3][4];
+  double V[BPW][3][4];
+#pragma unroll
+  for (int k = 0; k < BPW; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { U[k][d][e] = 0.f; V[k][d][e] = 0.0; }
+
+  float a0[BPW][3][4], a1[BPW][3][4];
+  int rd_slot = 0, consumed = 0;
+
+  // One pipeline step: landmark t into `cur` + correlation (phase A), then
+  // gradient of t - 1 from `prev` (phase B).
+  auto step = [&](int t, float (&cur)[BPW][3][4], float (&prev)[BPW][3][4]) {
+    if (t < nL) {
+      double M[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) M[q] = 0.0;
+#pragma unroll
+      for (int k = 0; k < BPW; ++k) {
+        if (k < nbw) {
+          wait_vm(3 * (issued - consumed - 1));
+          f4v p0, p1, p2;
+          read_block<0>(ring_addr + (unsigned)(rd_slot * kBlkFloats3 * 4), p0, p1, p2);
+          ++consumed;
+          if (++rd_slot == RS) rd_slot = 0;
+          if (issued < NB) issue_next();
+          f4v x0, x1, x2;
+          read_xblock(k, xs_addr, x0, x1, x2);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            cur[k][0][e] = p0[e]; cur[k][1][e] = p1[e]; cur[k][2][e] = p2[e];
+            const double y0 = x0[e], y1 = x1[e], y2 = x2[e];
+            const double b0 = p0[e], b1 = p1[e], b2 = p2[e];
+            M[0] = fma(b0, y0, M[0]); M[1] = fma(b0, y1, M[1]); M[2] = fma(b0, y2, M[2]);
+            M[3] = fma(b1, y0, M[3]); M[4] = fma(b1, y1, M[4]); M[5] = fma(b1, y2, M[5]);
+            M[6] = fma(b2, y0, M[6]); M[7] = fma(b2, y1, M[7]); M[8] = fma(b2, y2, M[8]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) M[q] = row_sum16(M[q]);
+      if ((lane & 15) == 0) {
+        double* pp = e3_part[t & 1][w * 4 + (lane >> 4)];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pp[q] = M[q];
+      }
+    }
+    bar3();
+    if (t >= 1) {
+      const double sc = e3_res[11];
+      if (sc != 1.0) {
+        const float scf = (float)sc;
+#pragma unroll
+        for (int k = 0; k < BPW; ++k)
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { U[k][d][e] *= scf; V[k][d][e] *= sc; }
+      }
+      float Rt[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Rt[q] = (float)e3_res[q];
+      const float alf = (float)e3_res[9];
+      const double be = e3_res[10];
+      const float ch0 = (float)e3_res[12], ch1 = (float)e3_res[13], ch2 = (float)e3_res[14];
+#pragma unroll
+      for (int k = 0; k < BPW; ++k) {
+        if (k < nbw) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float b0 = prev[k][0][e] - ch0, b1 = prev[k][1][e] - ch1, b2 = prev[k][2][e] - ch2;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float r = fmaf(Rt[d * 3 + 0], b0, fmaf(Rt[d * 3 + 1], b1, Rt[d * 3 + 2] * b2));
+              U[k][d][e] = fmaf(alf, r, U[k][d][e]);
+              V[k][d][e] = fma(be, (double)r, V[k][d][e]);
+            }
+          }
+        }
+      }
+    }
+    bar3();
+  };
+
+  for (int t = 0; t <= nL; t += 2) {
+    step(t, a0, a1);
+    if (t + 1 <= nL) step(t + 1, a1, a0);
+  }
+
+  bar3();   // item totals published by the solver
+  float* pu = partial_u<float>(c.P->vec, c.slot, n_pad);
+  double* pv = partial_v<float>(c.P->vec, c.slot, n_pad);
+  double mu[3], mv[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) { mu[d] = e3_misc[3 + d]; mv[d] = e3_misc[6 + d]; }
+#pragma unroll
+  for (int k = 0; k < BPW; ++k) {
+    if (k < nbw) {
+      const int j0 = (w + kWorkers3 * k) * kBlk3 + lane * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (j0 + e < n_pad) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            stg(pu + (size_t)d * n_pad + j0 + e, (float)((double)U[k][d][e] - mu[d]));
+            stg(pv + (size_t)d * n_pad + j0 + e, V[k][d][e] - mv[d]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ solver
+__device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, double* dout) {
+  const Problem& P = *c.P;
+  const double lam = c.lam, q0 = c.q0;
+  const int nL = c.nL;
+  const double Gxx = ldg(P.Gx32);
+  double xres[3], Rx[9];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xres[d] = ldg(P.xres + d);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rx[k] = (mode == MODE_APPROX) ? ldg(P.Rxy + k) : 0.0;
+  double m = INFINITY, Z = 0.0, S = 0.0, tU[3] = {0.0, 0.0, 0.0}, tV[3] = {0.0, 0.0, 0.0};
+  // Per-landmark inputs, fetched one step ahead of use.
+  auto fetch = [&](int t, double cap[3], double& Ga, double& qi, double Rs[9]) {
+    const int i = c.i0 + (t < nL ? t : nL - 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cap[d] = ldg(P.ca + (size_t)i * 3 + d);
+    Ga = ldg(P.Ga + i);
+    qi = ldg(P.q + i);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rs[k] = (mode == MODE_APPROX) ? ldg(P.Rsave + (size_t)i * 9 + k) : 0.0;
+  };
+  double cap[3], Ga = 0.0, qi = 0.0, Rs[9];
+  if (nL > 0) fetch(0, cap, Ga, qi, Rs);
+  for (int t = 0; t <= nL; ++t) {
+    if (t >= 1) {
+      const int i = c.i0 + t - 1;
+      const double cc[3] = {cap[0], cap[1], cap[2]};
+      const double Gai = Ga, qv = qi;
+      double Rsv[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rsv[k] = Rs[k];
+      if (t < nL) fetch(t, cap, Ga, qi, Rs);
+      // Correlation of landmark t - 1: 28 row sums added in a fixed order.
+      double ssum = 0.0;
+      if (lane < 9) {
+        const double(*pp)[9] = e3_part[(t - 1) & 1];
+        for (int p = 0; p < kWorkers3 * 4; ++p) ssum += pp[p][lane];
+      }
+      double Mc[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Mc[k] = __shfl(ssum, k, 64);
+      // The workers used w_j x_j rounded to FP32, whose sum (xres) is not
+      // exactly zero; remove its coupling to the landmark centroid.
+#pragma unroll
+      for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+        for (int c0 = 0; c0 < 3; ++c0) Mc[r0 * 3 + c0] = fma(-cc[r0], xres[c0], Mc[r0 * 3 + c0]);
+      double D, R[9];
+      if (mode == MODE_APPROX) {
+        double tr = 0.0;
+#pragma unroll
+        for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+          for (int c0 = 0; c0 < 3; ++c0) {
+            const double rt = Rx[c0 * 3 + 0] * Rsv[0 * 3 + r0] + Rx[c0 * 3 + 1] * Rsv[1 * 3 + r0] +
+                              Rx[c0 * 3 + 2] * Rsv[2 * 3 + r0];
+            tr = fma(rt, Mc[r0 * 3 + c0], tr);
+          }
+        D = clamp0_3(Gxx + Gai - 2.0 * tr);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = Rsv[k];
+      } else {
+        double F[10], lmax, qq[4];
+        const int fb = top_eigenpair(Mc, 0.5 * (Gxx + Gai), F, lmax, qq);
+        if (fb && lane == 0 && P.fallbacks) atomicAdd((unsigned long long*)P.fallbacks, 1ull);
+        D = clamp0_3(Gxx + Gai - 2.0 * lmax);
+        quat_to_rot(qq, R);
+        if (mode == MODE_EXACT_SAVE) {
+          double rv = 0.0;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) rv = (lane == q) ? R[q] : rv;
+          if (lane < 9) stg(P.Rsave + (size_t)i * 9 + lane, rv);
+        }
+      }
+      if (dout != nullptr && lane == 0) stg(dout + i, D);
+      const double mn = fmin(m, D);
+      const double sc = (m == INFINITY) ? 0.0 : ((mn == m) ? 1.0 : exp(-lam * (m - mn)));
+      const double e = exp(-lam * (D - mn));
+      const double al = e * (qv - q0);
+      Z = Z * sc + e;
+      S = S * sc + e * qv;
+      // Residual of the centroid split the workers use (c - (float)c).
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double c3[3] = {cc[0] - (double)(float)cc[0], cc[1] - (double)(float)cc[1],
+                              cc[2] - (double)(float)cc[2]};
+        const double rc = R[d * 3 + 0] * c3[0] + R[d * 3 + 1] * c3[1] + R[d * 3 + 2] * c3[2];
+        tU[d] = tU[d] * sc + al * rc;
+        tV[d] = tV[d] * sc + e * rc;
+      }
+      m = mn;
+      // Lane k publishes entry k (selects, not a register-array index).
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v = (lane == q) ? R[q] : v;
+      v = (lane == 9) ? al : v;
+      v = (lane == 10) ? e : v;
+      v = (lane == 11) ? sc : v;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v = (lane == 12 + d) ? cc[d] : v;
+      if (lane < 16) e3_res[lane] = v;
+    }
+    bar3();
+    bar3();
+  }
+  if (lane == 0) {
+    e3_misc[0] = m;
+    e3_misc[1] = Z;
+    e3_misc[2] = S;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      e3_misc[3 + d] = tU[d];
+      e3_misc[6 + d] = tV[d];
+    }
+    double* h = P.hdr + (size_t)c.slot * 4;
+    stg(h + 0, m);
+    stg(h + 1, Z);
+    stg(h + 2, S);
+    stg(h + 3, q0);
+  }
+  bar3();
+}
+
+}  // namespace
+
+template <int BPW>
+__global__ __launch_bounds__(kWG3) void engine3_kernel(const Problem* __restrict__ probs,
+                                                       const Item* __restrict__ items,
+                                                       const int* __restrict__ wg_off, int mode,
+                                                       const int* __restrict__ flag, int run_if,
+                                                       double* __restrict__ dout) {
+  constexpr int RS = ring_slots(BPW);
+  __shared__ float ring[kWorkers3 * RS * kBlkFloats3];
+  __shared__ float xs[kWorkers3 * BPW * kBlkFloats3];
+  if (flag != nullptr && *flag != run_if) return;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int it_end = wg_off[blockIdx.x + 1];
+  for (int it = wg_off[blockIdx.x]; it < it_end; ++it) {
+    const Item item = items[it];
+    E3Item c;
+    c.P = probs + item.prob;
+    c.i0 = item.i0;
+    c.nL = item.i1 - item.i0;
+    c.slot = item.slot;
+    c.n_pad = c.P->n_pad;
+    c.lam = c.P->lam;
+    c.q0 = c.P->q[item.i0];
+    if (wave < kWorkers3)
+      e3_worker<BPW>(c, wave, lane, ring + wave * RS * kBlkFloats3, xs + wave * BPW * kBlkFloats3);
+    else e3_solver(c, lane, mode, dout);
+    bar3();   // LDS is reused by the next item
+  }
+}
+
+int engine3_max_blocks(int bpw) { return kWorkers3 * bpw; }
+
+template <>
+hipError_t launch_engine3<float>(int bpw, int grid, const Problem* probs, const Item* items, const int* wg_off,
+                                 int mode, const int* flag, int run_if, double* dout, hipStream_t st) {
+  switch (bpw) {
+    case 1: hipLaunchKernelGGL(engine3_kernel<1>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
+                               run_if, dout); break;
+    case 2: hipLaunchKernelGGL(engine3_kernel<2>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
+                               run_if, dout); break;
+    case 3: hipLaunchKernelGGL(engine3_kernel<3>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
+                               run_if, dout); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_engine3<double>(int, int, const Problem*, const Item*, const int*, int, const int*, int, double*,
+                                  hipStream_t) {
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pcv

@@ -39,6 +39,8 @@ struct Problem {
   int out_off;          // atom offset of this problem in concatenated inputs/outputs
   int out_idx;          // index of this problem's (s, z) pair
   double lam;
+  const float* xw32;    // [3][n_x] w_j x_c,j rounded to FP32, zero past n (large-structure engine)
+  int n_x;              // plane stride of xw32: n_pad rounded up to 256
 };
 
 struct Item {
@@ -92,6 +94,8 @@ struct PrepArgs {
   int* status;      // [1]: sticky, set to 1 on non-finite input
   long long* counters;  // optional: CNT_EVALS / CNT_EXPENSIVE for Algorithm 1
   int n, n_pad, L;
+  float* xw32;          // optional: FP32 copy of xw, plane stride n_x (padding stays zero)
+  int n_x;
 };
 
 // Device-resident close-structure state (Algorithm 2).
@@ -159,6 +163,14 @@ hipError_t launch_engine2(int ncw, int aptc, int aptg, int grid, size_t lds, int
 void engine2_configs(bool fp64, int* ncw, int* aptc, int* aptg, int* count);
 hipError_t engine2_init_attributes();
 size_t engine2_lds_bytes(size_t lbuf, int bmax);
+
+// Large-structure engine (FP32 only): bpw = 256-atom blocks per worker wave
+// (1, 2 or 3; a structure may have up to 7 * bpw blocks).
+template <typename T>
+hipError_t launch_engine3(int bpw, int grid, const Problem* probs, const Item* items, const int* wg_off, int mode,
+                          const int* flag, int run_if, double* dout, hipStream_t st);
+int engine3_max_blocks(int bpw);
+
 
 bool engine_supported(EngineCfg cfg, bool fp64);
 void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu

@@ -199,6 +199,7 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
         const double xv = (double)x[3 * j + d] - c[d];
         const double xwv = wj * xv;
         a.xw[(size_t)d * a.n_pad + j] = xwv;
+        if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = (float)xwv;
         g[0] = fma(wj * xv, xv, g[0]);
         const double r = (double)(T)xwv;
         if (wj > 0.0) g[1] += r * r / wj;
@@ -206,7 +207,10 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
       }
     } else {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) a.xw[(size_t)d * a.n_pad + j] = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        a.xw[(size_t)d * a.n_pad + j] = 0.0;
+        if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = 0.f;
+      }
     }
   }
   block_sum<5, BS>(g, sh);

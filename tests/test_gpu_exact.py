@@ -110,6 +110,39 @@ def test_every_tiling_matches(torch, plan):
                name="tiling", plan=plan)
 
 
+# Large-structure engine: each compiled block count, structures that end
+# inside a 256-atom block or a 64-atom tile, and item counts from one item
+# (the whole landmark range streamed by one workgroup) to one landmark each.
+_E3_CASES = [(n, bpw, items) for n, bpws in ((100, (1, 2, 3)), (700, (1, 2, 3)), (1800, (2, 3)), (1793, (2, 3)),
+                                            (3000, (2, 3)), (3584, (2, 3)), (5000, (3,)), (5376, (3,)))
+             for bpw in bpws for items in (0, 1, 7)]
+
+
+@pytest.mark.parametrize("n,bpw,items", _E3_CASES)
+def test_engine3_tilings(torch, n, bpw, items):
+    from gpu_util import TOL32
+    L = 23
+    s = wl.small_path(n, L, 40 + n % 17, dtype=np.float32)
+    rng = np.random.default_rng(n + bpw)
+    frames = (s.waypoints[0] + rng.normal(0, 0.02, (2, n, 3))).astype(np.float32)
+    lam = landmark_lambda(s.landmarks)
+    plan = dict(engine=3, wg=512, apt=4 * bpw, team=0, aptg=0, batch=0, items=items if items else L)
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name=f"e3_{n}_{bpw}_{items}",
+               plan=plan)
+
+
+def test_engine3_rejects_structures_it_cannot_hold(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev
+    s = wl.small_path(1800, 3, 5, dtype=np.float32)
+    cv = pcv.PathCV(dev(s.landmarks, torch.float32), 10.0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=3, wg=512, apt=4, team=0, aptg=0, batch=0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=3, wg=512, apt=6, team=0, aptg=0, batch=0)
+    cv.close()
+
+
 def test_item_counts_and_graph_replay_are_bitwise_stable(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev, host
