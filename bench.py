@@ -35,10 +35,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_NAMES = {1: "engine_kernel", 2: "engine2_kernel", 3: "engine3_kernel"}
+
+
 def kernel_source_hash() -> str:
+    """Hash of every device source (the counter summary is only valid for it)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1801_02362_amd", "csrc", "pcv_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_1801_02362_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -125,7 +132,7 @@ def bench_exact(args):
     traffic = counted_traffic(f"engine_exact_{n}x{L}")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "engine_kernel (landmark streaming, exact mode)", "kernel_ms": round(kms, 5),
+            "kernel": f"{KERNEL_NAMES[cv.plan['engine']]} (landmark streaming, exact mode)", "kernel_ms": round(kms, 5),
             "algorithmic_bytes_per_launch": alg_bytes}
     out = {
         "metric": "structure-landmark MSD+grad evals/s",
@@ -231,12 +238,34 @@ def bench_batch(args):
     return out
 
 
+def bench_copy(args):
+    """Plain device-to-device copy of a known size (counter calibration)."""
+    import torch
+    nbytes = int(args.copy_mb * (1 << 20))
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"metric": "device copy bytes/s (read + write)", "value": round(2 * nbytes * args.steps / dt, 1),
+            "unit": "B/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"torch copy_ of {nbytes} bytes", "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["exact", "close", "batch"], default="exact")
+    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy"], default="exact")
+    ap.add_argument("--copy-mb", type=float, default=600.0)
     ap.add_argument("--atoms", type=int, default=5000)
     ap.add_argument("--landmarks", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -251,6 +280,8 @@ def main():
         out = bench_exact(args)
     elif args.workload == "close":
         out = bench_close(args)
+    elif args.workload == "copy":
+        out = bench_copy(args)
     else:
         out = bench_batch(args)
     print(json.dumps(out), flush=True)

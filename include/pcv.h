@@ -156,7 +156,7 @@ pcv_status pcv_reset_stats(pcv_handle* h);
 pcv_status pcv_check(pcv_handle* h);
 
 /*
- * Tiling of the landmark streaming kernel.  Two engines exist:
+ * Tiling of the landmark streaming kernel.  Three engines exist:
  *   engine 1  teams of `team` lanes, one landmark per team at a time, `apt`
  *             atoms per lane, `wg` threads per workgroup; every lane of a team
  *             takes part in the per-landmark eigen-solve.  Any n up to
@@ -167,6 +167,10 @@ pcv_status pcv_check(pcv_handle* h);
  *             `aptg` are the compiled atoms per correlation / gradient lane,
  *             `team` the lanes per landmark in the correlation stage
  *             (16, 32, 64 or 192).  Needs the landmark batch to fit in LDS.
+ *   engine 3  large FP32 structures: seven worker waves each own up to `apt`/4
+ *           blocks of 256 atoms (apt = 4, 8 or 12, so at most 7 * apt * 64
+ *           atoms) and stream them through a private LDS copy ring; one solver
+ *           wave; one barrier per landmark.  `team`, `aptg`, `batch` unused.
  * `grid` is an output; `items` <= 0 selects the default number of work items.
  */
 typedef struct pcv_plan {

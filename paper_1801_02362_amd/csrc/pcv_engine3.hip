@@ -6,18 +6,21 @@
 // its work item, so each worker keeps its atoms' share of the centred,
 // weighted structure in registers and streams only its own coordinates:
 //
-//   * a private ring of NS landmark slots in LDS is filled by asynchronous
+//   * a private ring of block slots in LDS is filled by asynchronous
 //     HBM -> LDS copies (global_load_lds_dwordx4, 16 B per lane); a wave
-//     waits only for the oldest slot (partial vmcnt), so NS - 1 landmarks
-//     stay in flight across the pipeline barriers;
+//     waits only for the oldest block it needs (partial vmcnt), so the
+//     younger copies stay in flight across the pipeline barrier;
 //   * the landmark is read from its slot into registers once; it feeds the
 //     correlation M = sum_j a_j (w_j x_j)^T (FP64 accumulation) at once and
 //     the gradient one step later, when the rotation is known;
-//   * per step (landmark t): phase A = correlation of t in the workers while
-//     the solver wave solves the quaternion eigenproblem of t - 1 (Section 3)
-//     and folds it into the running log-sum-exp (Eq. 2); phase B = gradient
-//     contributions of t - 1, U += e (q - q0) R (a - c) in FP32 and
-//     V += e R (a - c) in FP64, with R read from LDS.
+//   * one barrier per landmark t: before it, the workers contract landmark t
+//     and publish its correlation; after it, the solver wave solves the
+//     quaternion eigenproblem of t (Section 3) and folds it into the running
+//     log-sum-exp (Eq. 2) while the workers add the gradient terms of t - 1,
+//     U += e (q - q0) R (a - c) in FP32 and V += e R (a - c) in FP64, and go
+//     on to contract t + 1.  The solve is thus hidden behind a whole
+//     gradient-plus-correlation step; correlation and result slots are
+//     double-buffered by landmark parity.
 //
 // Workers reduce their 9 correlation sums over each 16-lane row with DPP
 // moves; the solver adds the 4 x 7 row sums in a fixed order, so results do
@@ -49,7 +52,7 @@ constexpr int ring_slots(int bpw) { return bpw >= 3 ? 4 : (bpw == 2 ? 5 : 6); }
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 __shared__ double e3_part[2][kWorkers3 * 4][9];
-__shared__ double e3_res[16];
+__shared__ double e3_res[2][16];
 __shared__ double e3_misc[16];
 
 // LDS-only workgroup barrier (the copies in flight are not waited for).
@@ -231,7 +234,8 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
     }
     bar3();
     if (t >= 1) {
-      const double sc = e3_res[11];
+      const double* rs = e3_res[(t - 1) & 1];
+      const double sc = rs[11];
       if (sc != 1.0) {
         const float scf = (float)sc;
 #pragma unroll
@@ -243,10 +247,10 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
       }
       float Rt[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) Rt[q] = (float)e3_res[q];
-      const float alf = (float)e3_res[9];
-      const double be = e3_res[10];
-      const float ch0 = (float)e3_res[12], ch1 = (float)e3_res[13], ch2 = (float)e3_res[14];
+      for (int q = 0; q < 9; ++q) Rt[q] = (float)rs[q];
+      const float alf = (float)rs[9];
+      const double be = rs[10];
+      const float ch0 = (float)rs[12], ch1 = (float)rs[13], ch2 = (float)rs[14];
 #pragma unroll
       for (int k = 0; k < BPW; ++k) {
         if (k < nbw) {
@@ -263,7 +267,6 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
         }
       }
     }
-    bar3();
   };
 
   for (int t = 0; t <= nL; t += 2) {
@@ -277,18 +280,27 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
   double mu[3], mv[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) { mu[d] = e3_misc[3 + d]; mv[d] = e3_misc[6 + d]; }
+  // 16-byte stores: a lane's four consecutive atoms (n_pad is a multiple of
+  // 64, so a group of four is either wholly inside or wholly past it).
+  typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < BPW; ++k) {
     if (k < nbw) {
       const int j0 = (w + kWorkers3 * k) * kBlk3 + lane * 4;
+      if (j0 < n_pad) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (j0 + e < n_pad) {
+        for (int d = 0; d < 3; ++d) {
+          f4v u4;
+          d2v v01, v23;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            stg(pu + (size_t)d * n_pad + j0 + e, (float)((double)U[k][d][e] - mu[d]));
-            stg(pv + (size_t)d * n_pad + j0 + e, V[k][d][e] - mv[d]);
-          }
+          for (int e = 0; e < 4; ++e) u4[e] = (float)((double)U[k][d][e] - mu[d]);
+          v01[0] = V[k][d][0] - mv[d];
+          v01[1] = V[k][d][1] - mv[d];
+          v23[0] = V[k][d][2] - mv[d];
+          v23[1] = V[k][d][3] - mv[d];
+          stg(reinterpret_cast<f4v*>(pu + (size_t)d * n_pad + j0), u4);
+          stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0), v01);
+          stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0 + 2), v23);
         }
       }
     }
@@ -320,18 +332,19 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
   double cap[3], Ga = 0.0, qi = 0.0, Rs[9];
   if (nL > 0) fetch(0, cap, Ga, qi, Rs);
   for (int t = 0; t <= nL; ++t) {
-    if (t >= 1) {
-      const int i = c.i0 + t - 1;
+    bar3();
+    if (t < nL) {
+      const int i = c.i0 + t;
       const double cc[3] = {cap[0], cap[1], cap[2]};
       const double Gai = Ga, qv = qi;
       double Rsv[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rsv[k] = Rs[k];
-      if (t < nL) fetch(t, cap, Ga, qi, Rs);
-      // Correlation of landmark t - 1: 28 row sums added in a fixed order.
+      if (t + 1 < nL) fetch(t + 1, cap, Ga, qi, Rs);
+      // Correlation of landmark t: 28 row sums added in a fixed order.
       double ssum = 0.0;
       if (lane < 9) {
-        const double(*pp)[9] = e3_part[(t - 1) & 1];
+        const double(*pp)[9] = e3_part[t & 1];
         for (int p = 0; p < kWorkers3 * 4; ++p) ssum += pp[p][lane];
       }
       double Mc[9];
@@ -396,10 +409,8 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
       v = (lane == 11) ? sc : v;
 #pragma unroll
       for (int d = 0; d < 3; ++d) v = (lane == 12 + d) ? cc[d] : v;
-      if (lane < 16) e3_res[lane] = v;
+      if (lane < 16) e3_res[t & 1][lane] = v;
     }
-    bar3();
-    bar3();
   }
   if (lane == 0) {
     e3_misc[0] = m;

@@ -223,14 +223,14 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
 
 // One workgroup per problem (the batched path and Algorithm 1).
 template <typename T>
-__global__ __launch_bounds__(256) void prep_kernel(const PrepArgs* __restrict__ args,
-                                                   const void* __restrict__ x_base) {
-  __shared__ double sh[4 * 5];
+__global__ __launch_bounds__(1024) void prep_kernel(const PrepArgs* __restrict__ args,
+                                                    const void* __restrict__ x_base) {
+  __shared__ double sh[16 * 5];
   const PrepArgs a = args[blockIdx.x];
   const T* x = (const T*)x_base + 3 * a.x_off;
   double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, 256>(a, x, sh, Gx, finite, c, g32);
+  centre_frame<T, 1024>(a, x, sh, Gx, finite, c, g32);
   if (threadIdx.x == 0) {
     *a.Gx = Gx;
     *a.Gx32 = g32[0];
@@ -607,7 +607,10 @@ __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, d
 // landmarks, ds/dx_k = -2 lambda w_k sum_i p_i (q_i - s)(x_k - r_ik)
 //                    = (2 lambda w_k / Z) sum_g f_g (U_g + (q0_g - s) V_g),
 // dz/dx_k = 2 w_k sum_i p_i (x_k - r_ik) = 2 (w_k x_k - w_k / Z sum_g f_g V_g).
-// Grid (atom blocks of 256, 3 coordinates, problems).
+// Grid (atom blocks of 64, 3 coordinates, problems); the 256 threads of a
+// workgroup are 64 atoms x 4 slot groups, so every slot's partial is read
+// coalesced and the work spreads over 4x more workgroups than atom tiles of
+// 256 would give.  The four group sums are added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restrict__ probs, Outs o,
                                                           const int* __restrict__ flag, int run_if) {
@@ -615,27 +618,29 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   if (flag != nullptr && *flag != run_if) return;
   __shared__ double sh[8];
   __shared__ double fq[2][256];
+  __shared__ double red[2][4][64];
   const Problem& P = probs[blockIdx.z];
-  if ((int)blockIdx.x * 256 >= P.n) return;
+  if ((int)blockIdx.x * 64 >= P.n) return;
   double m, Z, S;
   global_lse<256>(P, sh, m, Z, S);
   const double s = S / Z;
   const int c = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + a;
   const int n_pad = P.n_pad;
   double gs = 0.0, gz = 0.0;
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
     const int g = g0 + threadIdx.x;
     if (g < P.n_slots) {
-      fq[0][threadIdx.x] = scale_to(P.hdr[(size_t)g * 4], m, P.lam);
-      fq[1][threadIdx.x] = P.hdr[(size_t)g * 4 + 3] - s;
+      fq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, P.lam);
+      fq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
     }
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
 #pragma unroll 4
-      for (int t = 0; t < gn; ++t) {
+      for (int t = sg; t < gn; t += 4) {
         const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = fq[0][t];
@@ -644,7 +649,12 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
       }
     }
   }
-  if (j < P.n) {
+  red[0][sg][a] = gs;
+  red[1][sg][a] = gz;
+  __syncthreads();
+  if (sg == 0 && j < P.n) {
+    gs = ((red[0][0][a] + red[0][1][a]) + red[0][2][a]) + red[0][3][a];
+    gz = ((red[1][0][a] + red[1][1][a]) + red[1][2][a]) + red[1][3][a];
     const double wj = P.w[j];
     const size_t at = 3 * ((size_t)P.out_off + j) + c;
     if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * gs / Z);
@@ -793,7 +803,7 @@ hipError_t launch_pair_msd(const T* A, const double* ca, const double* Ga, const
 
 template <typename T>
 hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, hipStream_t st) {
-  hipLaunchKernelGGL((prep_kernel<T>), dim3(n_prob), dim3(256), 0, st, d_args, x_base);
+  hipLaunchKernelGGL((prep_kernel<T>), dim3(n_prob), dim3(1024), 0, st, d_args, x_base);
   return hipGetLastError();
 }
 
@@ -874,7 +884,7 @@ hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds, const Problem* pro
 template <typename T>
 hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
                               const int* flag, int run_if, hipStream_t st) {
-  dim3 grid((max_n_pad + 255) / 256, 3, n_prob);
+  dim3 grid((max_n_pad + 63) / 64, 3, n_prob);
   hipLaunchKernelGGL((merge_exact_kernel<T>), grid, dim3(256), 0, st, probs, outs, flag, run_if);
   return hipGetLastError();
 }

@@ -180,7 +180,7 @@ PCV_HD void jacobi_rot(double A[4][4], double V[4][4]) {
 // Cyclic Jacobi eigen-decomposition (fallback for (near-)degenerate top
 // eigenvalues, where Newton on the characteristic polynomial and the
 // adjugate lose accuracy).  Returns the largest eigenvalue and its vector.
-PCV_COLD double jacobi_top(const double F[10], double q[4]) {
+PCV_HD double jacobi_top_body(const double F[10], double q[4]) {
   double A[4][4], V[4][4];
   unpack4(F, A);
   for (int r = 0; r < 4; ++r)
@@ -199,6 +199,29 @@ PCV_COLD double jacobi_top(const double F[10], double q[4]) {
   if (A[2][2] > best) { best = A[2][2]; for (int k = 0; k < 4; ++k) q[k] = V[k][2]; }
   if (A[3][3] > best) { best = A[3][3]; for (int k = 0; k < 4; ++k) q[k] = V[k][3]; }
   return best;
+}
+
+struct TopPair {
+  double lam, q0, q1, q2, q3;
+};
+
+// Out-of-line copy for the streaming kernels: arguments and result travel in
+// registers, so nothing is stored to scratch memory unless it is called.
+PCV_COLD TopPair jacobi_top_v(double f0, double f1, double f2, double f3, double f4, double f5, double f6,
+                              double f7, double f8, double f9) {
+  const double F[10] = {f0, f1, f2, f3, f4, f5, f6, f7, f8, f9};
+  double q[4];
+  const double lam = jacobi_top_body(F, q);
+  return TopPair{lam, q[0], q[1], q[2], q[3]};
+}
+
+PCV_HD double jacobi_top(const double F[10], double q[4]) {
+  const TopPair t = jacobi_top_v(F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], F[9]);
+  q[0] = t.q0;
+  q[1] = t.q1;
+  q[2] = t.q2;
+  q[3] = t.q3;
+  return t.lam;
 }
 
 PCV_HD void quat_to_rot(const double q[4], double R[9]) {
@@ -230,15 +253,14 @@ PCV_HD int top_eigenpair(const double M[9], double lam_up, double F[10], double&
   double dp;
   lam = newton_top_root(c2, c1, c0, lam_up, dp);
   int fb = 0;
-  if (!(dp > kDegenerateGap * scale * scale * scale)) {
+  bool fallback = !(dp > kDegenerateGap * scale * scale * scale);
+  if (!fallback) {
+    const double diag = adjugate_eigvec(F, lam, q);
+    fallback = !(diag > 0.1 * dp);     // adj(F - lam I) = -dp q q^T: max |diag| >= dp/4
+  }
+  if (fallback) {
     lam = jacobi_top(F, q);
     fb = 1;
-  } else {
-    const double diag = adjugate_eigvec(F, lam, q);
-    if (!(diag > 0.1 * dp)) {           // adj(F - lam I) = -dp q q^T: max |diag| >= dp/4
-      lam = jacobi_top(F, q);
-      fb = 1;
-    }
   }
   return fb;
 }
