@@ -243,6 +243,95 @@ pcv_status pcv_batch_eval(pcv_batch* b, const void* x_all, double* sz_all, void*
 const char* pcv_batch_plan_string(const pcv_batch* b);
 const char* pcv_batch_last_error(const pcv_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate (a project addition beside the paper's method): an MLP
+ * maps a structure, superposed onto a fixed reference with the Eq. 3 /
+ * Section 3 rotation, to the standardised path variables (s, z) of Eq. 2;
+ * ds/dx and dz/dx come from its backward pass chained through the alignment.
+ * Layers: 3n -> H -> H -> H -> 2 with SiLU.  GEMMs run on the matrix cores
+ * with BF16 operands and FP32 accumulation; master weights, Adam moments,
+ * biases and activations before rounding are FP32.
+ *
+ * Parameters are one flat FP32 array: for l = 1..4, W_l [fan_in][fan_out]
+ * (row-major) followed by b_l [fan_out].  Initial values are the caller's
+ * (the library draws no random numbers).
+ * ---------------------------------------------------------------------- */
+typedef struct pcv_mlp pcv_mlp;
+
+typedef struct pcv_mlp_stats {
+  int64_t steps;            /* pcv_mlp_step calls */
+  int64_t surrogate_steps;  /* answered by the surrogate (drift <= epsilon) */
+  int64_t exact_steps;      /* answered exactly (drift > epsilon, first step, forced) and judged */
+  double max_abs_ds;        /* judge: max |s_surrogate - s_exact| over exact steps */
+  double max_abs_dz;
+  double mean_abs_ds;
+  double mean_abs_dz;
+} pcv_mlp_stats;
+
+/*
+ * Create a surrogate for structures of n_atoms atoms.
+ *   opt         device and stream (FP32 only; graphs per opt->use_graph)
+ *   hidden      hidden width H (>= 16)
+ *   max_batch   largest batch of any later call
+ *   ref         host [n][3] FP64 reference structure the inputs are aligned to
+ *   w           host [n] alignment weights or NULL (uniform); normalised
+ * Parameters start at zero: call pcv_mlp_set_params before use.
+ */
+pcv_status pcv_mlp_create(pcv_mlp** out, const pcv_options* opt, int n_atoms, int hidden, int max_batch,
+                          const double* ref, const double* w);
+pcv_status pcv_mlp_destroy(pcv_mlp* m);
+long long pcv_mlp_param_count(const pcv_mlp* m);
+/* Host FP32 parameters in (resets Adam's moments and step) / out.  Synchronise. */
+pcv_status pcv_mlp_set_params(pcv_mlp* m, const float* params, long long count);
+pcv_status pcv_mlp_get_params(pcv_mlp* m, float* params, long long count);
+/* Host copy of the gradients of the last pcv_mlp_train_step (same layout). */
+pcv_status pcv_mlp_get_grads(pcv_mlp* m, float* grads, long long count);
+/* Output scaling: s = mean[0] + sd[0] y0, z = mean[1] + sd[1] y1. */
+pcv_status pcv_mlp_set_scaling(pcv_mlp* m, const double mean[2], const double sd[2]);
+
+/*
+ * Align B structures (device [B][n][3] FP32) onto the reference: x' = R^T
+ * (x - c), device outputs [B][3n] as BF16 bits (uint16) and/or FP32 (either
+ * may be NULL).  Used to build training inputs.
+ */
+pcv_status pcv_mlp_align(pcv_mlp* m, const float* x, int B, uint16_t* xa_bf16, float* xa_f32);
+
+/* Network outputs (standardised, device [B][2] FP32) for B aligned BF16 inputs [B][3n]. */
+pcv_status pcv_mlp_forward(pcv_mlp* m, const uint16_t* inputs, int B, float* y);
+
+/*
+ * One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on the mean
+ * over the batch of the squared error summed over both outputs.
+ *   inputs   device [B][3n] BF16 aligned structures
+ *   targets  device [B][2] FP32 standardised (s, z)
+ *   loss     device float or NULL (the loss before the step)
+ */
+pcv_status pcv_mlp_train_step(pcv_mlp* m, const uint16_t* inputs, const float* targets, int B, float lr,
+                              float* loss);
+
+/*
+ * Surrogate (s, z) and gradients for B raw structures.
+ *   x      device [B][n][3] FP32;  sz  device double [B][2]
+ *   ds_dx, dz_dx   device [B][n][3] FP32 or NULL (alignment derivative included)
+ */
+pcv_status pcv_mlp_eval(pcv_mlp* m, const float* x, int B, double* sz, float* ds_dx, float* dz_dx);
+
+/*
+ * One step with fallback (Algorithm 2's drift test with the surrogate in
+ * place of Eq. 5): the exact handle h (FP32, same n) superposes its close
+ * structure y onto x; if D(x, y) > epsilon (or on its first step / when
+ * forced) the exact path answers, y <- x, and the surrogate's error on this
+ * frame is recorded (the judge); otherwise the surrogate answers.
+ *   x      device [n][3];  sz device double[2];  ds_dx, dz_dx device [n][3] or NULL
+ *   used_surrogate   device int or NULL: 1 surrogate, 0 exact
+ * The decision stays on the device (no host synchronisation).
+ */
+pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, double* sz, float* ds_dx, float* dz_dx,
+                        int* used_surrogate);
+pcv_status pcv_mlp_get_stats(pcv_mlp* m, pcv_mlp_stats* out);
+pcv_status pcv_mlp_reset_stats(pcv_mlp* m);
+const char* pcv_mlp_last_error(const pcv_mlp* m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["PcvError", "PathCV", "BatchPathCV", "library_path", "load_library", "FP32", "FP64"]
+__all__ = ["PcvError", "PathCV", "BatchPathCV", "Surrogate", "library_path", "load_library", "FP32", "FP64"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FP32, FP64 = 32, 64
@@ -41,6 +41,12 @@ class _Plan(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("frames", "recomputes", "expensive_msd", "approx_frames", "exact_evals", "eigen_fallbacks")]
+
+
+class _MlpStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("surrogate_steps", ctypes.c_int64), ("exact_steps", ctypes.c_int64),
+                ("max_abs_ds", ctypes.c_double), ("max_abs_dz", ctypes.c_double),
+                ("mean_abs_ds", ctypes.c_double), ("mean_abs_dz", ctypes.c_double)]
 
 
 _lib = None
@@ -88,6 +94,21 @@ def load_library():
         "pcv_batch_eval": (st, [vp, vp, vp, vp, vp]),
         "pcv_batch_plan_string": (ctypes.c_char_p, [vp]),
         "pcv_batch_last_error": (ctypes.c_char_p, [vp]),
+        "pcv_mlp_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_Options), i, i, i, vp, vp]),
+        "pcv_mlp_destroy": (st, [vp]),
+        "pcv_mlp_param_count": (ctypes.c_longlong, [vp]),
+        "pcv_mlp_set_params": (st, [vp, vp, ctypes.c_longlong]),
+        "pcv_mlp_get_params": (st, [vp, vp, ctypes.c_longlong]),
+        "pcv_mlp_get_grads": (st, [vp, vp, ctypes.c_longlong]),
+        "pcv_mlp_set_scaling": (st, [vp, vp, vp]),
+        "pcv_mlp_align": (st, [vp, vp, i, vp, vp]),
+        "pcv_mlp_forward": (st, [vp, vp, i, vp]),
+        "pcv_mlp_train_step": (st, [vp, vp, vp, i, ctypes.c_float, vp]),
+        "pcv_mlp_eval": (st, [vp, vp, i, vp, vp, vp]),
+        "pcv_mlp_step": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "pcv_mlp_get_stats": (st, [vp, ctypes.POINTER(_MlpStats)]),
+        "pcv_mlp_reset_stats": (st, [vp]),
+        "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -339,3 +360,138 @@ class BatchPathCV:
             self.close()
         except Exception:
             pass
+
+
+class Surrogate:
+    """MLP surrogate of (s, z) on one GPU (BF16 matrix-core kernels).
+
+    ``ref``: host ``[n][3]`` reference the inputs are aligned to; ``hidden``:
+    hidden width; ``max_batch``: largest batch of any call.  Parameters are
+    one flat FP32 array (W_l [fan_in][fan_out] then b_l, l = 1..4) supplied by
+    the caller (``set_params``).
+    """
+
+    def __init__(self, ref, *, hidden: int = 512, max_batch: int = 1024, w=None, use_graph: bool = True,
+                 stream=None, device: int = 0):
+        import numpy as np
+        self._L = load_library()
+        ref = np.ascontiguousarray(np.asarray(ref, dtype=np.float64))
+        self.n = ref.shape[0]
+        self.hidden = hidden
+        self.max_batch = max_batch
+        opt = _Options()
+        self._L.pcv_default_options(ctypes.byref(opt))
+        opt.device = device
+        opt.precision = FP32
+        opt.use_graph = 1 if use_graph else 0
+        opt.stream = _stream_ptr(stream)
+        warr, wptr = _as_host_f64(w, self.n, "w")
+        self._keep = (ref, warr)
+        h = ctypes.c_void_p()
+        s = self._L.pcv_mlp_create(ctypes.byref(h), ctypes.byref(opt), self.n, hidden, max_batch,
+                                   ref.ctypes.data_as(ctypes.c_void_p), wptr)
+        if s != 0:
+            raise PcvError(s, self._L.pcv_status_string(s).decode())
+        self._h = h
+        self.param_count = int(self._L.pcv_mlp_param_count(h))
+
+    def _check(self, s):
+        if s != 0:
+            msg = self._L.pcv_mlp_last_error(self._h).decode()
+            raise PcvError(s, f"{self._L.pcv_status_string(s).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pcv_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.size != self.param_count:
+            raise ValueError(f"expected {self.param_count} parameters")
+        self._check(self._L.pcv_mlp_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size))
+
+    def params(self):
+        import numpy as np
+        p = np.empty(self.param_count, dtype=np.float32)
+        self._check(self._L.pcv_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size))
+        return p
+
+    def grads(self):
+        import numpy as np
+        p = np.empty(self.param_count, dtype=np.float32)
+        self._check(self._L.pcv_mlp_get_grads(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size))
+        return p
+
+    def set_scaling(self, mean, sd):
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float64))
+        d = np.ascontiguousarray(np.asarray(sd, dtype=np.float64))
+        self._keep_scaling = (m, d)
+        self._check(self._L.pcv_mlp_set_scaling(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                                d.ctypes.data_as(ctypes.c_void_p)))
+
+    def align(self, x, *, bf16: bool = True, f32: bool = False):
+        """Aligned inputs of structures ``x`` (CUDA float32 ``[B][n][3]``):
+        BF16 bits as int16 ``[B][3n]`` and/or float32."""
+        import torch
+        x = x.contiguous()
+        B = x.shape[0]
+        ob = torch.empty(B, 3 * self.n, dtype=torch.int16, device=x.device) if bf16 else None
+        of = torch.empty(B, 3 * self.n, dtype=torch.float32, device=x.device) if f32 else None
+        self._check(self._L.pcv_mlp_align(self._h, _ptr(x), B, _ptr(ob), _ptr(of)))
+        return ob, of
+
+    def forward(self, inputs):
+        import torch
+        B = inputs.shape[0]
+        y = torch.empty(B, 2, dtype=torch.float32, device=inputs.device)
+        self._check(self._L.pcv_mlp_forward(self._h, _ptr(inputs.contiguous()), B, _ptr(y)))
+        return y
+
+    def train_step(self, inputs, targets, lr: float, loss=None):
+        """One Adam step on BF16 inputs ``[B][3n]`` (int16 bits) and float32
+        standardised targets ``[B][2]``; ``loss`` (float32 tensor [1]) receives
+        the loss before the step."""
+        self._check(self._L.pcv_mlp_train_step(self._h, _ptr(inputs), _ptr(targets), inputs.shape[0],
+                                               ctypes.c_float(lr), _ptr(loss)))
+
+    def eval(self, x, *, grad: bool = True, out=None):
+        """(s, z) and gradients for raw structures ``x`` ``[B][n][3]`` (float32)."""
+        import torch
+        x = x.contiguous()
+        B = x.shape[0]
+        o = out or {}
+        sz = o.get("sz") if o.get("sz") is not None else torch.empty(B, 2, dtype=torch.float64, device=x.device)
+        ds = dz = None
+        if grad:
+            ds = o.get("ds_dx") if o.get("ds_dx") is not None else torch.empty_like(x)
+            dz = o.get("dz_dx") if o.get("dz_dx") is not None else torch.empty_like(x)
+        self._check(self._L.pcv_mlp_eval(self._h, _ptr(x), B, _ptr(sz), _ptr(ds), _ptr(dz)))
+        return {"sz": sz, "ds_dx": ds, "dz_dx": dz}
+
+    def step(self, exact: "PathCV", x, *, out=None):
+        """One fallback step (drift test of the exact handle ``exact``)."""
+        import torch
+        o = out or {}
+        sz = o.get("sz") if o.get("sz") is not None else torch.empty(2, dtype=torch.float64, device=x.device)
+        ds = o.get("ds_dx") if o.get("ds_dx") is not None else torch.empty_like(x)
+        dz = o.get("dz_dx") if o.get("dz_dx") is not None else torch.empty_like(x)
+        used = o.get("used") if o.get("used") is not None else torch.empty(1, dtype=torch.int32, device=x.device)
+        self._check(self._L.pcv_mlp_step(self._h, exact._h, _ptr(x), _ptr(sz), _ptr(ds), _ptr(dz), _ptr(used)))
+        return {"sz": sz, "ds_dx": ds, "dz_dx": dz, "used": used}
+
+    def stats(self) -> dict:
+        st = _MlpStats()
+        self._check(self._L.pcv_mlp_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _MlpStats._fields_}
+
+    def reset_stats(self):
+        self._check(self._L.pcv_mlp_reset_stats(self._h))

@@ -556,6 +556,27 @@ extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, v
   });
 }
 
+// Exact half of the surrogate's fallback step: the close-structure drift test
+// and, on a reassignment, the exact pass (no Eq. 5 branch).  Returns the
+// device flag the surrogate's tail kernel reads.
+extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
+                                                       double* sz, void* ds, void* dz, const int** flag) {
+  if (h->fp64 || h->L == 0 || h->n != n_atoms) return hipErrorInvalidValue;
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, nullptr, h->n, h->n_pad, h->L};
+  pa.xw32 = h->xw32;
+  pa.n_x = h->n_x;
+  CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+  Outs o{ds, dz, sz, nullptr};
+  hipError_t e = launch_prep_close<float>(pa, x, ca, o, st);
+  if (e != hipSuccess) return e;
+  e = engine_timed<float>(h, st, MODE_EXACT_SAVE, h->flag, 1, nullptr);
+  if (e != hipSuccess) return e;
+  e = launch_merge_exact<float>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+  *flag = h->flag;
+  return e;
+}
+
 extern "C" pcv_status pcv_force_reassign(pcv_handle* h) {
   if (!h) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");

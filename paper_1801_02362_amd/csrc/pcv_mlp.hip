@@ -1,0 +1,877 @@
+// Learned surrogate of the path variables (a project addition, not in the
+// paper): a structure is superposed onto a fixed reference with the same
+// optimal-rotation machinery as Eq. 3 (Section 3), the aligned coordinates go
+// through an MLP (3n -> H -> H -> H -> 2, SiLU), and the two outputs are the
+// standardised path variables s and z of Eq. 2.  ds/dx and dz/dx come from
+// the network's backward pass chained through the alignment (explicit
+// rotation, centring projection and the derivative of the rotation, the
+// same eigenvector-perturbation adjoint as the close-structure derivative of
+// Eq. 6).  The fallback step follows Algorithm 2's drift test: whenever the
+// structure has moved more than epsilon from the last exactly evaluated
+// structure the exact path runs (and judges the surrogate on that frame),
+// otherwise the surrogate answers.
+//
+// Numerics: every GEMM multiplies BF16 operands on the matrix cores
+// (v_mfma_f32_16x16x16_bf16) with FP32 accumulation; biases, pre-activations,
+// SiLU, the loss, Adam's moments and the master weights are FP32; the
+// alignment and its derivative are FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcv.h"
+#include "pcv_host_util.h"
+#include "pcv_internal.h"
+#include "pcv_math.h"
+
+namespace pcv {
+namespace {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float sigm(float v) { return 1.0f / (1.0f + expf(-v)); }
+
+enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_SILU_GRAD = 3 };
+
+// C[M][N] = A[M][K] B[K][N] with A(i,k) = A[i sAi + k sAk] and
+// B(k,j) = B[k sBk + j sBj] (BF16), so one kernel serves the forward
+// product, the input-gradient product (W transposed) and the weight-gradient
+// product (activations transposed).
+struct GemmArgs {
+  const uint16_t* A;
+  long long sAi, sAk;
+  const uint16_t* B;
+  long long sBk, sBj;
+  int M, N, K;
+  float* C;          // FP32 result: C, pre-activation or backward signal
+  int ldc;
+  uint16_t* Cb;      // BF16 copy: activation or backward signal (may be null)
+  int ldcb;
+  const float* bias; // [N]
+  const float* pre;  // EPI_SILU_GRAD: pre-activation of row i / pre_div
+  int ldpre, pre_div;
+};
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  __shared__ uint16_t As[kTM][kTK + 4];
+  __shared__ uint16_t Bs[kTK][kTN + 4];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  f4v acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const bool a_rows_fast = (g.sAi == 1);
+  const bool b_cols_fast = (g.sBj == 1);
+  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int r = a_rows_fast ? (e % kTM) : (e / kTK);
+      const int c = a_rows_fast ? (e / kTM) : (e % kTK);
+      const int i = m0 + r, k = k0 + c;
+      As[r][c] = (i < g.M && k < g.K) ? g.A[(long long)i * g.sAi + (long long)k * g.sAk] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int r = b_cols_fast ? (e / kTN) : (e % kTK);
+      const int c = b_cols_fast ? (e % kTN) : (e / kTK);
+      const int k = k0 + r, j = n0 + c;
+      Bs[r][c] = (k < g.K && j < g.N) ? g.B[(long long)k * g.sBk + (long long)j * g.sBj] : (uint16_t)0;
+    }
+    __syncthreads();
+    s4v a;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = (short)As[16 * wave + (lane & 15)][4 * (lane >> 4) + r];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      s4v b;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) b[r] = (short)Bs[4 * (lane >> 4) + r][16 * t + (lane & 15)];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = m0 + 16 * wave + 4 * (lane >> 4) + r;
+      const int j = n0 + 16 * t + (lane & 15);
+      if (i >= g.M || j >= g.N) continue;
+      const float v = acc[t][r];
+      if (EPI == EPI_STORE) {
+        g.C[(long long)i * g.ldc + j] = v;
+      } else if (EPI == EPI_BIAS) {
+        g.C[(long long)i * g.ldc + j] = v + g.bias[j];
+      } else if (EPI == EPI_BIAS_SILU) {
+        const float p = v + g.bias[j];
+        g.C[(long long)i * g.ldc + j] = p;
+        g.Cb[(long long)i * g.ldcb + j] = f2bf(p * sigm(p));
+      } else {
+        const float p = g.pre[(long long)(i / g.pre_div) * g.ldpre + j];
+        const float sg = sigm(p);
+        const float d = v * (sg * (1.0f + p * (1.0f - sg)));
+        g.C[(long long)i * g.ldc + j] = d;
+        g.Cb[(long long)i * g.ldcb + j] = f2bf(d);
+      }
+    }
+  }
+}
+
+template <int EPI>
+hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
+  hipLaunchKernelGGL((gemm_bf16_kernel<EPI>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// Column sums of a row-major [M][N] FP32 matrix into out[N] (bias gradients).
+__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ d, int M, int N,
+                                                     float* __restrict__ out) {
+  __shared__ float red[4][64];
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+  float s = 0.f;
+  if (j < N)
+    for (int i = grp; i < M; i += 4) s += d[(long long)i * N + j];
+  red[grp][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (grp == 0 && j < N) out[j] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// Mean squared error over the batch (summed over the two outputs) and its
+// gradient dy = 2 (y - t) / B, rounded to BF16 for the backward product.
+__global__ __launch_bounds__(1024) void loss_kernel(const float* __restrict__ y, const float* __restrict__ t, int B,
+                                                    uint16_t* __restrict__ dy_bf, float* __restrict__ dy32,
+                                                    float* __restrict__ loss) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < 2 * B; e += 1024) {
+    const float r = y[e] - t[e];
+    acc += (double)r * r;
+    const float g = 2.0f * r / (float)B;
+    dy32[e] = g;
+    dy_bf[e] = f2bf(g);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += red[w];
+    if (loss) *loss = (float)(s / B);
+  }
+}
+
+// Adam on FP32 masters; refreshes the BF16 working copy.
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   uint16_t* __restrict__ wb, long long n, float lr,
+                                                   float b1, float b2, float c1, float c2, float eps) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  w[i] = wi;
+  wb[i] = f2bf(wi);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ w, uint16_t* __restrict__ wb,
+                                                      long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) wb[i] = f2bf(w[i]);
+}
+
+template <int NV>
+__device__ void bsum(double v[NV], double* sh) {
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += sh[w * NV + k];
+    v[k] = s;
+  }
+}
+
+// Reference set-up: weighted centring of the reference (once).
+__global__ __launch_bounds__(256) void ref_centre_kernel(const double* __restrict__ ref, const double* __restrict__ w,
+                                                         int n, double* __restrict__ ref_c, double* __restrict__ Ga) {
+  __shared__ double sh[4 * 3];
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += 256)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = fma(w[j], ref[3 * j + d], c[d]);
+  bsum<3>(c, sh);
+  double g[1] = {0.0};
+  for (int j = threadIdx.x; j < n; j += 256) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double a = ref[3 * j + d] - c[d];
+      ref_c[3 * j + d] = a;
+      g[0] = fma(w[j] * a, a, g[0]);
+    }
+  }
+  bsum<1>(g, sh);
+  if (threadIdx.x == 0) *Ga = g[0];
+}
+
+constexpr int kAl = 32;   // doubles of alignment state per frame: c[3], R[9], F[10], lam, q[4]
+
+// Superpose the reference onto each frame and write x' = R^T (x - c).
+__global__ __launch_bounds__(256) void align_kernel(const float* __restrict__ x, int n, const double* __restrict__ w,
+                                                    const double* __restrict__ ref_c, const double* __restrict__ Ga,
+                                                    double* __restrict__ st, float* __restrict__ xa32,
+                                                    uint16_t* __restrict__ xa_bf) {
+  __shared__ double sh[4 * 10];
+  __shared__ double Rs[9];
+  const int b = blockIdx.x;
+  const float* xb = x + (size_t)b * 3 * n;
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += 256)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = fma(w[j], (double)xb[3 * j + d], c[d]);
+  bsum<3>(c, sh);
+  double M[10] = {0.0};   // 9 correlation entries + Gx
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double xc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xc[d] = (double)xb[3 * j + d] - c[d];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) M[3 * r + s] = fma(w[j] * ref_c[3 * j + r], xc[s], M[3 * r + s]);
+    M[9] = fma(w[j], xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2], M[9]);
+  }
+  bsum<10>(M, sh);
+  double* S = st + (size_t)b * kAl;
+  if (threadIdx.x == 0) {
+    double F[10], lam, q[4], R[9];
+    top_eigenpair(M, 0.5 * (M[9] + *Ga), F, lam, q);
+    quat_to_rot(q, R);
+    for (int d = 0; d < 3; ++d) S[d] = c[d];
+    for (int k = 0; k < 9; ++k) { S[3 + k] = R[k]; Rs[k] = R[k]; }
+    for (int k = 0; k < 10; ++k) S[12 + k] = F[k];
+    S[22] = lam;
+    for (int k = 0; k < 4; ++k) S[23 + k] = q[k];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double xc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xc[d] = (double)xb[3 * j + d] - c[d];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const double v = Rs[0 * 3 + s] * xc[0] + Rs[1 * 3 + s] * xc[1] + Rs[2 * 3 + s] * xc[2];   // (R^T x_c)_s
+      const size_t o = (size_t)b * 3 * n + 3 * j + s;
+      if (xa32) xa32[o] = (float)v;
+      if (xa_bf) xa_bf[o] = f2bf((float)v);
+    }
+  }
+}
+
+// Output layer values -> (s, z), and the backward seeds: row 2b + k carries
+// d(output k)/dy = sd_k e_k.
+__global__ void outputs_kernel(const float* __restrict__ y, int B, double ms, double ss, double mz, double sz_,
+                               double* __restrict__ sz, uint16_t* __restrict__ seed_bf) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  sz[2 * b + 0] = ms + ss * (double)y[2 * b + 0];
+  sz[2 * b + 1] = mz + sz_ * (double)y[2 * b + 1];
+  seed_bf[4 * b + 0] = f2bf((float)ss);
+  seed_bf[4 * b + 1] = 0;
+  seed_bf[4 * b + 2] = 0;
+  seed_bf[4 * b + 3] = f2bf((float)sz_);
+}
+
+// Chain d f / d x' (rows 2b: s, 2b+1: z; layout 3j + d) through the
+// alignment: explicit rotation, centring projection and the rotation
+// derivative (Gamma = d(G:R)/dM with G = sum_j x_c,j g_j^T).
+__global__ __launch_bounds__(256) void align_back_kernel(const float* __restrict__ x, int n,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ ref_c,
+                                                         const double* __restrict__ st, const float* __restrict__ gx,
+                                                         float* __restrict__ ds, float* __restrict__ dz) {
+  __shared__ double sh[4 * 12];
+  __shared__ double gam[9], rsum[3];
+  const int b = blockIdx.x;
+  const float* xb = x + (size_t)b * 3 * n;
+  const double* S = st + (size_t)b * kAl;
+  double c[3], R[9];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c[d] = S[d];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = S[3 + k];
+  for (int o = 0; o < 2; ++o) {
+    float* out = (o == 0) ? ds : dz;
+    const float* g = gx + (size_t)(2 * b + o) * 3 * n;
+    double acc[12] = {0.0};   // G[9], sum_j R g_j [3]
+    for (int j = threadIdx.x; j < n; j += 256) {
+      double xc[3], gj[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xc[d] = (double)xb[3 * j + d] - c[d];
+        gj[d] = (double)g[3 * j + d];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) acc[3 * r + s] = fma(xc[r], gj[s], acc[3 * r + s]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) acc[9 + r] += R[3 * r + 0] * gj[0] + R[3 * r + 1] * gj[1] + R[3 * r + 2] * gj[2];
+    }
+    bsum<12>(acc, sh);
+    if (threadIdx.x == 0) {
+      double F[10], q[4], Gm[9], Gamma[9];
+      for (int k = 0; k < 10; ++k) F[k] = S[12 + k];
+      for (int k = 0; k < 4; ++k) q[k] = S[23 + k];
+      for (int k = 0; k < 9; ++k) Gm[k] = acc[k];
+      rotation_adjoint(F, S[22], q, Gm, Gamma);
+      for (int k = 0; k < 9; ++k) gam[k] = Gamma[k];
+      for (int r = 0; r < 3; ++r) rsum[r] = acc[9 + r];
+    }
+    __syncthreads();
+    if (out != nullptr) {
+      for (int j = threadIdx.x; j < n; j += 256) {
+        double gj[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gj[d] = (double)g[3 * j + d];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double ex = R[3 * r + 0] * gj[0] + R[3 * r + 1] * gj[1] + R[3 * r + 2] * gj[2] - w[j] * rsum[r];
+          const double rot = w[j] * (gam[0 * 3 + r] * ref_c[3 * j + 0] + gam[1 * 3 + r] * ref_c[3 * j + 1] +
+                                     gam[2 * 3 + r] * ref_c[3 * j + 2]);
+          out[(size_t)b * 3 * n + 3 * j + r] = (float)(ex + rot);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Fallback step tail: on a surrogate step (flag 0) the surrogate's outputs
+// become the step's outputs; on an exact step (flag 1) they are compared with
+// the exact ones (the judge); flag -1 (bad input) leaves everything.
+__global__ __launch_bounds__(256) void select_kernel(const int* __restrict__ flag, const double* __restrict__ sz_s,
+                                                     const float* __restrict__ ds_s, const float* __restrict__ dz_s,
+                                                     int n3, double* __restrict__ sz, float* __restrict__ ds,
+                                                     float* __restrict__ dz, int* __restrict__ used,
+                                                     double* __restrict__ judge, long long* __restrict__ cnt) {
+  const int f = *flag;
+  if (f == 0) {
+    for (int e = threadIdx.x; e < n3; e += 256) {
+      if (ds) ds[e] = ds_s[e];
+      if (dz) dz[e] = dz_s[e];
+    }
+    if (threadIdx.x == 0) {
+      sz[0] = sz_s[0];
+      sz[1] = sz_s[1];
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (used) *used = (f == 0) ? 1 : 0;
+    cnt[0] += 1;                          // steps
+    if (f == 0) cnt[1] += 1;              // surrogate steps
+    if (f == 1) {
+      cnt[2] += 1;                        // exact (judged) steps
+      const double es = fabs(sz_s[0] - sz[0]), ez = fabs(sz_s[1] - sz[1]);
+      judge[0] = fmax(judge[0], es);
+      judge[1] = fmax(judge[1], ez);
+      judge[2] += es;
+      judge[3] += ez;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace pcv
+
+using namespace pcv;
+
+// ============================================================ handle
+struct pcv_mlp {
+  pcv_options opt{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int n = 0, nin = 0, H = 0, maxB = 0;
+  long long P = 0;
+  long long off_W[4], off_b[4];
+  int dims[5];
+  double mean[2] = {0.0, 0.0}, sd[2] = {1.0, 1.0};
+  long long adam_t = 0;
+  DevMem mem;
+  float *w32 = nullptr, *g32 = nullptr, *m32 = nullptr, *v32 = nullptr;
+  uint16_t* wbf = nullptr;
+  double *ref_c = nullptr, *wts = nullptr, *Ga = nullptr, *alst = nullptr;
+  uint16_t *act[4] = {nullptr, nullptr, nullptr, nullptr};   // layer inputs (BF16)
+  float* pre[3] = {nullptr, nullptr, nullptr};
+  float* y = nullptr;
+  float* xa32 = nullptr;
+  uint16_t* dyb = nullptr;
+  float* dy32 = nullptr;
+  float* d32[3] = {nullptr, nullptr, nullptr};
+  uint16_t* dbf[3] = {nullptr, nullptr, nullptr};
+  float* gx = nullptr;
+  double *sz_s = nullptr, *judge = nullptr;
+  float *ds_s = nullptr, *dz_s = nullptr;
+  long long* cnt = nullptr;
+  struct GraphEntry {
+    const void* key[8];
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  std::string err;
+};
+
+static pcv_status mfail(pcv_mlp* m, pcv_status s, const std::string& msg) {
+  if (m) m->err = msg;
+  return s;
+}
+#define MHIP(m, expr)                                                                                 \
+  do {                                                                                                \
+    hipError_t _e = (expr);                                                                           \
+    if (_e != hipSuccess)                                                                             \
+      return mfail((m), _e == hipErrorOutOfMemory ? PCV_ENOMEM : PCV_EHIP,                          \
+                   std::string(#expr) + ": " + hipGetErrorString(_e));                               \
+  } while (0)
+#define MTRY(expr)                      \
+  do {                                  \
+    hipError_t _e = (expr);             \
+    if (_e != hipSuccess) return _e;    \
+  } while (0)
+
+static void mlp_drop_graphs(pcv_mlp* m) {
+  for (auto& g : m->graphs) (void)hipGraphExecDestroy(g.exec);
+  m->graphs.clear();
+}
+
+extern "C" pcv_status pcv_mlp_create(pcv_mlp** out, const pcv_options* opt, int n_atoms, int hidden, int max_batch,
+                                     const double* ref, const double* w) {
+  if (!out) return PCV_EINVAL;
+  *out = nullptr;
+  pcv_options o;
+  pcv_default_options(&o);
+  if (opt) o = *opt;
+  if (!ref || n_atoms < 3 || hidden < 16 || max_batch < 1 || 3 * (long long)n_atoms > 65536) return PCV_EINVAL;
+  if (o.precision != PCV_FP32) return PCV_EUNSUPPORTED;
+  std::vector<double> hw(n_atoms, 1.0 / n_atoms);
+  if (w) {
+    double s = 0.0;
+    for (int j = 0; j < n_atoms; ++j) {
+      if (!(w[j] >= 0.0) || !std::isfinite(w[j])) return PCV_EINVAL;
+      s += w[j];
+    }
+    if (!(s > 0.0)) return PCV_EINVAL;
+    for (int j = 0; j < n_atoms; ++j) hw[j] = w[j] / s;
+  }
+  for (int k = 0; k < 3 * n_atoms; ++k)
+    if (!std::isfinite(ref[k])) return PCV_EINVAL;
+  if (hipSetDevice(o.device) != hipSuccess) return PCV_EHIP;
+  pcv_mlp* m = new pcv_mlp();
+  m->opt = o;
+  m->stream = (hipStream_t)o.stream;
+  m->n = n_atoms;
+  m->nin = 3 * n_atoms;
+  m->H = hidden;
+  m->maxB = max_batch;
+  const int d[5] = {m->nin, hidden, hidden, hidden, 2};
+  long long off = 0;
+  for (int l = 0; l < 4; ++l) {
+    m->dims[l] = d[l];
+    m->off_W[l] = off;
+    off += (long long)d[l] * d[l + 1];
+    m->off_b[l] = off;
+    off += d[l + 1];
+  }
+  m->dims[4] = 2;
+  m->P = off;
+  auto fail_create = [&](pcv_status s) {
+    m->mem.release();
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+    delete m;
+    return s;
+  };
+  if (hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail_create(PCV_EHIP);
+  DevMem& M = m->mem;
+  const size_t B = max_batch, H = hidden, nin = m->nin, P = m->P;
+  bool ok = true;
+  auto A = [&](void** p, size_t bytes) { ok = ok && M.alloc(p, bytes) == hipSuccess; };
+  A((void**)&m->w32, P * 4);
+  A((void**)&m->g32, P * 4);
+  A((void**)&m->m32, P * 4);
+  A((void**)&m->v32, P * 4);
+  A((void**)&m->wbf, P * 2);
+  A((void**)&m->ref_c, nin * 8);
+  A((void**)&m->wts, n_atoms * 8);
+  A((void**)&m->Ga, 8);
+  A((void**)&m->alst, B * kAl * 8);
+  A((void**)&m->act[0], B * nin * 2);
+  for (int l = 1; l < 4; ++l) A((void**)&m->act[l], B * H * 2);
+  for (int l = 0; l < 3; ++l) A((void**)&m->pre[l], B * H * 4);
+  A((void**)&m->y, B * 2 * 4);
+  A((void**)&m->xa32, B * nin * 4);
+  A((void**)&m->dyb, 2 * B * 2 * 2);
+  A((void**)&m->dy32, 2 * B * 2 * 4);
+  for (int l = 0; l < 3; ++l) {
+    A((void**)&m->d32[l], 2 * B * H * 4);
+    A((void**)&m->dbf[l], 2 * B * H * 2);
+  }
+  A((void**)&m->gx, 2 * B * nin * 4);
+  A((void**)&m->sz_s, 2 * 8);
+  A((void**)&m->ds_s, nin * 4);
+  A((void**)&m->dz_s, nin * 4);
+  A((void**)&m->judge, 4 * 8);
+  A((void**)&m->cnt, 4 * 8);
+  if (!ok) return fail_create(PCV_ENOMEM);
+  double* dref = nullptr;
+  if (hipMalloc((void**)&dref, nin * 8) != hipSuccess) return fail_create(PCV_ENOMEM);
+  hipError_t e = hipMemcpy(dref, ref, nin * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->wts, hw.data(), n_atoms * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(ref_centre_kernel, dim3(1), dim3(256), 0, m->stream, dref, m->wts, n_atoms, m->ref_c, m->Ga);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(m->w32, 0, P * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->wbf, 0, P * 2, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->m32, 0, P * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->v32, 0, P * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->judge, 0, 4 * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->cnt, 0, 4 * 8, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  (void)hipFree(dref);
+  if (e != hipSuccess) return fail_create(PCV_EHIP);
+  *out = m;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_destroy(pcv_mlp* m) {
+  if (!m) return PCV_OK;
+  (void)hipSetDevice(m->opt.device);
+  (void)hipStreamSynchronize(m->stream);
+  mlp_drop_graphs(m);
+  m->mem.release();
+  if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  delete m;
+  return PCV_OK;
+}
+
+extern "C" long long pcv_mlp_param_count(const pcv_mlp* m) { return m ? m->P : 0; }
+
+extern "C" pcv_status pcv_mlp_set_params(pcv_mlp* m, const float* params, long long count) {
+  if (!m || !params) return PCV_EINVAL;
+  if (count != m->P) return mfail(m, PCV_EINVAL, "parameter count mismatch");
+  for (long long i = 0; i < count; ++i)
+    if (!std::isfinite(params[i])) return mfail(m, PCV_EINVAL, "parameters must be finite");
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemcpy(m->w32, params, m->P * 4, hipMemcpyHostToDevice));
+  MHIP(m, hipMemset(m->m32, 0, m->P * 4));
+  MHIP(m, hipMemset(m->v32, 0, m->P * 4));
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((m->P + 255) / 256)), dim3(256), 0, m->stream, m->w32, m->wbf,
+                     m->P);
+  MHIP(m, hipGetLastError());
+  MHIP(m, hipStreamSynchronize(m->stream));
+  m->adam_t = 0;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_get_params(pcv_mlp* m, float* params, long long count) {
+  if (!m || !params) return PCV_EINVAL;
+  if (count != m->P) return mfail(m, PCV_EINVAL, "parameter count mismatch");
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemcpy(params, m->w32, m->P * 4, hipMemcpyDeviceToHost));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_get_grads(pcv_mlp* m, float* grads, long long count) {
+  if (!m || !grads) return PCV_EINVAL;
+  if (count != m->P) return mfail(m, PCV_EINVAL, "parameter count mismatch");
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemcpy(grads, m->g32, m->P * 4, hipMemcpyDeviceToHost));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_set_scaling(pcv_mlp* m, const double mean[2], const double sd[2]) {
+  if (!m || !mean || !sd) return PCV_EINVAL;
+  if (!std::isfinite(mean[0]) || !std::isfinite(mean[1]) || !(sd[0] > 0) || !(sd[1] > 0) || !std::isfinite(sd[0]) ||
+      !std::isfinite(sd[1]))
+    return mfail(m, PCV_EINVAL, "scaling must be finite with positive deviations");
+  m->mean[0] = mean[0];
+  m->mean[1] = mean[1];
+  m->sd[0] = sd[0];
+  m->sd[1] = sd[1];
+  mlp_drop_graphs(m);
+  return PCV_OK;
+}
+
+// Forward pass of B rows of BF16 inputs (m->act[0] or the given pointer).
+static hipError_t mlp_forward(pcv_mlp* m, const uint16_t* in, int B, hipStream_t st) {
+  const int H = m->H;
+  for (int l = 0; l < 4; ++l) {
+    GemmArgs g{};
+    g.A = (l == 0) ? in : m->act[l];
+    g.sAi = m->dims[l];
+    g.sAk = 1;
+    g.B = m->wbf + m->off_W[l];
+    g.sBk = m->dims[l + 1];
+    g.sBj = 1;
+    g.M = B;
+    g.N = m->dims[l + 1];
+    g.K = m->dims[l];
+    g.bias = m->w32 + m->off_b[l];
+    if (l < 3) {
+      g.C = m->pre[l];
+      g.ldc = H;
+      g.Cb = m->act[l + 1];
+      g.ldcb = H;
+      MTRY(gemm<EPI_BIAS_SILU>(g, st));
+    } else {
+      g.C = m->y;
+      g.ldc = 2;
+      MTRY(gemm<EPI_BIAS>(g, st));
+    }
+  }
+  return hipSuccess;
+}
+
+// Backward signals for R rows seeded by dy (BF16 [R][2]); row r uses the
+// pre-activations of row r / pre_div.  Leaves d_l (FP32 and BF16) and, when
+// want_input, dX in m->gx.
+static hipError_t mlp_backward(pcv_mlp* m, const uint16_t* dy, int Rr, int pre_div, bool want_input,
+                               hipStream_t st) {
+  const int H = m->H;
+  const uint16_t* dprev = dy;
+  int ldprev = 2;
+  for (int l = 3; l >= 1; --l) {
+    // d_{l-1} = (d_l W_l^T) * silu'(pre_{l-1})
+    GemmArgs g{};
+    g.A = dprev;
+    g.sAi = ldprev;
+    g.sAk = 1;
+    g.B = m->wbf + m->off_W[l];
+    g.sBk = 1;
+    g.sBj = m->dims[l + 1];
+    g.M = Rr;
+    g.N = m->dims[l];
+    g.K = m->dims[l + 1];
+    g.C = m->d32[l - 1];
+    g.ldc = H;
+    g.Cb = m->dbf[l - 1];
+    g.ldcb = H;
+    g.pre = m->pre[l - 1];
+    g.ldpre = H;
+    g.pre_div = pre_div;
+    MTRY(gemm<EPI_SILU_GRAD>(g, st));
+    dprev = m->dbf[l - 1];
+    ldprev = H;
+  }
+  if (want_input) {
+    GemmArgs g{};
+    g.A = m->dbf[0];
+    g.sAi = H;
+    g.sAk = 1;
+    g.B = m->wbf + m->off_W[0];
+    g.sBk = 1;
+    g.sBj = H;
+    g.M = Rr;
+    g.N = m->nin;
+    g.K = H;
+    g.C = m->gx;
+    g.ldc = m->nin;
+    MTRY(gemm<EPI_STORE>(g, st));
+  }
+  return hipSuccess;
+}
+
+extern "C" pcv_status pcv_mlp_align(pcv_mlp* m, const float* x, int B, uint16_t* xa_bf16, float* xa_f32) {
+  if (!m || !x || B < 1) return PCV_EINVAL;
+  if (B > m->maxB) return mfail(m, PCV_ESHAPE, "batch exceeds max_batch");
+  for (int b0 = 0; b0 < B; b0 += m->maxB) {
+    const int nb = std::min(m->maxB, B - b0);
+    hipLaunchKernelGGL(align_kernel, dim3(nb), dim3(256), 0, m->stream, x + (size_t)b0 * m->nin, m->n, m->wts,
+                       m->ref_c, m->Ga, m->alst, xa_f32 ? xa_f32 + (size_t)b0 * m->nin : nullptr,
+                       xa_bf16 ? xa_bf16 + (size_t)b0 * m->nin : nullptr);
+    MHIP(m, hipGetLastError());
+  }
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_forward(pcv_mlp* m, const uint16_t* inputs, int B, float* y_out) {
+  if (!m || !inputs || B < 1) return PCV_EINVAL;
+  if (B > m->maxB) return mfail(m, PCV_ESHAPE, "batch exceeds max_batch");
+  MHIP(m, mlp_forward(m, inputs, B, m->stream));
+  if (y_out) MHIP(m, hipMemcpyAsync(y_out, m->y, (size_t)B * 2 * 4, hipMemcpyDeviceToDevice, m->stream));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_train_step(pcv_mlp* m, const uint16_t* inputs, const float* targets, int B, float lr,
+                                         float* loss) {
+  if (!m || !inputs || !targets || B < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return PCV_EINVAL;
+  if (B > m->maxB) return mfail(m, PCV_ESHAPE, "batch exceeds max_batch");
+  hipStream_t st = m->stream;
+  const int H = m->H;
+  MHIP(m, mlp_forward(m, inputs, B, st));
+  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(1024), 0, st, m->y, targets, B, m->dyb, m->dy32, loss);
+  MHIP(m, hipGetLastError());
+  MHIP(m, mlp_backward(m, m->dyb, B, 1, false, st));
+  // weight gradients dW_l = a_l^T d_l and bias gradients
+  for (int l = 0; l < 4; ++l) {
+    GemmArgs g{};
+    g.A = (l == 0) ? inputs : m->act[l];
+    g.sAi = 1;
+    g.sAk = m->dims[l];
+    g.B = (l == 3) ? m->dyb : m->dbf[l];
+    g.sBk = (l == 3) ? 2 : H;
+    g.sBj = 1;
+    g.M = m->dims[l];
+    g.N = m->dims[l + 1];
+    g.K = B;
+    g.C = m->g32 + m->off_W[l];
+    g.ldc = m->dims[l + 1];
+    MHIP(m, gemm<EPI_STORE>(g, st));
+    const float* dsrc = (l == 3) ? m->dy32 : m->d32[l];
+    const int N = m->dims[l + 1];
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64), dim3(256), 0, st, dsrc, B, N, m->g32 + m->off_b[l]);
+    MHIP(m, hipGetLastError());
+  }
+  m->adam_t += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)m->adam_t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)m->adam_t)));
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->P + 255) / 256)), dim3(256), 0, st, m->w32, m->g32, m->m32,
+                     m->v32, m->wbf, m->P, lr, (float)b1, (float)b2, c1, c2, 1e-8f);
+  MHIP(m, hipGetLastError());
+  return PCV_OK;
+}
+
+// Surrogate values and gradients for B structures (no graph).
+static hipError_t mlp_eval_enqueue(pcv_mlp* m, const float* x, int B, double* sz, float* ds, float* dz,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(align_kernel, dim3(B), dim3(256), 0, st, x, m->n, m->wts, m->ref_c, m->Ga, m->alst, m->xa32,
+                     m->act[0]);
+  MTRY(hipGetLastError());
+  MTRY(mlp_forward(m, m->act[0], B, st));
+  hipLaunchKernelGGL(outputs_kernel, dim3((B + 63) / 64), dim3(64), 0, st, m->y, B, m->mean[0], m->sd[0], m->mean[1],
+                     m->sd[1], sz, m->dyb);
+  MTRY(hipGetLastError());
+  if (ds || dz) {
+    MTRY(mlp_backward(m, m->dyb, 2 * B, 2, true, st));
+    hipLaunchKernelGGL(align_back_kernel, dim3(B), dim3(256), 0, st, x, m->n, m->wts, m->ref_c, m->alst, m->gx, ds,
+                       dz);
+    MTRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename F>
+static pcv_status mlp_run_graph(pcv_mlp* m, const void* const key[8], F&& enqueue) {
+  if (!m->opt.use_graph) {
+    hipError_t e = enqueue(m->stream);
+    return e == hipSuccess ? PCV_OK : mfail(m, PCV_EHIP, std::string("enqueue: ") + hipGetErrorString(e));
+  }
+  for (auto& g : m->graphs)
+    if (std::equal(key, key + 8, g.key)) {
+      MHIP(m, hipGraphLaunch(g.exec, m->stream));
+      return PCV_OK;
+    }
+  hipGraph_t graph = nullptr;
+  MHIP(m, hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue(m->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(m->cap_stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return mfail(m, PCV_EHIP, std::string("capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return mfail(m, PCV_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+  if (m->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(m->graphs.front().exec);
+    m->graphs.erase(m->graphs.begin());
+  }
+  pcv_mlp::GraphEntry ge;
+  std::copy(key, key + 8, ge.key);
+  ge.exec = exec;
+  m->graphs.push_back(ge);
+  MHIP(m, hipGraphLaunch(exec, m->stream));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_eval(pcv_mlp* m, const float* x, int B, double* sz, float* ds_dx, float* dz_dx) {
+  if (!m || !x || !sz || B < 1) return PCV_EINVAL;
+  if (B > m->maxB) return mfail(m, PCV_ESHAPE, "batch exceeds max_batch");
+  const void* key[8] = {x, sz, ds_dx, dz_dx, (const void*)(size_t)B, nullptr, nullptr, (const void*)1};
+  return mlp_run_graph(m, key, [&](hipStream_t st) { return mlp_eval_enqueue(m, x, B, sz, ds_dx, dz_dx, st); });
+}
+
+// ---- fallback step (uses the exact handle's close-structure drift test)
+extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
+                                                       double* sz, void* ds, void* dz, const int** flag);
+
+extern "C" pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, double* sz, float* ds_dx,
+                                   float* dz_dx, int* used_surrogate) {
+  if (!m || !h || !x || !sz) return PCV_EINVAL;
+  const void* key[8] = {x, sz, ds_dx, dz_dx, used_surrogate, h, nullptr, (const void*)2};
+  return mlp_run_graph(m, key, [&](hipStream_t st) -> hipError_t {
+    const int* flag = nullptr;
+    MTRY(pcv_internal_exact_for_surrogate(h, m->n, st, x, sz, ds_dx, dz_dx, &flag));
+    MTRY(mlp_eval_enqueue(m, x, 1, m->sz_s, m->ds_s, m->dz_s, st));
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, flag, m->sz_s, m->ds_s, m->dz_s, m->nin, sz, ds_dx,
+                       dz_dx, used_surrogate, m->judge, m->cnt);
+    return hipGetLastError();
+  });
+}
+
+extern "C" pcv_status pcv_mlp_get_stats(pcv_mlp* m, pcv_mlp_stats* out) {
+  if (!m || !out) return PCV_EINVAL;
+  long long c[4];
+  double j[4];
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemcpy(c, m->cnt, sizeof(c), hipMemcpyDeviceToHost));
+  MHIP(m, hipMemcpy(j, m->judge, sizeof(j), hipMemcpyDeviceToHost));
+  out->steps = c[0];
+  out->surrogate_steps = c[1];
+  out->exact_steps = c[2];
+  out->max_abs_ds = j[0];
+  out->max_abs_dz = j[1];
+  out->mean_abs_ds = c[2] ? j[2] / c[2] : 0.0;
+  out->mean_abs_dz = c[2] ? j[3] / c[2] : 0.0;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_reset_stats(pcv_mlp* m) {
+  if (!m) return PCV_EINVAL;
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemset(m->cnt, 0, 4 * 8));
+  MHIP(m, hipMemset(m->judge, 0, 4 * 8));
+  return PCV_OK;
+}
+
+extern "C" const char* pcv_mlp_last_error(const pcv_mlp* m) { return m ? m->err.c_str() : "null handle"; }

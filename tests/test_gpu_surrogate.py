@@ -1,0 +1,205 @@
+"""GPU parity of the surrogate kernels (BF16 matrix-core GEMMs, alignment and
+its derivative, training step, fallback step) against the FP64 oracle
+(oracle/mlp.py, which rounds GEMM operands to BF16 where the kernels do).
+
+Tolerances: products accumulate in FP32 on the GPU and in FP64 in the
+oracle, so a pre-activation differs by ~1e-6 relative; when such a value
+sits next to a BF16 rounding boundary the two sides round one activation
+to neighbouring BF16 values (0.4 % apart).  Outputs therefore agree to a
+few 1e-4 of their scale; the bounds below allow 2e-3 (values) and 1e-2
+(gradients, which pass three BF16-rounded backward signals)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as om
+from oracle.close import CloseStructure
+from oracle.path import landmark_lambda, path_cv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def _setup(n=20, hidden=64, seed=1, max_batch=64):
+    import paper_1801_02362_amd as pcv
+    s = wl.small_path(n, 30, 50 + seed, dtype=np.float32)
+    ref = s.landmarks[0].astype(np.float64)
+    sizes = wl.mlp_sizes(n, hidden)
+    params = wl.mlp_init(sizes, seed)
+    sur = pcv.Surrogate(ref, hidden=hidden, max_batch=max_batch, use_graph=False)
+    sur.set_params(params)
+    W, b = wl.mlp_unflatten(params.astype(np.float64), sizes)
+    net = om.MLP(W, b, mean=np.array([12.0, 0.002]), std=np.array([6.0, 0.003]))
+    sur.set_scaling(net.mean, net.std)
+    return s, ref, sur, net, params, sizes
+
+
+def _bf16_values(t):
+    """Float64 values of a tensor of BF16 bit patterns (int16)."""
+    b = t.detach().cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
+
+
+def _frames(s, k, seed, sigma=0.03):
+    rng = np.random.default_rng(seed)
+    base = s.waypoints[0]
+    return (base[None] + rng.normal(0, sigma, (k,) + base.shape)).astype(np.float32)
+
+
+def test_alignment_matches_oracle(torch):
+    from gpu_util import dev, host
+    s, ref, sur, net, _, _ = _setup()
+    X = _frames(s, 5, 2)
+    _, xa = sur.align(dev(X, torch.float32), bf16=False, f32=True)
+    xa = host(xa)
+    for k in range(5):
+        xp, _ = om.align(X[k].astype(np.float64), ref)
+        assert np.abs(xa[k] - xp.reshape(-1)).max() < 2e-6
+    sur.close()
+
+
+def test_forward_matches_oracle(torch):
+    from gpu_util import dev, host
+    s, ref, sur, net, _, _ = _setup(n=40, hidden=128, seed=3)
+    X = _frames(s, 33, 4)
+    xb, _ = sur.align(dev(X, torch.float32))
+    y = host(sur.forward(xb))
+    inputs = _bf16_values(xb)
+    ref_y = om.forward(net, inputs, rounded=True)["y"]
+    scale = np.abs(ref_y).max()
+    assert np.abs(y - ref_y).max() <= 2e-3 * scale
+    sur.close()
+
+
+@pytest.mark.parametrize("n,hidden", [(20, 64), (37, 96)])
+def test_values_and_gradients_match_oracle(torch, n, hidden):
+    from gpu_util import dev, host
+    s, ref, sur, net, _, _ = _setup(n=n, hidden=hidden, seed=5)
+    X = _frames(s, 4, 6)
+    o = sur.eval(dev(X, torch.float32))
+    sz, gs, gz = host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"])
+    for k in range(4):
+        rs, rz, rgs, rgz = om.surrogate(net, X[k].astype(np.float64), ref, rounded=True)
+        assert abs(sz[k, 0] - rs) <= 2e-3 * net.std[0]
+        assert abs(sz[k, 1] - rz) <= 2e-3 * net.std[1]
+        assert np.abs(gs[k] - rgs).max() <= 1e-2 * np.abs(rgs).max()
+        assert np.abs(gz[k] - rgz).max() <= 1e-2 * np.abs(rgz).max()
+        # a function of the aligned structure: no net force, no net torque
+        xc = X[k] - X[k].mean(0)
+        for g in (gs[k], gz[k]):
+            assert np.abs(g.sum(0)).max() <= 1e-4 * np.abs(g).max() * n
+            assert np.abs(np.cross(xc, g).sum(0)).max() <= 1e-3 * np.abs(g).max() * n
+    sur.close()
+
+
+def test_graph_replay_matches_eager(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev, host
+    s, ref, sur, net, params, _ = _setup(n=20, hidden=64, seed=7)
+    X = dev(_frames(s, 3, 8), torch.float32)
+    eager = sur.eval(X)
+    g = pcv.Surrogate(ref, hidden=64, max_batch=64, use_graph=True)
+    g.set_params(params)
+    g.set_scaling(net.mean, net.std)
+    out = {"sz": torch.empty(3, 2, dtype=torch.float64, device="cuda"),
+           "ds_dx": torch.empty_like(X), "dz_dx": torch.empty_like(X)}
+    for _ in range(3):
+        r = g.eval(X, out=out)
+        for key in ("sz", "ds_dx", "dz_dx"):
+            assert np.array_equal(host(r[key]), host(eager[key]))
+    g.close()
+    sur.close()
+
+
+def test_training_step_matches_oracle(torch):
+    from gpu_util import dev, host
+    s, ref, sur, net, params, sizes = _setup(n=24, hidden=64, seed=9)
+    X = _frames(s, 48, 10)
+    xb, _ = sur.align(dev(X, torch.float32))
+    rng = np.random.default_rng(11)
+    T = rng.normal(0, 1, (48, 2)).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    sur.train_step(xb, dev(T, torch.float32), lr, loss)
+    inputs = _bf16_values(xb)
+    cache = om.forward(net, inputs, rounded=True)
+    ref_loss, dy = om.loss_and_grad(cache["y"], T)
+    assert abs(host(loss)[0] - ref_loss) <= 2e-3 * ref_loss
+    dW, db = om.param_grads(net, cache, dy, rounded=True)
+    gW, gb = wl.mlp_unflatten(sur.grads().astype(np.float64), sizes)
+    for l in range(4):
+        assert np.abs(gW[l] - dW[l]).max() <= 1e-2 * np.abs(dW[l]).max()
+        assert np.abs(gb[l] - db[l]).max() <= 1e-2 * np.abs(db[l]).max() + 1e-7
+    # Adam's first step moves each weight by lr * sign(g) where |g| >> eps
+    newW, newb = wl.mlp_unflatten(sur.params().astype(np.float64), sizes)
+    for l in range(4):
+        w1, _, _ = om.adam_step(net.W[l], dW[l], 0.0 * dW[l], 0.0 * dW[l], 1, lr)
+        big = np.abs(dW[l]) > 1e-3 * np.abs(dW[l]).max()
+        assert np.abs(newW[l][big] - w1[big]).max() <= 1e-6 + 1e-6 * np.abs(w1[big]).max()
+    sur.close()
+
+
+def test_training_reduces_the_loss(torch):
+    from gpu_util import dev, host
+    s, ref, sur, net, params, sizes = _setup(n=24, hidden=64, seed=12, max_batch=256)
+    X = _frames(s, 256, 13, sigma=0.05)
+    xb, _ = sur.align(dev(X, torch.float32))
+    # a smooth target of the aligned coordinates
+    xa = _bf16_values(xb)
+    T = np.stack([np.tanh(xa[:, :6].sum(1)), np.cos(xa[:, 6:12].sum(1))], 1).astype(np.float32)
+    T = (T - T.mean(0)) / T.std(0)
+    Td = dev(T, torch.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for it in range(300):
+        sur.train_step(xb, Td, 3e-3, loss)
+        if it % 50 == 0 or it == 299:
+            losses.append(float(host(loss)[0]))
+    assert losses[-1] < 0.1 * losses[0], losses
+    sur.close()
+
+
+def test_fallback_step_follows_the_drift_test(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import TOL32, dev, host
+    n, L = 20, 30
+    s, ref, sur, net, params, _ = _setup(n=n, hidden=64, seed=14)
+    lam = landmark_lambda(s.landmarks)
+    eps = 0.002
+    exact = pcv.PathCV(dev(s.landmarks, torch.float32), lam, eps=eps)
+    walk = wl.random_walk(s.waypoints[0].astype(np.float32), 60, rng=np.random.default_rng(15))
+    orc = CloseStructure(s.landmarks.astype(np.float64), lam, eps)
+    x = torch.empty(n, 3, dtype=torch.float32, device="cuda")
+    used_steps = exact_steps = 0
+    errs = []
+    for t in range(len(walk)):
+        x.copy_(torch.as_tensor(walk[t]))
+        o = sur.step(exact, x)
+        step = orc.step(walk[t].astype(np.float64))
+        used = int(host(o["used"])[0])
+        assert used == (0 if step.recomputed else 1), t
+        if used:
+            used_steps += 1
+            rs, rz, rgs, _ = om.surrogate(net, walk[t].astype(np.float64), ref, rounded=True)
+            assert abs(host(o["sz"])[0] - rs) <= 2e-3 * net.std[0]
+            assert np.abs(host(o["ds_dx"]) - rgs).max() <= 1e-2 * np.abs(rgs).max()
+        else:
+            exact_steps += 1
+            ref_ex = path_cv(walk[t].astype(np.float64), s.landmarks.astype(np.float64), lam)
+            assert abs(host(o["sz"])[0] - ref_ex.s) <= TOL32["sz"]
+            rs, _, _, _ = om.surrogate(net, walk[t].astype(np.float64), ref, rounded=True)
+            errs.append(abs(rs - ref_ex.s))
+    st = sur.stats()
+    assert st["steps"] == len(walk)
+    assert st["surrogate_steps"] == used_steps and st["exact_steps"] == exact_steps
+    assert exact_steps >= 1 and used_steps >= 1
+    assert abs(st["max_abs_ds"] - max(errs)) <= 2e-3 * net.std[0]
+    ex = exact.stats()
+    assert ex["recomputes"] == exact_steps
+    exact.close()
+    sur.close()

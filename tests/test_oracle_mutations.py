@@ -80,3 +80,53 @@ def test_wrong_path_gradient_sign_is_caught(monkeypatch):
     xm = x.copy(); xm[2, 1] -= h
     fd = (op.path_cv(xp, A, lam, grad=False).s - op.path_cv(xm, A, lam, grad=False).s) / (2 * h)
     assert abs(r.ds_dx[2, 1] - fd) > 1e-6 * max(1.0, abs(fd))
+
+
+# ---- surrogate oracle (oracle/mlp.py)
+import oracle.mlp as om5
+
+
+def _surrogate_pins_hold():
+    n = 6
+    s = wl.small_path(n, 2, 21, dtype=np.float64)
+    ref = s.landmarks[0]
+    x = s.waypoints[1] + np.random.default_rng(22).normal(0, 0.05, (n, 3))
+    rng = np.random.default_rng(23)
+    sizes = [3 * n, 5, 5, 4, 2]
+    net = om5.MLP([rng.normal(0, 1 / np.sqrt(a), (a, b)) for a, b in zip(sizes[:-1], sizes[1:])],
+                  [rng.normal(0, 0.1, (b,)) for b in sizes[1:]])
+    _, _, gs, _ = om5.surrogate(net, x, ref, rounded=False)
+    f = om5.surrogate_fd_check_fn(net, ref)
+    h = 1e-6
+    fd = np.zeros_like(x)
+    for k in range(n):
+        for c in range(3):
+            xp = x.copy(); xp[k, c] += h
+            xm = x.copy(); xm[k, c] -= h
+            fd[k, c] = (f(xp)[0] - f(xm)[0]) / (2 * h)
+    return np.abs(gs - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_surrogate_pins_hold_unmutated():
+    assert _surrogate_pins_hold()
+
+
+def test_wrong_silu_derivative_is_caught(monkeypatch):
+    monkeypatch.setattr(om5, "silu_grad", lambda v: 1.0 / (1.0 + np.exp(-np.asarray(v))))
+    assert not _surrogate_pins_hold()
+
+
+def test_dropped_alignment_rotation_term_is_caught(monkeypatch):
+    monkeypatch.setattr(om5, "rotation_term", lambda Gamma, a_c, wp: np.zeros(a_c.shape))
+    assert not _surrogate_pins_hold()
+
+
+def test_untransposed_backward_weight_is_caught(monkeypatch):
+    orig = om5.input_grad
+
+    def bad(net, cache, dy, *, rounded=True):
+        ds = om5._backward(net, cache, dy, rounded)
+        W0 = net.W[0]
+        return ds[0] @ np.resize(W0, (W0.shape[1], W0.shape[0]))
+    monkeypatch.setattr(om5, "input_grad", bad)
+    assert not _surrogate_pins_hold()

@@ -35,7 +35,8 @@ N_CONFIGS = 5
 __all__ = [
     "ROOT_SEED", "PathSystem", "Walker", "config_rng", "path_system",
     "random_walk", "cfg0", "cfg1", "cfg2", "cfg2_frames", "cfg3",
-    "cfg4_training_walks", "small_path", "rigid_copy",
+    "cfg4_training_walks", "small_path", "rigid_copy", "mlp_sizes", "mlp_init", "mlp_unflatten",
+    "minibatch_order",
 ]
 
 
@@ -200,3 +201,37 @@ def rigid_copy(x: np.ndarray, seed: int, translate: float = 1.0) -> tuple[np.nda
     rot = _haar(rng, 1)[0]
     shift = rng.uniform(-translate, translate, size=3)
     return x @ rot.T + shift, rot, shift
+
+
+# ---- surrogate network parameters (random draws and layout only)
+def mlp_sizes(n_atoms: int, hidden: int = 512) -> list[int]:
+    """Layer widths of the surrogate: 3n -> H -> H -> H -> 2."""
+    return [3 * n_atoms, hidden, hidden, hidden, 2]
+
+
+def mlp_init(sizes: list[int], seed: int) -> np.ndarray:
+    """Flat FP32 initial parameters: for each layer W [fan_in][fan_out]
+    drawn N(0, 1/fan_in), then a zero bias [fan_out]."""
+    rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 4, seed]))
+    parts = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        parts.append(rng.normal(0.0, 1.0 / np.sqrt(a), (a, b)).astype(np.float32).ravel())
+        parts.append(np.zeros(b, dtype=np.float32))
+    return np.concatenate(parts)
+
+
+def mlp_unflatten(flat: np.ndarray, sizes: list[int]) -> tuple[list[np.ndarray], list[np.ndarray]]:
+    """Split a flat parameter array into per-layer W [fan_in][fan_out] and b."""
+    W, b, o = [], [], 0
+    for a, c in zip(sizes[:-1], sizes[1:]):
+        W.append(np.asarray(flat[o:o + a * c]).reshape(a, c))
+        o += a * c
+        b.append(np.asarray(flat[o:o + c]))
+        o += c
+    assert o == len(flat)
+    return W, b
+
+
+def minibatch_order(n: int, epoch: int, seed: int = 0) -> np.ndarray:
+    """Seeded permutation of n training rows for one epoch."""
+    return np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 4, 1000 + seed, epoch])).permutation(n)
