@@ -13,8 +13,11 @@ duration from HIP events recorded on its own stream) and ``cpu_baseline``
 (the FP64 oracle on a bounded sample of the same workload, host cores).
 
 Other workloads: ``--workload close`` (300 atoms x 500 landmarks, Algorithm 2
-along a random walk, steps/s) and ``--workload batch`` (64 uneven walkers in
-one persistent launch).
+along a random walk, steps/s), ``--workload batch`` (64 uneven walkers in one
+persistent launch), ``--workload surrogate`` (train the MLP surrogate on
+exact-labelled walks, then compare exact, close-structure and surrogate
+steps/s and |ds| on the test walk) and ``--workload copy`` (a plain device
+copy used to calibrate the traffic counters).
 """
 from __future__ import annotations
 
@@ -238,6 +241,145 @@ def bench_batch(args):
     return out
 
 
+def bench_surrogate(args):
+    """Learned surrogate on the 300-atom, 500-landmark path: train on
+    exact-labelled random walks (GPU), then run the test walk three ways
+    (exact every step, the paper's close structure, surrogate with the
+    close-structure drift test as fallback) and report steps/s and |ds|."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    from paper_1801_02362_amd import surrogate as sg
+    import workloads as wl
+    dev = torch.device("cuda", 0)
+    K = args.test_frames
+    sysm, walk = wl.cfg1(K)
+    n = sysm.n_atoms
+    lm = torch.as_tensor(sysm.landmarks, device=dev)
+    probe = pcv.PathCV(lm, None, eps=args.eps)
+    lam = probe.lam
+    probe.close()
+    t_start = time.perf_counter()
+    log(f"[surrogate] generating {args.train_walks} x {args.train_steps} training frames")
+    frames = wl.cfg4_training_walks(args.train_walks, args.train_steps, sysm)
+    frames = frames[wl.minibatch_order(frames.shape[0], 0)]
+    fd = torch.as_tensor(frames, device=dev)
+    del frames
+    t_gen = time.perf_counter() - t_start
+    t0 = time.perf_counter()
+    labels = sg.exact_labels(lm, lam, fd)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    mean, sd = sg.standardise(labels)
+    targets = ((labels - torch.as_tensor(mean, device=dev)) / torch.as_tensor(sd, device=dev)).float().contiguous()
+    sur = pcv.Surrogate(sysm.landmarks[0].astype(np.float64), hidden=args.hidden, max_batch=args.batch)
+    sur.set_params(wl.mlp_init(wl.mlp_sizes(n, args.hidden), 0))
+    sur.set_scaling(mean, sd)
+    inputs = sg.aligned_inputs(sur, fd)
+    del fd
+    F = int(inputs.shape[0])
+    n_val = max(args.batch, F // 50)
+    n_tr = F - n_val
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = sg.train(sur, inputs[:n_tr], targets[:n_tr], epochs=args.epochs, batch=args.batch, lr=args.lr,
+                    lr_final=args.lr * 0.02, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val = sg.test_loss(sur, inputs[n_tr:], targets[n_tr:])
+    log(f"[surrogate] trained {args.epochs} epochs in {t_train:.1f} s; validation loss {val:.3e}")
+    del inputs, targets, labels
+
+    walk_dev = torch.as_tensor(walk, device=dev)
+    x = torch.empty(n, 3, dtype=torch.float32, device=dev)
+
+    def timed(fn, steps):
+        for t in range(min(args.warmup, steps)):
+            x.copy_(walk_dev[t])
+            fn(x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for t in range(steps):
+            x.copy_(walk_dev[t])
+            fn(x)
+        torch.cuda.synchronize()
+        return steps / (time.perf_counter() - t1)
+
+    def recorded(fn, steps):
+        out = torch.empty(steps, 2, dtype=torch.float64, device=dev)
+        for t in range(steps):
+            x.copy_(walk_dev[t])
+            out[t].copy_(fn(x)["sz"])
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    ex = pcv.PathCV(lm, lam, eps=args.eps)
+    sps_exact = timed(lambda v: ex.eval(v, grad=True), K)
+    s_exact = recorded(lambda v: ex.eval(v, grad=True), K)
+    cl = pcv.PathCV(lm, lam, eps=args.eps)
+    sps_close = timed(lambda v: cl.eval_close(v), K)
+    cl.reset_stats()
+    cl2 = pcv.PathCV(lm, lam, eps=args.eps)
+    s_close = recorded(lambda v: cl2.eval_close(v), K)
+    st_close = cl2.stats()
+    so = {"sz": torch.empty(2, dtype=torch.float64, device=dev), "ds_dx": torch.empty_like(x),
+          "dz_dx": torch.empty_like(x), "used": torch.empty(1, dtype=torch.int32, device=dev)}
+    fb = pcv.PathCV(lm, lam, eps=args.eps)
+    sps_sur = timed(lambda v: sur.step(fb, v, out=so), K)
+    fb2 = pcv.PathCV(lm, lam, eps=args.eps)
+    sur.reset_stats()
+    s_sur = recorded(lambda v: sur.step(fb2, v, out=so), K)
+    st_sur = sur.stats()
+
+    def err(a):
+        d = np.abs(a[:, 0] - s_exact[:, 0])
+        return {"max": float(d.max()), "p99": float(np.quantile(d, 0.99)), "mean": float(d.mean()),
+                "frac_le_1e-3": float((d <= 1e-3).mean())}
+
+    # batched inference: many structures at once (frames of the test walk)
+    B = min(args.batch, K)
+    xb = walk_dev[:B].contiguous()
+    ob = sur.eval(xb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        sur.eval(xb, out=ob)
+    torch.cuda.synchronize()
+    sur_batched = 20 * B / (time.perf_counter() - t1)
+    bx = pcv.BatchPathCV([lm] * B, [lam] * B)
+    xall = xb.reshape(B * n, 3)
+    bx.eval(xall)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        bx.eval(xall)
+    torch.cuda.synchronize()
+    exact_batched = 20 * B / (time.perf_counter() - t1)
+    for h in (ex, cl, cl2, fb, fb2, bx):
+        h.close()
+    e_sur, e_close = err(s_sur), err(s_close)
+    out = {"metric": "surrogate+fallback steps/s", "value": round(sps_sur, 1), "unit": "steps/s", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": round(1e3 / sps_sur, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 MFMA (fp32 accumulate); fp64 alignment",
+           "data": "synthetic",
+           "config": {"workload": f"surrogate on the 300-atom x 500-landmark path, {K}-frame test walk, "
+                                  f"eps {args.eps} nm^2, trained on {F} exact-labelled walk frames",
+                      "exact_steps_per_s": round(sps_exact, 1), "close_steps_per_s": round(sps_close, 1),
+                      "surrogate_steps_per_s": round(sps_sur, 1),
+                      "surrogate_fraction": round(st_sur["surrogate_steps"] / max(1, st_sur["steps"]), 4),
+                      "ds_surrogate_vs_exact": e_sur, "ds_close_vs_exact": e_close,
+                      "meets_ds_1e-3": bool(e_sur["max"] <= 1e-3),
+                      "close_recomputes": st_close["recomputes"], "judge": st_sur,
+                      "batched": {"frames": B, "surrogate_frames_per_s": round(sur_batched, 1),
+                                  "exact_frames_per_s": round(exact_batched, 1)},
+                      "training": {"frames": F, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                                   "hidden": args.hidden, "seconds": round(t_train, 2),
+                                   "label_seconds": round(t_label, 2), "generate_seconds": round(t_gen, 2),
+                                   "epoch_loss": [round(v, 5) for v in hist], "validation_loss": val}}}
+    sur.close()
+    return out
+
+
 def bench_copy(args):
     """Plain device-to-device copy of a known size (counter calibration)."""
     import torch
@@ -264,7 +406,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy"], default="exact")
+    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate"], default="exact")
+    ap.add_argument("--train-walks", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=10000)
+    ap.add_argument("--test-frames", type=int, default=10000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--copy-mb", type=float, default=600.0)
     ap.add_argument("--atoms", type=int, default=5000)
     ap.add_argument("--landmarks", type=int, default=10000)
@@ -282,6 +432,8 @@ def main():
         out = bench_close(args)
     elif args.workload == "copy":
         out = bench_copy(args)
+    elif args.workload == "surrogate":
+        out = bench_surrogate(args)
     else:
         out = bench_batch(args)
     print(json.dumps(out), flush=True)

@@ -261,8 +261,9 @@ typedef struct pcv_mlp pcv_mlp;
 typedef struct pcv_mlp_stats {
   int64_t steps;            /* pcv_mlp_step calls */
   int64_t surrogate_steps;  /* answered by the surrogate (drift <= epsilon) */
-  int64_t exact_steps;      /* answered exactly (drift > epsilon, first step, forced) and judged */
-  double max_abs_ds;        /* judge: max |s_surrogate - s_exact| over exact steps */
+  int64_t exact_steps;      /* answered exactly (drift > epsilon, first step, forced) */
+  int64_t judged_steps;     /* exact steps that had an anchor: the surrogate's answer was judged */
+  double max_abs_ds;        /* judge: max |s_surrogate - s_exact| over judged steps */
   double max_abs_dz;
   double mean_abs_ds;
   double mean_abs_dz;
@@ -321,7 +322,9 @@ pcv_status pcv_mlp_eval(pcv_mlp* m, const float* x, int B, double* sz, float* ds
  * place of Eq. 5): the exact handle h (FP32, same n) superposes its close
  * structure y onto x; if D(x, y) > epsilon (or on its first step / when
  * forced) the exact path answers, y <- x, and the surrogate's error on this
- * frame is recorded (the judge); otherwise the surrogate answers.
+ * frame is recorded (the judge); otherwise the surrogate answers, anchored on
+ * the last exact step: s = f_s(x) + (s_exact(y) - f_s(y)), likewise z
+ * (before the first exact step, f(x) itself).  Gradients are the network's.
  *   x      device [n][3];  sz device double[2];  ds_dx, dz_dx device [n][3] or NULL
  *   used_surrogate   device int or NULL: 1 surrogate, 0 exact
  * The decision stays on the device (no host synchronisation).

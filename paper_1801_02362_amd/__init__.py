@@ -45,7 +45,7 @@ class _Stats(ctypes.Structure):
 
 class _MlpStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("surrogate_steps", ctypes.c_int64), ("exact_steps", ctypes.c_int64),
-                ("max_abs_ds", ctypes.c_double), ("max_abs_dz", ctypes.c_double),
+                ("judged_steps", ctypes.c_int64), ("max_abs_ds", ctypes.c_double), ("max_abs_dz", ctypes.c_double),
                 ("mean_abs_ds", ctypes.c_double), ("mean_abs_dz", ctypes.c_double)]
 
 

@@ -43,7 +43,7 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 
 __device__ __forceinline__ float sigm(float v) { return 1.0f / (1.0f + expf(-v)); }
 
-enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_SILU_GRAD = 3 };
+enum Epi { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_SILU = 2, EPI_SILU_GRAD = 3, EPI_PARTIAL = 4 };
 
 // C[M][N] = A[M][K] B[K][N] with A(i,k) = A[i sAi + k sAk] and
 // B(k,j) = B[k sBk + j sBj] (BF16), so one kernel serves the forward
@@ -62,7 +62,31 @@ struct GemmArgs {
   const float* bias; // [N]
   const float* pre;  // EPI_SILU_GRAD: pre-activation of row i / pre_div
   int ldpre, pre_div;
+  float* part;       // split-K partial sums [splits][M][N] (EPI_PARTIAL)
+  int kc;            // split-K: K range per split (multiple of 16)
 };
+
+// Epilogue of element (i, j) with accumulated value v.
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float v) {
+  if (EPI == EPI_STORE) {
+    g.C[(long long)i * g.ldc + j] = v;
+  } else if (EPI == EPI_BIAS) {
+    g.C[(long long)i * g.ldc + j] = v + g.bias[j];
+  } else if (EPI == EPI_BIAS_SILU) {
+    const float p = v + g.bias[j];
+    g.C[(long long)i * g.ldc + j] = p;
+    g.Cb[(long long)i * g.ldcb + j] = f2bf(p * sigm(p));
+  } else if (EPI == EPI_SILU_GRAD) {
+    const float p = g.pre[(long long)(i / g.pre_div) * g.ldpre + j];
+    const float sg = sigm(p);
+    const float d = v * (sg * (1.0f + p * (1.0f - sg)));
+    g.C[(long long)i * g.ldc + j] = d;
+    g.Cb[(long long)i * g.ldcb + j] = f2bf(d);
+  } else {
+    g.part[((long long)blockIdx.z * g.M + i) * g.N + j] = v;
+  }
+}
 
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
@@ -77,14 +101,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   for (int t = 0; t < 4; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
   const bool a_rows_fast = (g.sAi == 1);
   const bool b_cols_fast = (g.sBj == 1);
-  for (int k0 = 0; k0 < g.K; k0 += kTK) {
+  const int kbeg = (EPI == EPI_PARTIAL) ? (int)blockIdx.z * g.kc : 0;
+  const int kend = (EPI == EPI_PARTIAL) ? min(g.K, kbeg + g.kc) : g.K;
+  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int r = a_rows_fast ? (e % kTM) : (e / kTK);
       const int c = a_rows_fast ? (e / kTM) : (e % kTK);
       const int i = m0 + r, k = k0 + c;
-      As[r][c] = (i < g.M && k < g.K) ? g.A[(long long)i * g.sAi + (long long)k * g.sAk] : (uint16_t)0;
+      As[r][c] = (i < g.M && k < kend) ? g.A[(long long)i * g.sAi + (long long)k * g.sAk] : (uint16_t)0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -92,7 +118,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
       const int r = b_cols_fast ? (e / kTN) : (e % kTK);
       const int c = b_cols_fast ? (e % kTN) : (e / kTK);
       const int k = k0 + r, j = n0 + c;
-      Bs[r][c] = (k < g.K && j < g.N) ? g.B[(long long)k * g.sBk + (long long)j * g.sBj] : (uint16_t)0;
+      Bs[r][c] = (k < kend && j < g.N) ? g.B[(long long)k * g.sBk + (long long)j * g.sBj] : (uint16_t)0;
     }
     __syncthreads();
     s4v a;
@@ -114,29 +140,45 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
       const int i = m0 + 16 * wave + 4 * (lane >> 4) + r;
       const int j = n0 + 16 * t + (lane & 15);
       if (i >= g.M || j >= g.N) continue;
-      const float v = acc[t][r];
-      if (EPI == EPI_STORE) {
-        g.C[(long long)i * g.ldc + j] = v;
-      } else if (EPI == EPI_BIAS) {
-        g.C[(long long)i * g.ldc + j] = v + g.bias[j];
-      } else if (EPI == EPI_BIAS_SILU) {
-        const float p = v + g.bias[j];
-        g.C[(long long)i * g.ldc + j] = p;
-        g.Cb[(long long)i * g.ldcb + j] = f2bf(p * sigm(p));
-      } else {
-        const float p = g.pre[(long long)(i / g.pre_div) * g.ldpre + j];
-        const float sg = sigm(p);
-        const float d = v * (sg * (1.0f + p * (1.0f - sg)));
-        g.C[(long long)i * g.ldc + j] = d;
-        g.Cb[(long long)i * g.ldcb + j] = f2bf(d);
-      }
+      epilogue<EPI>(g, i, j, acc[t][r]);
     }
   }
 }
 
+// Split-K second stage: fixed-order sum of the partials, then the epilogue.
 template <int EPI>
-hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int splits) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)g.M * g.N) return;
+  const int i = (int)(e / g.N), j = (int)(e % g.N);
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += g.part[((long long)z * g.M + i) * g.N + j];
+  epilogue<EPI>(g, i, j, v);
+}
+
+constexpr int kMaxSplits = 16;
+
+// Batches that fit one 64-row tile split K over up to 16 workgroups per
+// column tile (partials in g.part, then a deterministic reduction), so a
+// single structure's pass is not serialised over the whole K loop.
+template <int EPI>
+hipError_t gemm(GemmArgs g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int kt = (g.K + kTK - 1) / kTK;
+  if (g.M <= kTM && g.part != nullptr && kt >= 8) {
+    const int splits = std::min(kMaxSplits, (kt + 3) / 4);
+    g.kc = ((kt + splits - 1) / splits) * kTK;
+    const int used = (g.K + g.kc - 1) / g.kc;
+    dim3 grid((g.N + kTN - 1) / kTN, 1, used);
+    hipLaunchKernelGGL((gemm_bf16_kernel<EPI_PARTIAL>), grid, dim3(256), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long total = (long long)g.M * g.N;
+    hipLaunchKernelGGL((splitk_reduce_kernel<EPI>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
+                       used);
+    return hipGetLastError();
+  }
+  g.kc = g.K;
   dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
   hipLaunchKernelGGL((gemm_bf16_kernel<EPI>), grid, dim3(256), 0, st, g);
   return hipGetLastError();
@@ -376,23 +418,30 @@ __global__ __launch_bounds__(256) void align_back_kernel(const float* __restrict
   }
 }
 
-// Fallback step tail: on a surrogate step (flag 0) the surrogate's outputs
-// become the step's outputs; on an exact step (flag 1) they are compared with
-// the exact ones (the judge); flag -1 (bad input) leaves everything.
+// Fallback step tail.  The surrogate is anchored on the last exactly
+// evaluated structure y: its answer is f(x) + (exact(y) - f(y)), so errors
+// of the network that vary slowly over the drift radius cancel.  On a
+// surrogate step (flag 0) the anchored values become the step's outputs
+// (gradients are the network's); on an exact step (flag 1) the anchored
+// prediction the surrogate would have given is compared with the exact
+// values (the judge) and the anchor moves to this structure; flag -1 (bad
+// input) leaves everything.  anchor = {valid, offset_s, offset_z}.
 __global__ __launch_bounds__(256) void select_kernel(const int* __restrict__ flag, const double* __restrict__ sz_s,
                                                      const float* __restrict__ ds_s, const float* __restrict__ dz_s,
                                                      int n3, double* __restrict__ sz, float* __restrict__ ds,
                                                      float* __restrict__ dz, int* __restrict__ used,
-                                                     double* __restrict__ judge, long long* __restrict__ cnt) {
+                                                     double* __restrict__ anchor, double* __restrict__ judge,
+                                                     long long* __restrict__ cnt) {
   const int f = *flag;
+  const bool valid = anchor[0] != 0.0;
   if (f == 0) {
     for (int e = threadIdx.x; e < n3; e += 256) {
       if (ds) ds[e] = ds_s[e];
       if (dz) dz[e] = dz_s[e];
     }
     if (threadIdx.x == 0) {
-      sz[0] = sz_s[0];
-      sz[1] = sz_s[1];
+      sz[0] = sz_s[0] + (valid ? anchor[1] : 0.0);
+      sz[1] = sz_s[1] + (valid ? anchor[2] : 0.0);
     }
   }
   if (threadIdx.x == 0) {
@@ -400,12 +449,18 @@ __global__ __launch_bounds__(256) void select_kernel(const int* __restrict__ fla
     cnt[0] += 1;                          // steps
     if (f == 0) cnt[1] += 1;              // surrogate steps
     if (f == 1) {
-      cnt[2] += 1;                        // exact (judged) steps
-      const double es = fabs(sz_s[0] - sz[0]), ez = fabs(sz_s[1] - sz[1]);
-      judge[0] = fmax(judge[0], es);
-      judge[1] = fmax(judge[1], ez);
-      judge[2] += es;
-      judge[3] += ez;
+      cnt[2] += 1;                        // exact steps
+      if (valid) {
+        cnt[3] += 1;                      // judged steps
+        const double es = fabs(sz_s[0] + anchor[1] - sz[0]), ez = fabs(sz_s[1] + anchor[2] - sz[1]);
+        judge[0] = fmax(judge[0], es);
+        judge[1] = fmax(judge[1], ez);
+        judge[2] += es;
+        judge[3] += ez;
+      }
+      anchor[0] = 1.0;
+      anchor[1] = sz[0] - sz_s[0];
+      anchor[2] = sz[1] - sz_s[1];
     }
   }
 }
@@ -439,7 +494,8 @@ struct pcv_mlp {
   float* d32[3] = {nullptr, nullptr, nullptr};
   uint16_t* dbf[3] = {nullptr, nullptr, nullptr};
   float* gx = nullptr;
-  double *sz_s = nullptr, *judge = nullptr;
+  double *sz_s = nullptr, *judge = nullptr, *anchor = nullptr;
+  float* part = nullptr;   // split-K partials: kMaxSplits x 64 rows x max width
   float *ds_s = nullptr, *dz_s = nullptr;
   long long* cnt = nullptr;
   struct GraphEntry {
@@ -549,6 +605,8 @@ extern "C" pcv_status pcv_mlp_create(pcv_mlp** out, const pcv_options* opt, int 
   A((void**)&m->dz_s, nin * 4);
   A((void**)&m->judge, 4 * 8);
   A((void**)&m->cnt, 4 * 8);
+  A((void**)&m->anchor, 3 * 8);
+  A((void**)&m->part, (size_t)kMaxSplits * 64 * std::max<size_t>(nin, H) * 4);
   if (!ok) return fail_create(PCV_ENOMEM);
   double* dref = nullptr;
   if (hipMalloc((void**)&dref, nin * 8) != hipSuccess) return fail_create(PCV_ENOMEM);
@@ -564,6 +622,7 @@ extern "C" pcv_status pcv_mlp_create(pcv_mlp** out, const pcv_options* opt, int 
   if (e == hipSuccess) e = hipMemsetAsync(m->v32, 0, P * 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->judge, 0, 4 * 8, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->cnt, 0, 4 * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->anchor, 0, 3 * 8, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   (void)hipFree(dref);
   if (e != hipSuccess) return fail_create(PCV_EHIP);
@@ -635,6 +694,7 @@ static hipError_t mlp_forward(pcv_mlp* m, const uint16_t* in, int B, hipStream_t
   const int H = m->H;
   for (int l = 0; l < 4; ++l) {
     GemmArgs g{};
+    g.part = m->part;
     g.A = (l == 0) ? in : m->act[l];
     g.sAi = m->dims[l];
     g.sAk = 1;
@@ -671,6 +731,7 @@ static hipError_t mlp_backward(pcv_mlp* m, const uint16_t* dy, int Rr, int pre_d
   for (int l = 3; l >= 1; --l) {
     // d_{l-1} = (d_l W_l^T) * silu'(pre_{l-1})
     GemmArgs g{};
+    g.part = m->part;
     g.A = dprev;
     g.sAi = ldprev;
     g.sAk = 1;
@@ -693,6 +754,7 @@ static hipError_t mlp_backward(pcv_mlp* m, const uint16_t* dy, int Rr, int pre_d
   }
   if (want_input) {
     GemmArgs g{};
+    g.part = m->part;
     g.A = m->dbf[0];
     g.sAi = H;
     g.sAk = 1;
@@ -743,6 +805,7 @@ extern "C" pcv_status pcv_mlp_train_step(pcv_mlp* m, const uint16_t* inputs, con
   // weight gradients dW_l = a_l^T d_l and bias gradients
   for (int l = 0; l < 4; ++l) {
     GemmArgs g{};
+    g.part = m->part;
     g.A = (l == 0) ? inputs : m->act[l];
     g.sAi = 1;
     g.sAk = m->dims[l];
@@ -844,7 +907,7 @@ extern "C" pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, do
     MTRY(pcv_internal_exact_for_surrogate(h, m->n, st, x, sz, ds_dx, dz_dx, &flag));
     MTRY(mlp_eval_enqueue(m, x, 1, m->sz_s, m->ds_s, m->dz_s, st));
     hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, flag, m->sz_s, m->ds_s, m->dz_s, m->nin, sz, ds_dx,
-                       dz_dx, used_surrogate, m->judge, m->cnt);
+                       dz_dx, used_surrogate, m->anchor, m->judge, m->cnt);
     return hipGetLastError();
   });
 }
@@ -861,8 +924,9 @@ extern "C" pcv_status pcv_mlp_get_stats(pcv_mlp* m, pcv_mlp_stats* out) {
   out->exact_steps = c[2];
   out->max_abs_ds = j[0];
   out->max_abs_dz = j[1];
-  out->mean_abs_ds = c[2] ? j[2] / c[2] : 0.0;
-  out->mean_abs_dz = c[2] ? j[3] / c[2] : 0.0;
+  out->judged_steps = c[3];
+  out->mean_abs_ds = c[3] ? j[2] / c[3] : 0.0;
+  out->mean_abs_dz = c[3] ? j[3] / c[3] : 0.0;
   return PCV_OK;
 }
 
