@@ -488,7 +488,7 @@ static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, do
   if (e != hipSuccess) return e;
   e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
   if (e != hipSuccess) return e;
-  return launch_merge_close<T>(h->d_prob + MODE_APPROX, o, ca, h->gtmp, st);
+  return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
 }
 
 // Run an enqueue function directly or through a cached hipGraph keyed on the

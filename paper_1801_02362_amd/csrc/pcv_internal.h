@@ -151,7 +151,7 @@ template <typename T>
 hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
                               const int* flag, int run_if, hipStream_t st);
 template <typename T>
-hipError_t launch_merge_close(const Problem* prob, Outs outs, CloseArgs ca, double* gtmp,
+hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
                               hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);

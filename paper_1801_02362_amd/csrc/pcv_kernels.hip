@@ -666,8 +666,8 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   }
 }
 
-// Algorithm 2 merge for the approximate step (single workgroup).  The
-// partials accumulate b_ik = R_{a_i y} (a_ik - c_i) (landmarks in y's frame):
+// Algorithm 2 merge for the approximate step.  The partials accumulate
+// b_ik = R_{a_i y} (a_ik - c_i) (landmarks in y's frame):
 //   beta_k  = sum_i c_i b_ik = -(lambda/Z) sum_g f_g (U_g + (q0_g - s) V_g),
 //   betaz_k = sum_i p_i b_ik = (1/Z) sum_g f_g V_g,
 // the explicit Eq. 6 terms ds/dx_k = -2 w_k R_xy beta_k and
@@ -675,91 +675,127 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
 // G = -2 sum_j w_j x_j beta_j^T (the symmetric part of Eq. 6's contraction
 // has no tangent component), Gamma = d(G:R_xy)/dM_xy and the contribution
 // w_k sum_a Gamma_ac y_k[a].
+//
+// Stage 1 (one workgroup per 64 atoms, 4 slot groups): beta, betaz and the
+// explicit terms of its atoms, and its share of G (18 values, written per
+// workgroup).  Stage 2 (one workgroup): G summed over workgroups in a fixed
+// order, the two rotation adjoints, the outputs.
+// gtmp layout: [0, 3 n_pad) explicit ds, [3 n_pad, 6 n_pad) explicit dz,
+// [6 n_pad, 6 n_pad + 18 * tiles) G shares.
 template <typename T>
-__global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __restrict__ prob, Outs o,
-                                                           CloseArgs cs, double* __restrict__ gtmp) {
+__global__ __launch_bounds__(256) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
+                                                               double* __restrict__ gtmp) {
   using acc = typename AccT<T>::type;  // partial storage type
-  constexpr int BS = 1024;
   if (*cs.flag != 0) return;
-  __shared__ double sh[16 * 18];
-  __shared__ double fq[2][2048];
-  __shared__ double part[8][128][2];
-  __shared__ double gam[18];
+  __shared__ double sh[8];
+  __shared__ double fq[2][256];
+  __shared__ double red[4][64][6];
+  __shared__ double gsh[4 * 18];
   const Problem& P = *prob;
   double m, Z, S;
-  global_lse<BS>(P, sh, m, Z, S);
+  global_lse<256>(P, sh, m, Z, S);
   const double s = S / Z;
   const double lam = P.lam;
-  const int n = P.n, n_pad = P.n_pad;
-  const int ns = P.n_slots;  // <= 2048 (host guarantees)
-  for (int g = threadIdx.x; g < ns; g += BS) {
-    fq[0][g] = scale_to(P.hdr[(size_t)g * 4], m, lam);
-    fq[1][g] = P.hdr[(size_t)g * 4 + 3] - s;
-  }
-  __syncthreads();
-  // beta (rows 0..2) and betaz (rows 3..5) for every (coordinate, atom) column.
-  const int ncol = 3 * n_pad;
-  const int cl = threadIdx.x & 127, grp = threadIdx.x >> 7;
-  for (int col0 = 0; col0 < ncol; col0 += 128) {
-    const int col = col0 + cl;
-    double su = 0.0, sv = 0.0;
-    if (col < ncol) {
-      const int c = col / n_pad, j = col - c * n_pad;
-      for (int g = grp; g < ns; g += 8) {
-        const double u = (double)ldg(partial_u<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + j);
-        const double v = ldg(partial_v<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + j);
-        su = fma(fq[0][g], fma(fq[1][g], v, u), su);
-        sv = fma(fq[0][g], v, sv);
+  const int n_pad = P.n_pad;
+  const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + a;
+  double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
+  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
+    __syncthreads();
+    const int g = g0 + threadIdx.x;
+    if (g < P.n_slots) {
+      fq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
+      fq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
+    }
+    __syncthreads();
+    const int gn = min(256, P.n_slots - g0);
+    if (j < n_pad) {
+      for (int t = sg; t < gn; t += 4) {
+        const acc* pu = partial_u<acc>(P.vec, g0 + t, n_pad);
+        const double* pv = partial_v<acc>(P.vec, g0 + t, n_pad);
+        const double f = fq[0][t], dq = fq[1][t];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double u = (double)ldg(pu + (size_t)c * n_pad + j);
+          const double v = ldg(pv + (size_t)c * n_pad + j);
+          su[c] = fma(f, fma(dq, v, u), su[c]);
+          sv[c] = fma(f, v, sv[c]);
+        }
       }
     }
-    part[grp][cl][0] = su;
-    part[grp][cl][1] = sv;
-    __syncthreads();
-    if (grp == 0 && col < ncol) {
-      double a = 0.0, b = 0.0;
-      for (int k = 0; k < 8; ++k) { a += part[k][cl][0]; b += part[k][cl][1]; }
-      gtmp[col] = -lam / Z * a;                       // beta
-      gtmp[ncol + col] = b / Z;                       // betaz
-    }
-    __syncthreads();
   }
-  // Explicit terms and the rotation-gradient contraction.
-  const double* Rx = cs.Rxy;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    red[sg][a][c] = su[c];
+    red[sg][a][3 + c] = sv[c];
+  }
+  __syncthreads();
   double G[18];
 #pragma unroll
   for (int k = 0; k < 18; ++k) G[k] = 0.0;
-  for (int j = threadIdx.x; j < n; j += BS) {
+  if (sg == 0 && j < P.n) {
     double be[3], bz[3], xw[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      be[d] = gtmp[(size_t)d * n_pad + j];
-      bz[d] = gtmp[ncol + (size_t)d * n_pad + j];
-      xw[d] = P.xw[(size_t)d * n_pad + j];
+    for (int c = 0; c < 3; ++c) {
+      const double a0 = ((red[0][a][c] + red[1][a][c]) + red[2][a][c]) + red[3][a][c];
+      const double b0 = ((red[0][a][3 + c] + red[1][a][3 + c]) + red[2][a][3 + c]) + red[3][a][3 + c];
+      be[c] = -lam / Z * a0;
+      bz[c] = b0 / Z;
+      xw[c] = P.xw[(size_t)c * n_pad + j];
     }
+    const double* Rx = cs.Rxy;
     const double wj = P.w[j];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double rb = Rx[d * 3 + 0] * be[0] + Rx[d * 3 + 1] * be[1] + Rx[d * 3 + 2] * be[2];
       const double rz = Rx[d * 3 + 0] * bz[0] + Rx[d * 3 + 1] * bz[1] + Rx[d * 3 + 2] * bz[2];
-      gtmp[2 * ncol + (size_t)d * n_pad + j] = -2.0 * wj * rb;
-      gtmp[3 * ncol + (size_t)d * n_pad + j] = 2.0 * (xw[d] - wj * rz);
+      gtmp[(size_t)d * n_pad + j] = -2.0 * wj * rb;
+      gtmp[3 * (size_t)n_pad + (size_t)d * n_pad + j] = 2.0 * (xw[d] - wj * rz);
     }
 #pragma unroll
     for (int r0 = 0; r0 < 3; ++r0)
 #pragma unroll
       for (int c0 = 0; c0 < 3; ++c0) {
-        G[r0 * 3 + c0] = fma(-2.0 * xw[r0], be[c0], G[r0 * 3 + c0]);
-        G[9 + r0 * 3 + c0] = fma(-2.0 * xw[r0], bz[c0], G[9 + r0 * 3 + c0]);
+        G[r0 * 3 + c0] = -2.0 * xw[r0] * be[c0];
+        G[9 + r0 * 3 + c0] = -2.0 * xw[r0] * bz[c0];
       }
   }
-  block_sum<18, BS>(G, sh);
+  // G share of this tile (64 atoms; waves 1..3 contribute zeros).
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 18; ++k) G[k] += __shfl_xor(G[k], off, 64);
   if (threadIdx.x == 0) {
-    double Gs[9], Gz[9];
+    double* gs = gtmp + 6 * (size_t)n_pad + (size_t)blockIdx.x * 18;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) gs[k] = G[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void merge_close_final_kernel(const Problem* __restrict__ prob, Outs o,
+                                                                 CloseArgs cs, const double* __restrict__ gtmp,
+                                                                 int tiles) {
+  constexpr int BS = 1024;
+  if (*cs.flag != 0) return;
+  __shared__ double sh[16 * 18];
+  __shared__ double gam[18];
+  const Problem& P = *prob;
+  const int n = P.n, n_pad = P.n_pad;
+  if (threadIdx.x < 18) {
+    double g = 0.0;
+    for (int t = 0; t < tiles; ++t) g += gtmp[6 * (size_t)n_pad + (size_t)t * 18 + threadIdx.x];
+    sh[threadIdx.x] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double G[18], Gs[9], Gz[9];
+    for (int k = 0; k < 18; ++k) G[k] = sh[k];
     rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G, Gs);
     rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G + 9, Gz);
     for (int k = 0; k < 9; ++k) { gam[k] = Gs[k]; gam[9 + k] = Gz[k]; }
   }
-  __syncthreads();
+  double m, Z, S;
+  global_lse<BS>(P, sh + 32, m, Z, S);   // also orders gam[] before its use below
   T* ds = (T*)o.ds;
   T* dz = (T*)o.dz;
   for (int j = threadIdx.x; j < n; j += BS) {
@@ -771,13 +807,13 @@ __global__ __launch_bounds__(1024) void merge_close_kernel(const Problem* __rest
     for (int c0 = 0; c0 < 3; ++c0) {
       const double rs = wj * (gam[0 * 3 + c0] * y[0] + gam[1 * 3 + c0] * y[1] + gam[2 * 3 + c0] * y[2]);
       const double rz = wj * (gam[9 + 0 * 3 + c0] * y[0] + gam[9 + 1 * 3 + c0] * y[1] + gam[9 + 2 * 3 + c0] * y[2]);
-      if (ds) ds[3 * j + c0] = (T)(gtmp[2 * ncol + (size_t)c0 * n_pad + j] + rs);
-      if (dz) dz[3 * j + c0] = (T)(gtmp[3 * ncol + (size_t)c0 * n_pad + j] + rz);
+      if (ds) ds[3 * j + c0] = (T)(gtmp[(size_t)c0 * n_pad + j] + rs);
+      if (dz) dz[3 * j + c0] = (T)(gtmp[3 * (size_t)n_pad + (size_t)c0 * n_pad + j] + rz);
     }
   }
   if (threadIdx.x == 0) {
-    o.sz[0] = s;
-    o.sz[1] = m - log(Z) / lam;
+    o.sz[0] = S / Z;
+    o.sz[1] = m - log(Z) / P.lam;
   }
 }
 
@@ -890,9 +926,13 @@ hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int m
 }
 
 template <typename T>
-hipError_t launch_merge_close(const Problem* prob, Outs outs, CloseArgs ca, double* gtmp,
+hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
                               hipStream_t st) {
-  hipLaunchKernelGGL((merge_close_kernel<T>), dim3(1), dim3(1024), 0, st, prob, outs, ca, gtmp);
+  const int tiles = (n_pad + 63) / 64;
+  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles), dim3(256), 0, st, prob, ca, gtmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(1024), 0, st, prob, outs, ca, gtmp, tiles);
   return hipGetLastError();
 }
 
@@ -917,7 +957,7 @@ hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) 
                                        const int*, int, const int*, int, double*, hipStream_t);    \
   template hipError_t launch_merge_exact<T>(const Problem*, Outs, int, int, const int*, int,       \
                                             hipStream_t);                                          \
-  template hipError_t launch_merge_close<T>(const Problem*, Outs, CloseArgs, double*, hipStream_t);
+  template hipError_t launch_merge_close<T>(const Problem*, int, Outs, CloseArgs, double*, hipStream_t);
 PCV_INST(float)
 PCV_INST(double)
 
