@@ -21,8 +21,12 @@ namespace {
 constexpr int kMaxAtomsF32 = 512 * 16;
 constexpr int kMaxAtomsF64 = 256 * 8;
 constexpr int kMaxCloseSlots = 2048;
-// Smallest structure (padded atoms) for which engine 3 is the default.
-constexpr int kEngine3MinAtoms = 1024;
+// Largest structure (padded atoms) engine 4 holds; engine 3 takes larger
+// FP32 structures.
+constexpr int kEngine4MaxAtoms = 2048;
+// Landmark steps per work item engine 4 aims for when its items write
+// several partial slots (fewer, longer items keep the merge traffic small).
+constexpr int kEngine4MinSteps = 2;
 
 struct Plan {
   int engine = 1;
@@ -31,6 +35,8 @@ struct Plan {
   Engine2Cfg c2{0, 0};      // engine 2
   int g = 0, B = 1, lbuf = 0;
   int bpw = 0;              // engine 3: 256-atom blocks per worker wave
+  int spw = 0;              // engine 4: units per worker wave (B = landmark lanes K)
+  int R = 1;                // partial slots per work item
   int grid = 0;
   int n_items = 0;
   size_t lds = 0;
@@ -172,11 +178,13 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
 static pcv_status build_plan(pcv_handle* h) {
   Plan& p = h->plan;
   // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
-  const int unit = (p.engine == 2) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
+  const int unit = (p.engine == 2 || p.engine == 4) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
   const int units = (h->L + unit - 1) / unit;
+  p.R = (p.engine == 4) ? e4_subslots(p.B) : 1;
   if (!h->user_plan || p.n_items <= 0) {
     const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
-    p.n_items = std::max(1, std::min(units, cap));
+    const int want = (p.R > 1) ? (units + kEngine4MinSteps - 1) / kEngine4MinSteps : units;
+    p.n_items = std::max(1, std::min(want, cap));
   }
   p.n_items = std::min(p.n_items, units);
   p.n_items = std::min(p.n_items, kMaxCloseSlots);
@@ -184,15 +192,16 @@ static pcv_status build_plan(pcv_handle* h) {
   if (p.engine == 2) {
     p.lbuf = p.B * 3 * h->n_pad * (h->fp64 ? 8 : 4);
     p.lds = engine2_lds_bytes((size_t)p.lbuf, p.B);
-  } else if (p.engine == 3) {
+  } else if (p.engine == 3 || p.engine == 4) {
     p.lds = 0;   // static LDS
   } else {
     p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
   }
   h->pmem.release();
-  HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, (size_t)p.n_items * 4 * sizeof(double)));
-  HIP_TRY(h, h->pmem.alloc(&h->vec, (size_t)p.n_items * (h->fp64 ? partial_bytes<double>(h->n_pad)
-                                                                  : partial_bytes<float>(h->n_pad))));
+  const size_t n_slots = (size_t)p.n_items * p.R;
+  HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, n_slots * 4 * sizeof(double)));
+  HIP_TRY(h, h->pmem.alloc(&h->vec, n_slots * (h->fp64 ? partial_bytes<double>(h->n_pad)
+                                                       : partial_bytes<float>(h->n_pad))));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 3 * sizeof(Problem)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
@@ -209,7 +218,7 @@ static pcv_status build_plan(pcv_handle* h) {
     const int u1 = (int)((long long)(k + 1) * units / p.n_items);
     items[k].i0 = std::min(h->L, u0 * unit);
     items[k].i1 = std::min(h->L, u1 * unit);
-    items[k].slot = k;
+    items[k].slot = k * p.R;
     wgoff[k] = k;
   }
   wgoff[p.grid] = p.n_items;
@@ -234,7 +243,7 @@ static pcv_status build_plan(pcv_handle* h) {
   base.n_pad = h->n_pad;
   base.L = h->L;
   base.ts = p.ts;
-  base.n_slots = p.n_items;
+  base.n_slots = p.n_items * p.R;
   base.out_off = 0;
   base.out_idx = 0;
   base.lam = h->lam;
@@ -279,8 +288,20 @@ static int e3_bpw_for(int n_pad) {
   return 0;
 }
 
+static bool default_plan4(pcv_handle* h) {
+  if (h->fp64 || h->n_pad > kEngine4MaxAtoms) return false;
+  const int K = engine4_lanes(h->n_pad, 3);
+  if (K < 1) return false;
+  h->plan.engine = 4;
+  h->plan.spw = 3;
+  h->plan.B = K;
+  h->plan.cfg = EngineCfg{512, 12};
+  h->plan.ts = 0;
+  return true;
+}
+
 static bool default_plan3(pcv_handle* h) {
-  if (h->fp64 || h->n_pad < kEngine3MinAtoms) return false;
+  if (h->fp64 || h->n_pad <= kEngine4MaxAtoms) return false;
   const int bpw = e3_bpw_for(h->n_pad);
   if (bpw == 0) return false;
   h->plan.engine = 3;
@@ -293,6 +314,7 @@ static bool default_plan3(pcv_handle* h) {
 static void default_plan(pcv_handle* h) {
   h->plan.n_items = 0;
   h->user_plan = false;
+  if (default_plan4(h)) return;
   if (default_plan3(h)) return;
   if (default_plan2(h)) return;
   h->plan.engine = 1;
@@ -445,7 +467,9 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
   }
   const Plan& p = h->plan;
   hipError_t e;
-  if (p.engine == 3)
+  if (p.engine == 4)
+    e = launch_engine4<T>(p.spw, p.grid, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if, msd, st);
+  else if (p.engine == 3)
     e = launch_engine3<T>(p.bpw, p.grid, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if, msd, st);
   else if (p.engine == 2)
     e = launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
@@ -633,10 +657,10 @@ extern "C" pcv_status pcv_get_plan(pcv_handle* h, pcv_plan* out) {
   const Plan& p = h->plan;
   out->engine = p.engine;
   out->wg = p.engine >= 2 ? 512 : p.cfg.wg;
-  out->apt = p.engine == 2 ? p.c2.aptc : (p.engine == 3 ? 4 * p.bpw : p.cfg.apt);
-  out->team = p.engine == 2 ? p.g : (p.engine == 3 ? 0 : p.ts);
+  out->apt = p.engine == 2 ? p.c2.aptc : (p.engine == 3 ? 4 * p.bpw : (p.engine == 4 ? 4 * p.spw : p.cfg.apt));
+  out->team = p.engine == 2 ? p.g : (p.engine >= 3 ? 0 : p.ts);
   out->aptg = p.engine == 2 ? p.c2.aptg : 0;
-  out->batch = p.engine == 2 ? p.B : 0;
+  out->batch = (p.engine == 2 || p.engine == 4) ? p.B : 0;
   out->grid = p.grid;
   out->items = p.n_items;
   return PCV_OK;
@@ -682,8 +706,21 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
     p.bpw = bpw;
     p.cfg = EngineCfg{512, 4 * bpw};
     p.ts = 0;
+  } else if (q->engine == 4) {
+    if (h->fp64) return fail(h, PCV_EUNSUPPORTED, "engine 4 is FP32 only");
+    const int spw = q->apt / 4;
+    if (q->apt % 4 != 0 || spw < 2 || spw > 3) return fail(h, PCV_EUNSUPPORTED, "engine 4 needs apt = 8 or 12");
+    const int kmax = engine4_lanes(h->n_pad, spw);
+    if (kmax < 1) return fail(h, PCV_EINVAL, "engine 4 cannot hold the structure");
+    const int K = q->batch > 0 ? q->batch : kmax;
+    if (K > kmax) return fail(h, PCV_EINVAL, "engine 4: batch exceeds the landmark lanes of the tiling");
+    p.engine = 4;
+    p.spw = spw;
+    p.B = K;
+    p.cfg = EngineCfg{512, 4 * spw};
+    p.ts = 0;
   } else {
-    return fail(h, PCV_EINVAL, "engine must be 1, 2 or 3");
+    return fail(h, PCV_EINVAL, "engine must be 1, 2, 3 or 4");
   }
   p.n_items = q->items;
   HIP_TRY(h, hipStreamSynchronize(h->stream));

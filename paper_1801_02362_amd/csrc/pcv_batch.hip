@@ -28,12 +28,16 @@ struct BatchPlan {
   int engine = 2;
   EngineCfg cfg{256, 8};   // engine 1 tiling
   Engine2Cfg c2{3, 16, 8}; // engine 2 tiling
-  int per_team = 4;        // engine 1: landmarks per team per item; engine 2: batches per item
+  int spw = 3;             // engine 4: units per worker wave
+  int per_team = 4;        // engine 1: landmarks per team per item; engine 2: batches per item;
+                           // engine 4: landmark steps per item
   int grid_mult = 2;       // workgroups = grid_mult * CUs
   int lpt = 1;             // 1: longest-processing-time schedule, 0: round robin
   std::string str() const {
     std::ostringstream o;
-    if (engine == 2)
+    if (engine == 4)
+      o << "engine=4 spw=" << spw;
+    else if (engine == 2)
       o << "engine=2 ncw=" << c2.ncw << " aptc=" << c2.aptc << " aptg=" << c2.aptg;
     else
       o << "engine=1 wg=" << cfg.wg << " apt=" << cfg.apt;
@@ -58,6 +62,8 @@ struct pcv_batch {
   void* A = nullptr;
   double *ca = nullptr, *Ga = nullptr, *q = nullptr, *w = nullptr, *xw = nullptr, *Gx = nullptr,
          *Gx32 = nullptr, *xres = nullptr;
+  float* xw32 = nullptr;      // FP32 batches: [3][n_x] per walker (engine 4)
+  std::vector<size_t> x32_off;
   int* status = nullptr;
   PrepArgs* d_prep = nullptr;
   // plan
@@ -190,6 +196,13 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
   BHIP_TRY(b, m.alloc((void**)&b->xres, 3 * W * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->status, W * sizeof(int)));
   BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
+  b->x32_off.assign(W + 1, 0);
+  for (int i = 0; i < W; ++i) b->x32_off[i + 1] = b->x32_off[i] + 3 * (size_t)round_up(b->n_pad[i], 256);
+  b->xw32 = nullptr;
+  if (!b->fp64) {
+    BHIP_TRY(b, m.alloc((void**)&b->xw32, b->x32_off[W] * sizeof(float)));
+    BHIP_TRY(b, hipMemset(b->xw32, 0, b->x32_off[W] * sizeof(float)));
+  }
   std::vector<double> hw(Ptot, 0.0), hq(Ltot);
   std::vector<PrepArgs> pa(W);
   for (int i = 0; i < W; ++i) {
@@ -198,6 +211,8 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
     const size_t po = b->pad_off[i];
     pa[i] = PrepArgs{(long long)b->atom_off[i], b->w + po, b->xw + 3 * po, b->Gx + i, b->Gx32 + i,
                      b->xres + 3 * i, b->status + i, nullptr, b->n[i], b->n_pad[i], b->L[i]};
+    pa[i].xw32 = b->xw32 ? b->xw32 + b->x32_off[i] : nullptr;
+    pa[i].n_x = round_up(b->n_pad[i], 256);
   }
   BHIP_TRY(b, hipMemcpy(b->w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->q, hq.data(), hq.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -219,10 +234,16 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
 // Lay out items and partial slots for a plan and upload the descriptors.
 static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   const size_t tsz = b->fp64 ? 8 : 4;
-  std::vector<int> ts(b->W, 0), gsz(b->W, 0), bsz(b->W, 1);
+  std::vector<int> ts(b->W, 0), gsz(b->W, 0), bsz(b->W, 1), rsl(b->W, 1);
   int bmax = 1, lbuf = 0;
   for (int i = 0; i < b->W; ++i) {
-    if (p.engine == 2) {
+    if (p.engine == 4) {
+      if (b->fp64) return bfail(b, PCV_EUNSUPPORTED, "engine 4 is FP32 only");
+      const int K = engine4_lanes(b->n_pad[i], p.spw);
+      if (K < 1) return bfail(b, PCV_ESHAPE, "engine 4 cannot hold a walker");
+      bsz[i] = K;
+      rsl[i] = e4_subslots(K);
+    } else if (p.engine == 2) {
       const int B = e2_batch(b->n_pad[i], b->fp64);
       if (B == 0 || !e2_fits(b->n_pad[i], p.c2)) return bfail(b, PCV_ESHAPE, "engine 2 cannot hold a walker");
       const int g = e2_group(b->n_pad[i], p.c2, B);
@@ -247,7 +268,15 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   for (int i = 0; i < b->W; ++i) {
     int chunk;
     double per_lm;
-    if (p.engine == 2) {
+    double item_cost = 3000.0;
+    if (p.engine == 4) {
+      // A step streams K n_pad 12 bytes (about 25 B/ns per CU) and waits for
+      // at least one eigen-solve (about 1.5 us); an item also stages the
+      // structure and writes its partial slots.
+      chunk = std::max(1, bsz[i] * p.per_team);
+      per_lm = std::max((double)bsz[i] * b->n_pad[i] * 12.0 / 25.0, 1500.0) / bsz[i];
+      item_cost = 4000.0 + rsl[i] * 36.0 * b->n_pad[i] / 25.0;
+    } else if (p.engine == 2) {
       chunk = std::max(1, bsz[i] * p.per_team);
       per_lm = (double)b->n_pad[i] * 24.0 + 4000.0 / bsz[i];
     } else {
@@ -261,13 +290,13 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
       it.prob = i;
       it.i0 = k * chunk;
       it.i1 = std::min(b->L[i], (k + 1) * chunk);
-      it.slot = k;
-      items.push_back({it, per_lm * (it.i1 - it.i0) + 3000.0});
+      it.slot = k * rsl[i];
+      items.push_back({it, per_lm * (it.i1 - it.i0) + item_cost});
     }
-    slots[i] = cnt;
-    slot_base[i + 1] = slot_base[i] + cnt;
+    slots[i] = cnt * rsl[i];
+    slot_base[i + 1] = slot_base[i] + slots[i];
     vec_off[i] = vec_elems;   // bytes
-    vec_elems += (size_t)cnt * (b->fp64 ? partial_bytes<double>(b->n_pad[i]) : partial_bytes<float>(b->n_pad[i]));
+    vec_elems += (size_t)slots[i] * (b->fp64 ? partial_bytes<double>(b->n_pad[i]) : partial_bytes<float>(b->n_pad[i]));
   }
   const int G = std::max(1, std::min((int)items.size(), p.grid_mult * b->cus));
   std::vector<std::vector<int>> per_wg(G);
@@ -292,7 +321,8 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   }
   wgoff[G] = (int)flat.size();
   size_t lds = 0;
-  if (p.engine == 2) lds = engine2_lds_bytes((size_t)lbuf, bmax);
+  if (p.engine == 4) lds = 0;   // static LDS
+  else if (p.engine == 2) lds = engine2_lds_bytes((size_t)lbuf, bmax);
   else
     for (int i = 0; i < b->W; ++i) lds = std::max(lds, engine_lds_bytes(p.cfg, ts[i], b->fp64));
 
@@ -322,6 +352,8 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.fallbacks = nullptr;
     P.Gx32 = b->Gx32 + i;
     P.xres = b->xres + 3 * i;
+    P.xw32 = b->xw32 ? b->xw32 + b->x32_off[i] : nullptr;
+    P.n_x = round_up(b->n_pad[i], 256);
     P.bsz = bsz[i];
     P.cg = gsz[i];
     P.n = b->n[i];
@@ -354,6 +386,9 @@ template <typename T>
 static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, double* sz, void* ds, void* dz) {
   hipError_t e = launch_prep<T>(b->d_prep, x, b->W, st);
   if (e != hipSuccess) return e;
+  if (b->plan.engine == 4)
+    e = launch_engine4<T>(b->plan.spw, b->grid, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st);
+  else
   e = (b->plan.engine == 2)
           ? launch_engine2<T>(b->plan.c2.ncw, b->plan.c2.aptc, b->plan.c2.aptg, b->grid, b->lds, b->lbuf, b->bmax, b->d_prob,
                               b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st)
@@ -427,8 +462,22 @@ static bool heuristic_plan2(const pcv_batch* b, BatchPlan* out) {
   return false;
 }
 
+// Engine 4 holds every FP32 walker of up to 2048 padded atoms.
+static bool heuristic_plan4(const pcv_batch* b, BatchPlan* out) {
+  if (b->fp64) return false;
+  for (int i = 0; i < b->W; ++i)
+    if (engine4_lanes(b->n_pad[i], 3) < 1) return false;
+  out->engine = 4;
+  out->spw = 3;
+  out->per_team = 24;
+  out->grid_mult = 1;
+  out->lpt = 1;
+  return true;
+}
+
 static BatchPlan heuristic_plan(const pcv_batch* b) {
   BatchPlan p2;
+  if (heuristic_plan4(b, &p2)) return p2;
   if (heuristic_plan2(b, &p2)) return p2;
   EngineCfg menu[16];
   int cnt = 0;
@@ -466,7 +515,8 @@ static std::string shape_key(const pcv_batch* b) {
   return o.str();
 }
 
-// Minimal JSON cache: one line per entry, "key": "wg apt per_team grid_mult lpt".
+// Minimal JSON cache: one line per entry,
+// "key": "engine wg apt ncw aptc aptg per_team grid_mult lpt spw".
 static bool cache_lookup(const char* path, const std::string& key, BatchPlan* p) {
   if (!path) return false;
   std::ifstream f(path);
@@ -479,7 +529,7 @@ static bool cache_lookup(const char* path, const std::string& key, BatchPlan* p)
     std::istringstream v(line.substr(at + k.size()));
     BatchPlan q;
     if (v >> q.engine >> q.cfg.wg >> q.cfg.apt >> q.c2.ncw >> q.c2.aptc >> q.c2.aptg >> q.per_team >> q.grid_mult >>
-        q.lpt) {
+        q.lpt >> q.spw) {
       *p = q;
       return true;
     }
@@ -505,7 +555,8 @@ static void cache_store(const char* path, const std::string& key, const BatchPla
     f << t << ",\n";
   }
   f << "  \"" << key << "\": \"" << p.engine << " " << p.cfg.wg << " " << p.cfg.apt << " " << p.c2.ncw << " "
-    << p.c2.aptc << " " << p.c2.aptg << " " << p.per_team << " " << p.grid_mult << " " << p.lpt << "\"\n}\n";
+    << p.c2.aptc << " " << p.c2.aptg << " " << p.per_team << " " << p.grid_mult << " " << p.lpt << " " << p.spw
+    << "\"\n}\n";
 }
 
 extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path) {
@@ -560,6 +611,18 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   engine2_configs(b->fp64, nw, ac, ag, &cnt2);
   const int maxn = *std::max_element(b->n.begin(), b->n.end());
   std::vector<BatchPlan> cands;
+  if (!b->fp64)
+    for (int spw : {3, 2})
+      for (int per : {8, 16, 32, 64})
+        for (int lpt : {1, 0}) {
+          BatchPlan c;
+          c.engine = 4;
+          c.spw = spw;
+          c.per_team = per;
+          c.grid_mult = 1;
+          c.lpt = lpt;
+          cands.push_back(c);
+        }
   for (int k = 0; k < cnt2; ++k)
     for (int per : {1, 2, 4, 8})
       for (int gm : {1, 2})

@@ -35,6 +35,7 @@
 // own results, so the compiler never adds a full vmcnt wait in front of them.
 #include "pcv_internal.h"
 #include "pcv_math.h"
+#include "pcv_stream.h"
 
 namespace pcv {
 
@@ -49,49 +50,9 @@ constexpr int kBlkFloats3 = 3 * kBlk3;          // one block of one landmark (x,
 // ring and the wave's FP32 structure share about 150 KB of LDS.
 constexpr int ring_slots(int bpw) { return bpw >= 3 ? 4 : (bpw == 2 ? 5 : 6); }
 
-typedef float f4v __attribute__((ext_vector_type(4)));
-
 __shared__ double e3_part[2][kWorkers3 * 4][9];
 __shared__ double e3_res[2][16];
 __shared__ double e3_misc[16];
-
-// LDS-only workgroup barrier (the copies in flight are not waited for).
-__device__ __forceinline__ void bar3() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited for
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// Wait until at most n vector-memory instructions of this wave are
-// outstanding (n a multiple of 3, at most 15).
-__device__ __forceinline__ void wait_vm(int n) {
-#define PCV_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | 0x0F70)
-  switch (n) {
-    case 0: PCV_VM(0); break;
-    case 3: PCV_VM(3); break;
-    case 6: PCV_VM(6); break;
-    case 9: PCV_VM(9); break;
-    case 12: PCV_VM(12); break;
-    default: PCV_VM(15); break;
-  }
-#undef PCV_VM
-}
-
-// Three 16-byte LDS reads (the x, y, z planes of one block, OFF bytes past
-// addr) that wait for their own data.
-template <int OFF>
-__device__ __forceinline__ void read_block(unsigned addr, f4v& p0, f4v& p1, f4v& p2) {
-  static_assert(OFF >= 0 && OFF + 2048 < 65536, "ds offset field");
-  asm volatile(
-      "ds_read_b128 %0, %3 offset:%4\n\t"
-      "ds_read_b128 %1, %3 offset:%5\n\t"
-      "ds_read_b128 %2, %3 offset:%6\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(p0), "=&v"(p1), "=&v"(p2)   // early clobber: results must not reuse the address register
-      : "v"(addr), "i"(OFF), "i"(OFF + 1024), "i"(OFF + 2048)
-      : "memory");
-}
 
 // Block k of a wave's structure area (k is a constant after unrolling).
 __device__ __forceinline__ void read_xblock(int k, unsigned addr, f4v& p0, f4v& p1, f4v& p2) {
@@ -100,23 +61,6 @@ __device__ __forceinline__ void read_xblock(int k, unsigned addr, f4v& p0, f4v& 
     case 1: read_block<kBlkFloats3 * 4>(addr, p0, p1, p2); break;
     default: read_block<2 * kBlkFloats3 * 4>(addr, p0, p1, p2); break;
   }
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
-}
-
-// Sum over each row of 16 lanes (every lane of the row receives it).
-__device__ __forceinline__ double row_sum16(double v) {
-  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);   // row_half_mirror
-  v += dpp_f64<0x140>(v);   // row_mirror
-  return v;
 }
 
 __device__ __forceinline__ double clamp0_3(double v) { return v < 0.0 ? 0.0 : v; }
@@ -232,7 +176,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
         for (int q = 0; q < 9; ++q) pp[q] = M[q];
       }
     }
-    bar3();
+    bar_lds();
     if (t >= 1) {
       const double* rs = e3_res[(t - 1) & 1];
       const double sc = rs[11];
@@ -274,7 +218,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
     if (t + 1 <= nL) step(t + 1, a1, a0);
   }
 
-  bar3();   // item totals published by the solver
+  bar_lds();   // item totals published by the solver
   float* pu = partial_u<float>(c.P->vec, c.slot, n_pad);
   double* pv = partial_v<float>(c.P->vec, c.slot, n_pad);
   double mu[3], mv[3];
@@ -282,7 +226,6 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
   for (int d = 0; d < 3; ++d) { mu[d] = e3_misc[3 + d]; mv[d] = e3_misc[6 + d]; }
   // 16-byte stores: a lane's four consecutive atoms (n_pad is a multiple of
   // 64, so a group of four is either wholly inside or wholly past it).
-  typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < BPW; ++k) {
     if (k < nbw) {
@@ -332,7 +275,7 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
   double cap[3], Ga = 0.0, qi = 0.0, Rs[9];
   if (nL > 0) fetch(0, cap, Ga, qi, Rs);
   for (int t = 0; t <= nL; ++t) {
-    bar3();
+    bar_lds();
     if (t < nL) {
       const int i = c.i0 + t;
       const double cc[3] = {cap[0], cap[1], cap[2]};
@@ -427,7 +370,7 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
     stg(h + 2, S);
     stg(h + 3, q0);
   }
-  bar3();
+  bar_lds();
 }
 
 }  // namespace
@@ -458,7 +401,7 @@ __global__ __launch_bounds__(kWG3) void engine3_kernel(const Problem* __restrict
     if (wave < kWorkers3)
       e3_worker<BPW>(c, wave, lane, ring + wave * RS * kBlkFloats3, xs + wave * BPW * kBlkFloats3);
     else e3_solver(c, lane, mode, dout);
-    bar3();   // LDS is reused by the next item
+    bar_lds();   // LDS is reused by the next item
   }
 }
 

@@ -1,0 +1,89 @@
+// Device helpers shared by the streaming landmark engines that copy landmark
+// blocks HBM -> LDS asynchronously (global_load_lds) and synchronise with
+// LDS-only barriers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pcv {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// LDS-only workgroup barrier: the asynchronous copies in flight are not
+// waited for (the compiler's workgroup barrier would drain them).
+__device__ __forceinline__ void bar_lds() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait until at most n vector-memory instructions of this wave are
+// outstanding (n a multiple of 3, at most 15).
+__device__ __forceinline__ void wait_vm(int n) {
+#define PCV_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | 0x0F70)
+  switch (n) {
+    case 0: PCV_VM(0); break;
+    case 3: PCV_VM(3); break;
+    case 6: PCV_VM(6); break;
+    case 9: PCV_VM(9); break;
+    case 12: PCV_VM(12); break;
+    default: PCV_VM(15); break;
+  }
+#undef PCV_VM
+}
+
+// Three 16-byte LDS reads (the x, y, z planes of one 256-atom block, 1 KiB
+// apart, OFF bytes past addr) that wait for their own data.
+template <int OFF>
+__device__ __forceinline__ void read_block(unsigned addr, f4v& p0, f4v& p1, f4v& p2) {
+  static_assert(OFF >= 0 && OFF + 2048 < 65536, "ds offset field");
+  asm volatile(
+      "ds_read_b128 %0, %3 offset:%4\n\t"
+      "ds_read_b128 %1, %3 offset:%5\n\t"
+      "ds_read_b128 %2, %3 offset:%6\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(p0), "=&v"(p1), "=&v"(p2)   // early clobber: results must not reuse the address register
+      : "v"(addr), "i"(OFF), "i"(OFF + 1024), "i"(OFF + 2048)
+      : "memory");
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, true);
+  return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over each row of 16 lanes (every lane of the row receives it).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return v;
+}
+
+// Sum over the whole wave; lane 63 receives the total (rows 1 and 3 add the
+// last lane of the row below, then rows 2 and 3 add lane 31).  Rows that a
+// broadcast does not write receive 0 and keep their value.
+__device__ __forceinline__ double wave_sum_to63(double v) {
+  v = row_sum16(v);
+  v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15
+  v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31
+  return v;
+}
+
+// Minimum over each row of 16 lanes (every lane of the row receives it).
+// Lanes must hold finite values or +inf.
+__device__ __forceinline__ double row_min16(double v) {
+  v = fmin(v, dpp_f64<0xB1>(v));
+  v = fmin(v, dpp_f64<0x4E>(v));
+  v = fmin(v, dpp_f64<0x141>(v));
+  v = fmin(v, dpp_f64<0x140>(v));
+  return v;
+}
+
+}  // namespace pcv

@@ -143,6 +143,57 @@ def test_engine3_rejects_structures_it_cannot_hold(torch):
     cv.close()
 
 
+# Multi-landmark engine: structures of one to eight 256-atom blocks
+# (K = floor(7 spw / nblk) landmark lanes per step), 23 landmarks (the last
+# step is short), fewer landmark lanes than the tiling allows (K = 1 writes a
+# single partial per item, K = 2 several), and item counts from one item to
+# one landmark per item (items shorter than a step).
+_E4_CASES = [(n, spw, K, items) for n in (1, 64, 100, 300, 513, 1000, 1793, 2048) for spw in (2, 3)
+             for K, items in ((0, 0), (0, 1), (0, 23), (1, 5), (2, 0))]
+
+
+@pytest.mark.parametrize("n,spw,K,items", _E4_CASES)
+def test_engine4_tilings(torch, n, spw, K, items):
+    from gpu_util import TOL32
+    L = 23
+    s = wl.small_path(n, L, 60 + n % 13, dtype=np.float32)
+    rng = np.random.default_rng(n + 7 * spw)
+    frames = (s.waypoints[0] + rng.normal(0, 0.02, (2, n, 3))).astype(np.float32)
+    lam = landmark_lambda(s.landmarks) if n > 1 else 100.0
+    plan = dict(engine=4, wg=512, apt=4 * spw, team=0, aptg=0, batch=K, items=items)
+    if K > (7 * spw) // ((n + 63) // 64 * 64 // 256 + ((n + 63) // 64 * 64 % 256 > 0)):
+        import paper_1801_02362_amd as pcv
+        from gpu_util import dev
+        cv = pcv.PathCV(dev(s.landmarks, torch.float32), lam)
+        with pytest.raises(pcv.PcvError):
+            cv.set_plan(**plan)
+        cv.close()
+        return
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32,
+               name=f"e4_{n}_{spw}_{K}_{items}", plan=plan)
+
+
+def test_engine4_plan_reports_and_rejects(torch):
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev
+    s = wl.small_path(700, 3, 5, dtype=np.float32)
+    cv = pcv.PathCV(dev(s.landmarks, torch.float32), 10.0)
+    p = cv.plan
+    assert p["engine"] == 4 and p["apt"] == 12 and p["batch"] == 7   # 3 blocks: 21 // 3 landmark lanes
+    cv.set_plan(engine=4, wg=512, apt=8, team=0, aptg=0, batch=0)
+    assert cv.plan["batch"] == 4                                      # 14 // 3
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=4, wg=512, apt=8, team=0, aptg=0, batch=5)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=4, wg=512, apt=4, team=0, aptg=0, batch=0)
+    cv.close()
+    big = wl.small_path(2049, 2, 6, dtype=np.float32)
+    cv = pcv.PathCV(dev(big.landmarks, torch.float32), 10.0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=4, wg=512, apt=12, team=0, aptg=0, batch=0)
+    cv.close()
+
+
 def test_item_counts_and_graph_replay_are_bitwise_stable(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev, host
