@@ -24,9 +24,6 @@ constexpr int kMaxCloseSlots = 2048;
 // Largest structure (padded atoms) engine 4 holds; engine 3 takes larger
 // FP32 structures.
 constexpr int kEngine4MaxAtoms = 2048;
-// Landmark steps per work item engine 4 aims for when its items write
-// several partial slots (fewer, longer items keep the merge traffic small).
-constexpr int kEngine4MinSteps = 2;
 
 struct Plan {
   int engine = 1;
@@ -36,7 +33,6 @@ struct Plan {
   int g = 0, B = 1, lbuf = 0;
   int bpw = 0;              // engine 3: 256-atom blocks per worker wave
   int spw = 0;              // engine 4: units per worker wave (B = landmark lanes K)
-  int R = 1;                // partial slots per work item
   int grid = 0;
   int n_items = 0;
   size_t lds = 0;
@@ -180,11 +176,9 @@ static pcv_status build_plan(pcv_handle* h) {
   // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
   const int unit = (p.engine == 2 || p.engine == 4) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
   const int units = (h->L + unit - 1) / unit;
-  p.R = (p.engine == 4) ? e4_subslots(p.B) : 1;
   if (!h->user_plan || p.n_items <= 0) {
     const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
-    const int want = (p.R > 1) ? (units + kEngine4MinSteps - 1) / kEngine4MinSteps : units;
-    p.n_items = std::max(1, std::min(want, cap));
+    p.n_items = std::max(1, std::min(units, cap));
   }
   p.n_items = std::min(p.n_items, units);
   p.n_items = std::min(p.n_items, kMaxCloseSlots);
@@ -198,7 +192,7 @@ static pcv_status build_plan(pcv_handle* h) {
     p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
   }
   h->pmem.release();
-  const size_t n_slots = (size_t)p.n_items * p.R;
+  const size_t n_slots = (size_t)p.n_items;
   HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, n_slots * 4 * sizeof(double)));
   HIP_TRY(h, h->pmem.alloc(&h->vec, n_slots * (h->fp64 ? partial_bytes<double>(h->n_pad)
                                                        : partial_bytes<float>(h->n_pad))));
@@ -218,7 +212,7 @@ static pcv_status build_plan(pcv_handle* h) {
     const int u1 = (int)((long long)(k + 1) * units / p.n_items);
     items[k].i0 = std::min(h->L, u0 * unit);
     items[k].i1 = std::min(h->L, u1 * unit);
-    items[k].slot = k * p.R;
+    items[k].slot = k;
     wgoff[k] = k;
   }
   wgoff[p.grid] = p.n_items;
@@ -243,7 +237,7 @@ static pcv_status build_plan(pcv_handle* h) {
   base.n_pad = h->n_pad;
   base.L = h->L;
   base.ts = p.ts;
-  base.n_slots = p.n_items * p.R;
+  base.n_slots = p.n_items;
   base.out_off = 0;
   base.out_idx = 0;
   base.lam = h->lam;

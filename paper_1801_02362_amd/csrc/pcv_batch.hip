@@ -234,7 +234,7 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
 // Lay out items and partial slots for a plan and upload the descriptors.
 static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
   const size_t tsz = b->fp64 ? 8 : 4;
-  std::vector<int> ts(b->W, 0), gsz(b->W, 0), bsz(b->W, 1), rsl(b->W, 1);
+  std::vector<int> ts(b->W, 0), gsz(b->W, 0), bsz(b->W, 1);
   int bmax = 1, lbuf = 0;
   for (int i = 0; i < b->W; ++i) {
     if (p.engine == 4) {
@@ -242,7 +242,6 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
       const int K = engine4_lanes(b->n_pad[i], p.spw);
       if (K < 1) return bfail(b, PCV_ESHAPE, "engine 4 cannot hold a walker");
       bsz[i] = K;
-      rsl[i] = e4_subslots(K);
     } else if (p.engine == 2) {
       const int B = e2_batch(b->n_pad[i], b->fp64);
       if (B == 0 || !e2_fits(b->n_pad[i], p.c2)) return bfail(b, PCV_ESHAPE, "engine 2 cannot hold a walker");
@@ -272,10 +271,10 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     if (p.engine == 4) {
       // A step streams K n_pad 12 bytes (about 25 B/ns per CU) and waits for
       // at least one eigen-solve (about 1.5 us); an item also stages the
-      // structure and writes its partial slots.
+      // structure and writes its partial.
       chunk = std::max(1, bsz[i] * p.per_team);
       per_lm = std::max((double)bsz[i] * b->n_pad[i] * 12.0 / 25.0, 1500.0) / bsz[i];
-      item_cost = 4000.0 + rsl[i] * 36.0 * b->n_pad[i] / 25.0;
+      item_cost = 4000.0 + 36.0 * b->n_pad[i] / 25.0;
     } else if (p.engine == 2) {
       chunk = std::max(1, bsz[i] * p.per_team);
       per_lm = (double)b->n_pad[i] * 24.0 + 4000.0 / bsz[i];
@@ -290,10 +289,10 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
       it.prob = i;
       it.i0 = k * chunk;
       it.i1 = std::min(b->L[i], (k + 1) * chunk);
-      it.slot = k * rsl[i];
+      it.slot = k;
       items.push_back({it, per_lm * (it.i1 - it.i0) + item_cost});
     }
-    slots[i] = cnt * rsl[i];
+    slots[i] = cnt;
     slot_base[i + 1] = slot_base[i] + slots[i];
     vec_off[i] = vec_elems;   // bytes
     vec_elems += (size_t)slots[i] * (b->fp64 ? partial_bytes<double>(b->n_pad[i]) : partial_bytes<float>(b->n_pad[i]));

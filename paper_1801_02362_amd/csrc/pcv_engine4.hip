@@ -3,15 +3,17 @@
 //
 // A step covers K landmarks at once.  Its work is cut into units
 // u = k * nblk + b (landmark lane k < K, atom block b < nblk); worker wave w
-// of the seven owns the units w, w + 7, w + 14 (at most SPW), so with
+// of the seven owns the run of units w SPW ... w SPW + SPW - 1, so with
 // K = floor(7 SPW / nblk) nearly every worker slot carries a block in every
-// step, whatever the structure size.  Per step:
+// step, whatever the structure size, and a worker's units of one landmark
+// are adjacent (their correlation sums are added before one wave
+// reduction).  Per step:
 //
 //   * workers: each owned unit's block arrives through the wave's private
 //     LDS copy ring (global_load_lds_dwordx4, partial vmcnt waits), is read
 //     into registers once, and is contracted with the shared FP32 copy of
-//     w_j x_c,j in LDS into the unit's correlation sums (FP64), reduced over
-//     the wave with DPP moves;
+//     w_j x_c,j in LDS into correlation sums (FP64), reduced over the wave
+//     with DPP moves once per landmark the worker touches;
 //   * one LDS-only barrier;
 //   * solver wave: lane k adds the nblk unit sums of landmark k, solves its
 //     quaternion eigenproblem (Section 3; K independent solves side by
@@ -23,12 +25,11 @@
 //     step from the registers they kept, U += e (q - q0) R (a - c) (FP32)
 //     and V += e R (a - c) (FP64), and go on to contract the next step.
 //
-// With K > 1 several workers accumulate the same atoms (for different
-// landmark lanes); each worker then writes its own partial (sub-slot w of the
-// item, zero where it owns none of a block), and the merge kernels add the
-// sub-slots like any other partials.  With K = 1 every block has one owner
-// and the item writes a single partial.  Results do not depend on timing:
-// every sum is taken in a fixed order.
+// With K > 1 several units accumulate the same atoms (for different
+// landmark lanes); at the end of a work item their U and V go through the
+// idle copy rings in LDS and are added per block in landmark-lane order, so
+// every item writes one partial.  Results do not depend on timing: every sum
+// is taken in a fixed order.
 #include "pcv_internal.h"
 #include "pcv_math.h"
 #include "pcv_stream.h"
@@ -55,6 +56,8 @@ __shared__ double e4_res[2][kMaxUnits4][kRes4];    // per landmark lane
 __shared__ double e4_sc[2];                        // rescale factor of the step
 __shared__ double e4_misc[16];                     // item totals
 
+static_assert(kMaxUnits4 * kBF4 * 8 <= kW4 * kRing4 * kBF4 * 4, "unit sums (FP64) fit in the copy rings");
+
 __device__ __forceinline__ double clamp0_4(double v) { return v < 0.0 ? 0.0 : v; }
 
 __device__ __forceinline__ unsigned lds_addr(const float* p) {
@@ -63,15 +66,16 @@ __device__ __forceinline__ unsigned lds_addr(const float* p) {
 
 struct E4Item {
   const Problem* P;
-  int i0, nL, slot, n_pad, nblk, K, R;
+  int i0, nL, slot, n_pad, nblk, K;
   double lam, q0;
 };
 
 // ------------------------------------------------------------------ worker
-// ring: this wave's copy ring; xs: the workgroup's FP32 copy of w_j x_c,j
-// (nblk blocks, x/y/z planes of 256 atoms each).
+// ring: this wave's copy ring; rings: all seven (reused at the item end);
+// xs: the workgroup's FP32 copy of w_j x_c,j (nblk blocks, x/y/z planes of
+// 256 atoms each).
 template <int SPW>
-__device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, float* ring, float* xs) {
+__device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, float* ring, float* rings, float* xs) {
   constexpr int RS = kRing4;
   const int n_pad = c.n_pad, nblk = c.nblk, K = c.K, nL = c.nL;
   const int T = (nL + K - 1) / K;
@@ -79,7 +83,7 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
   int uk[SPW], ub[SPW];   // landmark lane and block of slot s (wave-uniform)
 #pragma unroll
   for (int s = 0; s < SPW; ++s) {
-    const int u = w + kW4 * s;
+    const int u = w * SPW + s;
     uk[s] = u / nblk;
     ub[s] = u - uk[s] * nblk;
   }
@@ -88,7 +92,7 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
     const int lim = min(K, nL - t * K) * nblk;
     int a = 0;
 #pragma unroll
-    for (int s = 0; s < SPW; ++s) a += (w + kW4 * s < lim) ? 1 : 0;
+    for (int s = 0; s < SPW; ++s) a += (w * SPW + s < lim) ? 1 : 0;
     return a;
   };
   const int na_full = T > 0 ? nact(0) : 0;
@@ -158,9 +162,13 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
   auto step = [&](int t, float (&cur)[SPW][3][4], float (&prev)[SPW][3][4]) {
     if (t < T) {
       const int lim = min(K, nL - t * K) * nblk;
+      double M[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) M[q] = 0.0;
 #pragma unroll
       for (int s = 0; s < SPW; ++s) {
-        if (w + kW4 * s < lim) {
+        const int u = w * SPW + s;
+        if (u < lim) {
           wait_vm(3 * (issued - consumed - 1));
           f4v p0, p1, p2;
           read_block<0>(ring_addr + (unsigned)(rd_slot * kBF4 * 4), p0, p1, p2);
@@ -170,9 +178,6 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
           f4v x0, x1, x2;
           read_block<0>(xs_addr + (unsigned)(ub[s] * kBF4 * 4), x0, x1, x2);
           const bool in = ub[s] * kBlk4 + lane * 4 < n_pad;
-          double M[9];
-#pragma unroll
-          for (int q = 0; q < 9; ++q) M[q] = 0.0;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float c0 = in ? p0[e] : 0.f, c1 = in ? p1[e] : 0.f, c2 = in ? p2[e] : 0.f;
@@ -183,12 +188,22 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
             M[3] = fma(b1, y0, M[3]); M[4] = fma(b1, y1, M[4]); M[5] = fma(b1, y2, M[5]);
             M[6] = fma(b2, y0, M[6]); M[7] = fma(b2, y1, M[7]); M[8] = fma(b2, y2, M[8]);
           }
+          // A run of units of one landmark ends here: reduce it once and
+          // store it at this unit; the run's earlier units store zeros.
+          const bool last = (s == SPW - 1) || (u + 1 >= lim) || (uk[s < SPW - 1 ? s + 1 : s] != uk[s]);
+          double* pp = e4_part[t & 1][u];
+          if (last) {
 #pragma unroll
-          for (int q = 0; q < 9; ++q) M[q] = wave_sum_to63(M[q]);
-          if (lane == 63) {
-            double* pp = e4_part[t & 1][w + kW4 * s];
+            for (int q = 0; q < 9; ++q) M[q] = wave_sum_to63(M[q]);
+            if (lane == 63) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) pp[q] = M[q];
+              for (int q = 0; q < 9; ++q) pp[q] = M[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) M[q] = 0.0;
+          } else if (lane == 63) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) pp[q] = 0.0;
           }
         }
       }
@@ -209,7 +224,7 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
       }
 #pragma unroll
       for (int s = 0; s < SPW; ++s) {
-        if (w + kW4 * s < limp) {
+        if (w * SPW + s < limp) {
           const double* rs = e4_res[tp & 1][uk[s]];
           float Rt[9];
 #pragma unroll
@@ -243,52 +258,110 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
   for (int d = 0; d < 3; ++d) { mu[d] = e4_misc[3 + d]; mv[d] = e4_misc[6 + d]; }
   // 16-byte stores of a lane's four consecutive atoms (n_pad is a multiple
   // of 64, so a group of four is either wholly inside or wholly past it).
-  auto store = [&](int slot, int b, const float (&u)[3][4], const double (&v)[3][4], bool corr) {
-    const int j0 = b * kBlk4 + lane * 4;
-    if (j0 >= n_pad) return;
-    float* pu = partial_u<float>(c.P->vec, slot, n_pad);
-    double* pv = partial_v<float>(c.P->vec, slot, n_pad);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double cu = corr ? mu[d] : 0.0, cv = corr ? mv[d] : 0.0;
-      f4v u4;
-      d2v v01, v23;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) u4[e] = (float)((double)u[d][e] - cu);
-      v01[0] = v[d][0] - cv;
-      v01[1] = v[d][1] - cv;
-      v23[0] = v[d][2] - cv;
-      v23[1] = v[d][3] - cv;
-      stg(reinterpret_cast<f4v*>(pu + (size_t)d * n_pad + j0), u4);
-      stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0), v01);
-      stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0 + 2), v23);
-    }
-  };
-  if (c.R == 1) {
+  float* pu = partial_u<float>(c.P->vec, c.slot, n_pad);
+  double* pv = partial_v<float>(c.P->vec, c.slot, n_pad);
+  if (K == 1) {
     // One landmark lane: every block has exactly one owner.
 #pragma unroll
-    for (int s = 0; s < SPW; ++s)
-      if (w + kW4 * s < ufull) store(c.slot, ub[s], U[s], V[s], true);
-  } else {
-    // Sub-slot w: this worker's sums per block (zero for blocks it does not
-    // own); the centroid-residual totals go to sub-slot 0 only.
-    for (int b = 0; b < nblk; ++b) {
-      float su[3][4];
-      double sv[3][4];
+    for (int s = 0; s < SPW; ++s) {
+      const int j0 = ub[s] * kBlk4 + lane * 4;
+      if (w * SPW + s < ufull && j0 < n_pad) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d) {
+          f4v u4;
+          d2v v01, v23;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { su[d][e] = 0.f; sv[d][e] = 0.0; }
-#pragma unroll
-      for (int s = 0; s < SPW; ++s) {
-        if (w + kW4 * s < ufull && ub[s] == b) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) { su[d][e] += U[s][d][e]; sv[d][e] += V[s][d][e]; }
+          for (int e = 0; e < 4; ++e) u4[e] = (float)((double)U[s][d][e] - mu[d]);
+          v01[0] = V[s][d][0] - mv[d];
+          v01[1] = V[s][d][1] - mv[d];
+          v23[0] = V[s][d][2] - mv[d];
+          v23[1] = V[s][d][3] - mv[d];
+          stg(reinterpret_cast<f4v*>(pu + (size_t)d * n_pad + j0), u4);
+          stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0), v01);
+          stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0 + 2), v23);
         }
       }
-      store(c.slot + w, b, su, sv, w == 0);
+    }
+    return;
+  }
+  // K > 1: unit sums through the idle copy rings (unit u at u * kBF4 floats
+  // for U, u * kBF4 doubles for V), then block b (owned by worker b mod 7)
+  // adds its K units in landmark-lane order.  Three barriers, matched by the
+  // solver.
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) {
+    const int u = w * SPW + s;
+    if (u < ufull) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        f4v u4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u4[e] = U[s][d][e];
+        *reinterpret_cast<f4v*>(rings + (size_t)u * kBF4 + d * kBlk4 + lane * 4) = u4;
+      }
+    }
+  }
+  bar_lds();
+  for (int b = w; b < nblk; b += kW4) {
+    const int j0 = b * kBlk4 + lane * 4;
+    f4v acc[3] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    for (int k = 0; k < K; ++k) {
+      const float* src = rings + (size_t)(k * nblk + b) * kBF4 + lane * 4;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[d] += *reinterpret_cast<const f4v*>(src + d * kBlk4);
+    }
+    if (j0 < n_pad) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        f4v u4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u4[e] = (float)((double)acc[d][e] - mu[d]);
+        stg(reinterpret_cast<f4v*>(pu + (size_t)d * n_pad + j0), u4);
+      }
+    }
+  }
+  bar_lds();
+  double* vr = reinterpret_cast<double*>(rings);
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) {
+    const int u = w * SPW + s;
+    if (u < ufull) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        d2v v01, v23;
+        v01[0] = V[s][d][0];
+        v01[1] = V[s][d][1];
+        v23[0] = V[s][d][2];
+        v23[1] = V[s][d][3];
+        double* dst = vr + (size_t)u * kBF4 + d * kBlk4 + lane * 4;
+        *reinterpret_cast<d2v*>(dst) = v01;
+        *reinterpret_cast<d2v*>(dst + 2) = v23;
+      }
+    }
+  }
+  bar_lds();
+  for (int b = w; b < nblk; b += kW4) {
+    const int j0 = b * kBlk4 + lane * 4;
+    d2v acc[3][2] = {};
+    for (int k = 0; k < K; ++k) {
+      const double* src = vr + (size_t)(k * nblk + b) * kBF4 + lane * 4;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        acc[d][0] += *reinterpret_cast<const d2v*>(src + d * kBlk4);
+        acc[d][1] += *reinterpret_cast<const d2v*>(src + d * kBlk4 + 2);
+      }
+    }
+    if (j0 < n_pad) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        d2v v01 = acc[d][0], v23 = acc[d][1];
+        v01[0] -= mv[d];
+        v01[1] -= mv[d];
+        v23[0] -= mv[d];
+        v23[1] -= mv[d];
+        stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0), v01);
+        stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0 + 2), v23);
+      }
     }
   }
 }
@@ -429,15 +502,19 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
       e4_misc[6 + d] = tV[d];
     }
   }
-  const double Zt = __shfl(Z, 63, 64), St = __shfl(S, 63, 64);   // all lanes active here
-  if (lane < c.R) {
-    double* h = P.hdr + (size_t)(c.slot + lane) * 4;
+  if (lane == 63) {
+    double* h = P.hdr + (size_t)c.slot * 4;
     stg(h + 0, m);
-    stg(h + 1, lane == 0 ? Zt : 0.0);
-    stg(h + 2, lane == 0 ? St : 0.0);
+    stg(h + 1, Z);
+    stg(h + 2, S);
     stg(h + 3, q0);
   }
   bar_lds();
+  if (K > 1) {   // the workers' three barriers of the unit-sum reduction
+    bar_lds();
+    bar_lds();
+    bar_lds();
+  }
 }
 
 }  // namespace
@@ -464,12 +541,11 @@ __global__ __launch_bounds__(kWG4) void engine4_kernel(const Problem* __restrict
     c.n_pad = c.P->n_pad;
     c.nblk = (c.n_pad + kBlk4 - 1) / kBlk4;
     c.K = c.P->bsz;
-    c.R = e4_subslots(c.K);
     c.lam = c.P->lam;
     c.q0 = c.P->q[item.i0];
     // Shapes the host planner never produces are skipped by every wave alike.
     if (c.nL < 1 || c.nblk > kMaxBlk4 || c.K < 1 || c.K * c.nblk > kW4 * SPW) continue;
-    if (wave < kW4) e4_worker<SPW>(c, wave, lane, ring + wave * kRing4 * kBF4, xs);
+    if (wave < kW4) e4_worker<SPW>(c, wave, lane, ring + wave * kRing4 * kBF4, ring, xs);
     else e4_solver(c, lane, mode, dout);
     bar_lds();   // LDS is reused by the next item
   }

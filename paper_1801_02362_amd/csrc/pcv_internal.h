@@ -174,13 +174,11 @@ int engine3_max_blocks(int bpw);
 // Multi-landmark engine (FP32, n_pad <= 2048): spw = units (landmark lane,
 // 256-atom block) per worker wave (2 or 3).  A problem's Problem::bsz is its
 // landmark lanes K per step, at most engine4_lanes(n_pad, spw) (0: the
-// structure does not fit).  Every work item writes e4_subslots(K)
-// consecutive partial slots starting at Item::slot.
+// structure does not fit).
 template <typename T>
 hipError_t launch_engine4(int spw, int grid, const Problem* probs, const Item* items, const int* wg_off, int mode,
                           const int* flag, int run_if, double* dout, hipStream_t st);
 int engine4_lanes(int n_pad, int spw);
-__host__ __device__ inline int e4_subslots(int K) { return K == 1 ? 1 : 7; }
 
 
 bool engine_supported(EngineCfg cfg, bool fp64);
