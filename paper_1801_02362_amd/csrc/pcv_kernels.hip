@@ -250,9 +250,12 @@ __global__ __launch_bounds__(1024) void prep_kernel(const PrepArgs* __restrict__
 // decide the reassignment (strict D_xy > epsilon; always on the first frame or
 // when forced), move y <- x when reassigning, update the counters.
 template <typename T>
-__global__ __launch_bounds__(1024) void prep_close_kernel(PrepArgs a, const T* __restrict__ x,
-                                                          CloseArgs cs, Outs nan_outs) {
-  constexpr int BS = 1024;
+// 256 threads: the serial eigen-solve of thread 0 keeps its arrays in
+// registers (at 1024 threads the per-thread register budget forces them to
+// scratch memory, one cache round trip per access).
+__global__ __launch_bounds__(256) void prep_close_kernel(PrepArgs a, const T* __restrict__ x,
+                                                         CloseArgs cs, Outs nan_outs) {
+  constexpr int BS = 256;
   __shared__ double sh[16 * 9];
   __shared__ int s_flag;
   double Gx, c[3], g32[4];
@@ -845,7 +848,7 @@ hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, h
 
 template <typename T>
 hipError_t launch_prep_close(PrepArgs pa, const void* x, CloseArgs ca, Outs outs, hipStream_t st) {
-  hipLaunchKernelGGL((prep_close_kernel<T>), dim3(1), dim3(1024), 0, st, pa, (const T*)x, ca, outs);
+  hipLaunchKernelGGL((prep_close_kernel<T>), dim3(1), dim3(256), 0, st, pa, (const T*)x, ca, outs);
   return hipGetLastError();
 }
 
