@@ -14,6 +14,8 @@ implementation written from the paper (arXiv:1801.02362):
   Eq. 6, including the derivative of the close-structure rotation.
 * ``oracle.cost``  -- O4: the cost model of Section 6.2 and Eq. 7.
 * ``oracle.mlp``   -- O5: FP64 reference of the surrogate network.
+* ``oracle.bias``  -- O6: the metadynamics bias of Eq. 1 on (s, z), kept on
+  a grid with bicubic Hermite interpolation, and its gradient on the atoms.
 
 Everything is FP64 NumPy on FP64 copies of the caller's (possibly FP32)
 inputs.  The oracle shares no code, header, table or constant with the HIP

@@ -130,3 +130,44 @@ def test_untransposed_backward_weight_is_caught(monkeypatch):
         return ds[0] @ np.resize(W0, (W0.shape[1], W0.shape[0]))
     monkeypatch.setattr(om5, "input_grad", bad)
     assert not _surrogate_pins_hold()
+
+
+# --- metadynamics bias (oracle/bias.py): planted mistakes caught by its pins
+import oracle.bias as ob
+import test_oracle_bias as tb
+
+
+def test_bias_swapped_hermite_slope_basis_is_caught(monkeypatch):
+    orig = ob.hermite_basis
+
+    def bad(t):
+        (h0, h1, h2, h3), (d0, d1, d2, d3) = orig(t)
+        return (h0, h3, h2, h1), (d0, d3, d2, d1)
+
+    monkeypatch.setattr(ob, "hermite_basis", bad)
+    with pytest.raises(AssertionError):
+        tb.test_bicubic_polynomials_are_reproduced_exactly()
+
+
+def test_bias_wrong_hill_derivative_sign_is_caught(monkeypatch):
+    orig = ob.hill_sum
+
+    def bad(s, z, centres, height, sigma_s, sigma_z):
+        V, Vs, Vz, Vsz = orig(s, z, centres, height, sigma_s, sigma_z)
+        return V, -Vs, Vz, Vsz
+
+    monkeypatch.setattr(ob, "hill_sum", bad)
+    with pytest.raises(AssertionError):
+        tb.test_hill_derivatives_match_finite_differences()
+    with pytest.raises(AssertionError):
+        tb.test_fine_grid_is_within_the_hermite_error_bound()
+
+
+def test_bias_dropped_z_term_in_the_force_is_caught(monkeypatch):
+    def bad(g, s, z, ds_dx, dz_dx):
+        V, Vs, Vz, ok = ob.interpolate(g, s, z)
+        return V, Vs, Vz, ok, Vs * np.asarray(ds_dx, dtype=np.float64)
+
+    monkeypatch.setattr(ob, "bias_gradient", bad)
+    with pytest.raises(AssertionError):
+        tb.test_bias_gradient_is_the_chain_rule_through_the_path_variables()
