@@ -14,7 +14,8 @@ duration from HIP events recorded on its own stream) and ``cpu_baseline``
 
 Other workloads: ``--workload close`` (300 atoms x 500 landmarks, Algorithm 2
 along a random walk, steps/s), ``--workload batch`` (64 uneven walkers in one
-persistent launch), ``--workload surrogate`` (train the MLP surrogate on
+persistent launch), ``--workload mtd`` (close-structure CVs plus the Eq. 1
+grid bias and its atom gradient every step), ``--workload surrogate`` (train the MLP surrogate on
 exact-labelled walks, then compare exact, close-structure and surrogate
 steps/s and |ds| on the test walk) and ``--workload copy`` (a plain device
 copy used to calibrate the traffic counters).
@@ -202,6 +203,62 @@ def bench_close(args):
                       "exact_steps_per_s": round(args.steps / dt_ex, 1)}}
     cv.close()
     ex.close()
+    return out
+
+
+def bench_mtd(args):
+    """Metadynamics step on the 300-atom, 500-landmark path: close-structure
+    path CVs (Algorithm 2), the grid bias of Eq. 1 and its atom gradient every
+    step, a hill every ``--hill-stride`` steps; steps/s with and without the
+    bias on the same walk."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    dev = torch.device("cuda", 0)
+    L = sysm.n_landmarks
+    cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, eps=0.01)
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])
+    x.copy_(x_all[0])
+    z0 = float(cv.eval(x)["sz"][1].item())
+    bias = pcv.Bias((0.0, L + 1.0), (z0 - 0.5, z0 + 0.5), (4 * (L + 1) + 1, 401), 1.0, (0.5, 0.01))
+    o = cv.eval_close(x)        # output buffers reused by every step
+    cv.reset_stats()
+    g = {}
+
+    def run(with_bias, t0, count):
+        for t in range(count):
+            x.copy_(x_all[t0 + t])
+            r = cv.eval_close(x, out=o)
+            if with_bias:
+                gr = bias.gradient(r["sz"], r["ds_dx"], r["dz_dx"], out=g)
+                g.update({"grad": gr[0], "v": gr[1], "in_range": gr[2]})
+                if (t0 + t) % args.hill_stride == 0:
+                    bias.deposit(r["sz"])
+
+    run(True, 0, args.warmup)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run(True, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    hills = bias.hills()
+    t2 = time.perf_counter()
+    run(False, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    dt_cv = time.perf_counter() - t2
+    out = {"metric": "metadynamics CV+bias steps/s", "value": round(args.steps / dt, 1), "unit": "steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 coords, f64 correlation/eigen/lse/bias grid", "data": "synthetic",
+           "config": {"workload": f"close-structure path CVs (300 atoms x 500 landmarks) + Eq. 1 grid bias "
+                                  f"({4 * (L + 1) + 1} x 401 nodes, hill every {args.hill_stride} steps)",
+                      "hills": hills, "cv_only_steps_per_s": round(args.steps / dt_cv, 1),
+                      "bias_us_per_step": round((dt - dt_cv) / args.steps * 1e6, 2)}}
+    cv.close()
+    bias.close()
     return out
 
 
@@ -406,7 +463,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate"], default="exact")
+    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate", "mtd"], default="exact")
+    ap.add_argument("--hill-stride", type=int, default=50)
     ap.add_argument("--train-walks", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--test-frames", type=int, default=10000)
@@ -434,6 +492,8 @@ def main():
         out = bench_copy(args)
     elif args.workload == "surrogate":
         out = bench_surrogate(args)
+    elif args.workload == "mtd":
+        out = bench_mtd(args)
     else:
         out = bench_batch(args)
     print(json.dumps(out), flush=True)

@@ -335,6 +335,58 @@ pcv_status pcv_mlp_get_stats(pcv_mlp* m, pcv_mlp_stats* out);
 pcv_status pcv_mlp_reset_stats(pcv_mlp* m);
 const char* pcv_mlp_last_error(const pcv_mlp* m);
 
+/* ------------------------------------------------------------------------
+ * Metadynamics bias on the path variables (Eq. 1).
+ *
+ * Hills w exp(-(s - s_k)^2 / (2 sigma_s^2) - (z - z_k)^2 / (2 sigma_z^2))
+ * deposited at earlier CV values are summed on a regular (s, z) grid, as in
+ * the paper's runs (one height per hill, one width per CV; the paper's single
+ * sigma is sigma_s = sigma_z).  Every node holds the exact hill sum and its
+ * derivatives dV/ds, dV/dz, d2V/dsdz; between nodes the bias is their bicubic
+ * Hermite interpolant; outside the grid it is zero.  The handle owns the
+ * grid (4 ns nz doubles of device memory); all calls are asynchronous on the
+ * options' stream unless stated.  A bias handle is not thread-safe.
+ */
+typedef struct pcv_bias pcv_bias;
+typedef struct pcv_bias_options {
+  int device;              /* HIP device ordinal */
+  void* stream;            /* hipStream_t; NULL = the null stream */
+  double s_min, s_max;     /* s range of the grid (nodes s_min + i (s_max - s_min)/(ns - 1)) */
+  int ns;                  /* nodes along s, >= 2 */
+  double z_min, z_max;     /* z range (nm^2) */
+  int nz;                  /* nodes along z, >= 2 (ns nz <= 2^28) */
+  double height;           /* hill height w (energy units) */
+  double sigma_s, sigma_z; /* hill widths, > 0 */
+} pcv_bias_options;
+
+/* PCV_EINVAL for a bad range, size, height or width; PCV_ENOMEM / PCV_EHIP. */
+pcv_status pcv_bias_create(pcv_bias** out, const pcv_bias_options* opt);
+pcv_status pcv_bias_destroy(pcv_bias* b);
+
+/* Eq. 1, one more hill at the CV values in device memory: sz_dev[0] = s,
+ * sz_dev[1] = z (for example the sz output of pcv_eval_close).  Non-finite
+ * values deposit nothing.  Deposits are applied in stream order. */
+pcv_status pcv_bias_deposit(pcv_bias* b, const double* sz_dev);
+
+/* Bias at the CV values sz_dev (device double[2]) and its gradient on the
+ * atoms, dV/dx_k = dV/ds ds/dx_k + dV/dz dz/dx_k (the bias force is its
+ * negative).
+ *   n_atoms, precision   size and coordinate type (PCV_FP32 / PCV_FP64) of
+ *                        ds_dx, dz_dx and grad_out, device [n][3]
+ *   grad_out             device [n][3] or NULL (then ds_dx, dz_dx unused);
+ *                        must not alias ds_dx or dz_dx
+ *   v_dev                device double[3] or NULL: V, dV/ds, dV/dz
+ *   in_range_dev         device int or NULL: 1 inside the grid, 0 outside
+ *                        (V and its derivatives are 0 there) */
+pcv_status pcv_bias_gradient(pcv_bias* b, const double* sz_dev, int n_atoms, int precision, const void* ds_dx,
+                             const void* dz_dx, void* grad_out, double* v_dev, int* in_range_dev);
+/* Hills deposited so far (host counter). */
+pcv_status pcv_bias_hills(const pcv_bias* b, long long* count);
+/* Copy the grid to host memory [4][ns][nz] (V, dV/ds, dV/dz, d2V/dsdz);
+ * synchronises the stream. */
+pcv_status pcv_bias_get_grid(pcv_bias* b, double* host_out);
+const char* pcv_bias_last_error(const pcv_bias* b);
+
 #ifdef __cplusplus
 }
 #endif

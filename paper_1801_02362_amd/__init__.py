@@ -14,7 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["PcvError", "PathCV", "BatchPathCV", "Surrogate", "library_path", "load_library", "FP32", "FP64"]
+__all__ = ["PcvError", "PathCV", "BatchPathCV", "Surrogate", "Bias", "library_path", "load_library", "FP32", "FP64"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FP32, FP64 = 32, 64
@@ -32,6 +32,13 @@ class PcvError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("eps", ctypes.c_double), ("use_graph", ctypes.c_int)]
+
+
+class _BiasOptions(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("s_min", ctypes.c_double),
+                ("s_max", ctypes.c_double), ("ns", ctypes.c_int), ("z_min", ctypes.c_double),
+                ("z_max", ctypes.c_double), ("nz", ctypes.c_int), ("height", ctypes.c_double),
+                ("sigma_s", ctypes.c_double), ("sigma_z", ctypes.c_double)]
 
 
 class _Plan(ctypes.Structure):
@@ -109,6 +116,13 @@ def load_library():
         "pcv_mlp_get_stats": (st, [vp, ctypes.POINTER(_MlpStats)]),
         "pcv_mlp_reset_stats": (st, [vp]),
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
+        "pcv_bias_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_BiasOptions)]),
+        "pcv_bias_destroy": (st, [vp]),
+        "pcv_bias_deposit": (st, [vp, vp]),
+        "pcv_bias_gradient": (st, [vp, vp, i, i, vp, vp, vp, vp, vp]),
+        "pcv_bias_hills": (st, [vp, ctypes.POINTER(ctypes.c_longlong)]),
+        "pcv_bias_get_grid": (st, [vp, vp]),
+        "pcv_bias_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -495,3 +509,80 @@ class Surrogate:
 
     def reset_stats(self):
         self._check(self._L.pcv_mlp_reset_stats(self._h))
+
+
+class Bias:
+    """Metadynamics bias of Eq. 1 on (s, z), kept on a device grid.
+
+    ``s_range``, ``z_range``: (min, max); ``bins``: (ns, nz) nodes;
+    ``height`` and ``sigma`` = (sigma_s, sigma_z) of every hill.
+    """
+
+    def __init__(self, s_range, z_range, bins, height: float, sigma, *, stream=None, device: int = 0):
+        self._L = load_library()
+        o = _BiasOptions()
+        o.device = device
+        o.stream = _stream_ptr(stream)
+        o.s_min, o.s_max = float(s_range[0]), float(s_range[1])
+        o.z_min, o.z_max = float(z_range[0]), float(z_range[1])
+        o.ns, o.nz = int(bins[0]), int(bins[1])
+        o.height = float(height)
+        o.sigma_s, o.sigma_z = float(sigma[0]), float(sigma[1])
+        self.shape = (o.ns, o.nz)
+        h = ctypes.c_void_p()
+        st = self._L.pcv_bias_create(ctypes.byref(h), ctypes.byref(o))
+        if st != 0:
+            raise PcvError(st, self._L.pcv_status_string(st).decode())
+        self._h = h
+
+    def _check(self, s):
+        if s != 0:
+            msg = self._L.pcv_bias_last_error(self._h).decode()
+            raise PcvError(s, f"{self._L.pcv_status_string(s).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pcv_bias_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def deposit(self, sz):
+        """One hill at the CV values of the device tensor ``sz`` (float64 [2])."""
+        self._check(self._L.pcv_bias_deposit(self._h, _ptr(sz)))
+
+    def gradient(self, sz, ds_dx=None, dz_dx=None, *, out=None):
+        """Bias (V, dV/ds, dV/dz) at ``sz`` and dV/dx (same dtype as ds_dx).
+        Returns (grad or None, v [3] float64, in_range [1] int32), all device tensors."""
+        import torch
+        o = out or {}
+        v = o.get("v") if o.get("v") is not None else torch.empty(3, dtype=torch.float64, device=sz.device)
+        ok = o.get("in_range") if o.get("in_range") is not None else torch.empty(1, dtype=torch.int32,
+                                                                                 device=sz.device)
+        grad = None
+        n, prec = 0, FP32
+        if ds_dx is not None:
+            if dz_dx is None or ds_dx.shape != dz_dx.shape or ds_dx.dtype != dz_dx.dtype:
+                raise ValueError("ds_dx and dz_dx must match")
+            n = ds_dx.shape[0]
+            prec = FP64 if ds_dx.dtype == torch.float64 else FP32
+            grad = o.get("grad") if o.get("grad") is not None else torch.empty_like(ds_dx)
+        self._check(self._L.pcv_bias_gradient(self._h, _ptr(sz), n, prec, _ptr(ds_dx), _ptr(dz_dx), _ptr(grad),
+                                              _ptr(v), _ptr(ok)))
+        return grad, v, ok
+
+    def hills(self) -> int:
+        c = ctypes.c_longlong()
+        self._check(self._L.pcv_bias_hills(self._h, ctypes.byref(c)))
+        return c.value
+
+    def grid(self):
+        """Host copy [4][ns][nz]: V, dV/ds, dV/dz, d2V/dsdz at the nodes."""
+        import numpy as np
+        out = np.empty((4,) + self.shape, dtype=np.float64)
+        self._check(self._L.pcv_bias_get_grid(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
