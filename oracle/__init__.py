@@ -16,6 +16,8 @@ implementation written from the paper (arXiv:1801.02362):
 * ``oracle.mlp``   -- O5: FP64 reference of the surrogate network.
 * ``oracle.bias``  -- O6: the metadynamics bias of Eq. 1 on (s, z), kept on
   a grid with bicubic Hermite interpolation, and its gradient on the atoms.
+* ``oracle.nl``    -- O7: neighbour lists (Section 2) with Algorithm 1 and
+  with the close structure (selection by Eq. 5 at list updates, Section 3.2).
 
 Everything is FP64 NumPy on FP64 copies of the caller's (possibly FP32)
 inputs.  The oracle shares no code, header, table or constant with the HIP

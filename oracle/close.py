@@ -34,7 +34,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .msd import normalise_weights, centre, superpose, rotation_adjoint, rotation_term
-from .path import PathResult, path_sz, path_cv
+from .path import PathResult, default_q, path_sz, path_cv
 
 __all__ = ["CloseStep", "CloseStructure", "approx_distances"]
 
@@ -83,11 +83,17 @@ class CloseStructure:
         return res
 
     # -- Algorithm 2, approximate branch (Eq. 5 and Eq. 6) ---------------
-    def _approx(self, x, sp_xy) -> PathResult:
+    def _approx(self, x, sp_xy, idx=None) -> PathResult:
+        """Eq. 5 / Eq. 6 over all landmarks, or over the subset ``idx``
+        (a neighbour list; properties follow their landmarks)."""
         w, wp = self.w, self.wp
         x_c = sp_xy.x_c
-        D, d, B = approx_distances(x_c, sp_xy.R, self.R_save, self.A_c, w)
-        res = path_sz(D, self.lam, self.q)
+        R_save, A_c, q = self.R_save, self.A_c, self.q
+        if idx is not None:
+            q = (default_q(self.L) if q is None else np.asarray(q, dtype=np.float64))[idx]
+            R_save, A_c = R_save[idx], A_c[idx]
+        D, d, B = approx_distances(x_c, sp_xy.R, R_save, A_c, w)
+        res = path_sz(D, self.lam, q)
         # Eq. 6 for each landmark: displacement + centre-of-mass + rotation terms.
         g = 2.0 * w[None, :, None] * d
         g -= 2.0 * wp[None, :, None] * np.einsum("j,ija->ia", w, d)[:, None, :]
@@ -96,7 +102,7 @@ class CloseStructure:
         g += rotation_term(Gamma, self.y[None], wp)
         res.ds_dx = np.einsum("i,ija->ja", res.c, g)
         res.dz_dx = np.einsum("i,ija->ja", res.p, g)
-        res.R = np.einsum("ab,ibc->iac", sp_xy.R, self.R_save)
+        res.R = np.einsum("ab,ibc->iac", sp_xy.R, R_save)
         return res
 
     def step(self, x, force: bool | None = None) -> CloseStep:

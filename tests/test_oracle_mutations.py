@@ -171,3 +171,35 @@ def test_bias_dropped_z_term_in_the_force_is_caught(monkeypatch):
     monkeypatch.setattr(ob, "bias_gradient", bad)
     with pytest.raises(AssertionError):
         tb.test_bias_gradient_is_the_chain_rule_through_the_path_variables()
+
+
+# --- neighbour list (oracle/nl.py)
+import oracle.nl as onl
+import test_oracle_nl as tn
+
+
+def test_nl_farthest_members_are_caught(monkeypatch):
+    orig = onl.nearest
+    monkeypatch.setattr(onl, "nearest", lambda D, M: orig(-np.asarray(D), M))
+    with pytest.raises(AssertionError):
+        tn.test_members_are_the_brute_force_nearest_of_the_update_frame()
+
+
+def test_nl_stale_list_is_caught(monkeypatch):
+    orig = onl.nearest
+    calls = []
+
+    def first_only(D, M):          # the list is chosen once and never refreshed
+        calls.append(1)
+        return orig(D, M) if len(calls) == 1 else first_only.kept
+    first_only.kept = None
+
+    def wrapped(D, M):
+        r = first_only(D, M)
+        if first_only.kept is None:
+            first_only.kept = r
+        return r
+
+    monkeypatch.setattr(onl, "nearest", wrapped)
+    with pytest.raises(AssertionError):
+        tn.test_members_are_the_brute_force_nearest_of_the_update_frame()
