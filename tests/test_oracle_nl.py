@@ -12,13 +12,18 @@ from oracle.msd import msd
 from oracle.path import landmark_lambda, path_cv
 
 
-def _walk(n=12, L=30, T=24, seed=3, step=0.01):
+def _walk(n=12, L=30, T=24, seed=3, step=0.01, drift=False):
+    """Random walk from a waypoint; with ``drift`` it also slides along the
+    path (landmark 1 to landmark L over the walk), so the nearest set moves."""
     sp = wl.small_path(n, L, seed, dtype=np.float64)
     rng = np.random.default_rng(seed + 1)
-    x0 = sp.waypoints[1]
+    x0 = sp.landmarks[0] if drift else sp.waypoints[1]
     frames = [x0]
-    for _ in range(T - 1):
-        frames.append(frames[-1] + rng.normal(0, step, x0.shape))
+    noise = np.zeros_like(x0)
+    for t in range(1, T):
+        noise = noise + rng.normal(0, step, x0.shape)
+        base = (1 - t / (T - 1)) * sp.landmarks[0] + (t / (T - 1)) * sp.landmarks[-1] if drift else x0
+        frames.append(base + noise)
     return sp.landmarks, landmark_lambda(sp.landmarks), np.array(frames)
 
 
@@ -56,7 +61,7 @@ def test_stride_one_is_the_plain_close_structure():
 
 
 def test_members_are_the_brute_force_nearest_of_the_update_frame():
-    A, lam, frames = _walk(T=13)
+    A, lam, frames = _walk(T=13, drift=True)
     M, L_nl = 6, 4
     q = np.arange(1, A.shape[0] + 1.0)
     ex = nl.ExactNeighbourList(A, lam, M=M, L_nl=L_nl)
