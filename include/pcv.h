@@ -147,6 +147,35 @@ pcv_status pcv_force_reassign(pcv_handle* h);
 /* Reassign now: y <- x and recompute every saved rotation R_{a_i y}. */
 pcv_status pcv_update_close(pcv_handle* h, const void* x);
 
+/*
+ * Neighbour list (Section 2; with the close structure, Section 3.2).
+ * With M > 0, pcv_eval and pcv_eval_close use the M references nearest to
+ * the structure, refreshed every `stride` calls (calls counted from 0 after
+ * this one; call t refreshes when t is a multiple of stride; pcv_update_close
+ * is not counted).  A refreshing call evaluates all L references (its s, z
+ * and gradients use all of them) and keeps the M nearest, ties to the lower
+ * index: pcv_eval by the exact distances, pcv_eval_close by that call's
+ * distances (exact when it reassigns the close structure, Eq. 5 otherwise).
+ * Other calls evaluate the members only: pcv_eval exactly, pcv_eval_close by
+ * Eq. 5 -- except on a reassignment, which evaluates all L exactly (its CV
+ * uses all of them) and refreshes the members' saved rotations without
+ * changing the members.  Counters follow Section 6.2: expensive_msd grows by
+ * L on a refreshing pcv_eval call and by M on the others; pcv_eval_close
+ * counts as without a list (1 per call + L per reassignment).
+ *   M       0 switches the list off; otherwise 1 <= M <= L
+ *   stride  >= 1
+ * PCV_EINVAL for bad M / stride; PCV_EUNSUPPORTED when L > 8192.  While a
+ * list is on, the msd output of pcv_eval / pcv_eval_close must be NULL.
+ * Allocates M (3 n_pad coordinates + 14 doubles) + L doubles of device
+ * memory and synchronises the stream; loading landmarks switches it off.
+ */
+pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride);
+/* The current members (host copy, nearest first as chosen; the first M
+ * references before the first refresh).  *count = M (0 when off); members
+ * (NULL: only the count) must hold `capacity` >= M ints.  Synchronises the
+ * stream. */
+pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int capacity, int* count);
+
 /* Counters (synchronises the stream). */
 pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out);
 pcv_status pcv_reset_stats(pcv_handle* h);

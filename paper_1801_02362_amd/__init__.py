@@ -116,6 +116,8 @@ def load_library():
         "pcv_mlp_get_stats": (st, [vp, ctypes.POINTER(_MlpStats)]),
         "pcv_mlp_reset_stats": (st, [vp]),
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
+        "pcv_set_neighbour_list": (st, [vp, i, i]),
+        "pcv_get_neighbour_list": (st, [vp, vp, i, ctypes.POINTER(i)]),
         "pcv_bias_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_BiasOptions)]),
         "pcv_bias_destroy": (st, [vp]),
         "pcv_bias_deposit": (st, [vp, vp]),
@@ -255,6 +257,22 @@ class PathCV:
 
     def force_reassign(self):
         self._check(self._L.pcv_force_reassign(self._h))
+
+    def set_neighbour_list(self, M: int, stride: int = 1):
+        """Neighbour list of the ``M`` nearest references refreshed every
+        ``stride`` calls (``M = 0``: off).  See ``pcv_set_neighbour_list``."""
+        self._check(self._L.pcv_set_neighbour_list(self._h, int(M), int(stride)))
+
+    def neighbour_list(self):
+        """Current members (host int array, empty when off)."""
+        import numpy as np
+        cnt = ctypes.c_int()
+        self._check(self._L.pcv_get_neighbour_list(self._h, None, 0, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, dtype=np.int32)
+        if cnt.value:
+            self._check(self._L.pcv_get_neighbour_list(self._h, out.ctypes.data_as(ctypes.c_void_p), cnt.value,
+                                                        ctypes.byref(cnt)))
+        return out
 
     def stats(self) -> dict:
         st = _Stats()

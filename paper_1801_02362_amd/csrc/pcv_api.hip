@@ -77,6 +77,21 @@ struct pcv_handle {
   int* d_wgoff = nullptr;
   PrepArgs* d_prep = nullptr;   // Algorithm 1 prep arguments (one problem)
   int plan_version = 0;
+  // neighbour list (Section 2): members, their compact landmark set and its
+  // work items (the engine configuration is the full set's)
+  int nl_M = 0, nl_stride = 0;
+  long long nl_step = 0;
+  DevMem nlmem, nlpmem;
+  int* nl_members = nullptr;
+  void* A_nl = nullptr;
+  double *ca_nl = nullptr, *Ga_nl = nullptr, *q_nl = nullptr, *Rsave_nl = nullptr, *dfull = nullptr;
+  double* hdr_nl = nullptr;
+  void* vec_nl = nullptr;
+  Problem* d_prob_nl = nullptr;   // [3]: EXACT, EXACT_SAVE, APPROX
+  Item* d_items_nl = nullptr;
+  int* d_wgoff_nl = nullptr;
+  PrepArgs* d_prep_nl = nullptr;
+  int grid_nl = 0, items_nl = 0;
   // graphs
   struct GraphEntry {
     const void* key[7];
@@ -163,12 +178,16 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   collect_timing(h);
   drop_graphs(h);
+  h->nlpmem.release();
+  h->nlmem.release();
   h->pmem.release();
   h->mem.release();
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return PCV_OK;
 }
+
+static pcv_status build_nl_plan(pcv_handle* h, const Problem& full);
 
 // Build (or rebuild) work items and problem descriptors for the current plan.
 static pcv_status build_plan(pcv_handle* h) {
@@ -247,6 +266,62 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, hipMemcpy(h->d_prob, probs, sizeof(probs), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->plan_version++;
+  drop_graphs(h);
+  if (h->nl_M > 0) {
+    pcv_status s = build_nl_plan(h, base);
+    if (s != PCV_OK) return s;
+  }
+  return PCV_OK;
+}
+
+// Work items and descriptors of the neighbour-list set (M landmarks in the
+// compact buffers), with the full set's engine configuration; `full` is the
+// full set's problem descriptor (frame buffers, lambda, tiling).
+static pcv_status build_nl_plan(pcv_handle* h, const Problem& full) {
+  const Plan& p = h->plan;
+  const int M = h->nl_M;
+  const int unit = (p.engine == 2 || p.engine == 4) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
+  const int units = (M + unit - 1) / unit;
+  const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
+  const int n_items = std::max(1, std::min(units, cap));
+  h->nlpmem.release();
+  HIP_TRY(h, h->nlpmem.alloc((void**)&h->hdr_nl, (size_t)n_items * 4 * sizeof(double)));
+  HIP_TRY(h, h->nlpmem.alloc(&h->vec_nl, (size_t)n_items * (h->fp64 ? partial_bytes<double>(h->n_pad)
+                                                                     : partial_bytes<float>(h->n_pad))));
+  HIP_TRY(h, h->nlpmem.alloc((void**)&h->d_prob_nl, 3 * sizeof(Problem)));
+  HIP_TRY(h, h->nlpmem.alloc((void**)&h->d_items_nl, (size_t)n_items * sizeof(Item)));
+  HIP_TRY(h, h->nlpmem.alloc((void**)&h->d_wgoff_nl, (size_t)(n_items + 1) * sizeof(int)));
+  HIP_TRY(h, h->nlpmem.alloc((void**)&h->d_prep_nl, sizeof(PrepArgs)));
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, h->counters, h->n, h->n_pad, M};
+  pa.xw32 = h->xw32;
+  pa.n_x = h->n_x;
+  HIP_TRY(h, hipMemcpy(h->d_prep_nl, &pa, sizeof(pa), hipMemcpyHostToDevice));
+  std::vector<Item> items(n_items);
+  std::vector<int> wgoff(n_items + 1);
+  for (int k = 0; k < n_items; ++k) {
+    const int u0 = (int)((long long)k * units / n_items);
+    const int u1 = (int)((long long)(k + 1) * units / n_items);
+    items[k] = Item{0, std::min(M, u0 * unit), std::min(M, u1 * unit), k};
+    wgoff[k] = k;
+  }
+  wgoff[n_items] = n_items;
+  Problem b = full;
+  b.A = h->A_nl;
+  b.ca = h->ca_nl;
+  b.Ga = h->Ga_nl;
+  b.q = h->q_nl;
+  b.Rsave = h->Rsave_nl;
+  b.hdr = h->hdr_nl;
+  b.vec = h->vec_nl;
+  b.L = M;
+  b.n_slots = n_items;
+  Problem probs[3] = {b, b, b};
+  HIP_TRY(h, hipMemcpy(h->d_prob_nl, probs, sizeof(probs), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_items_nl, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_wgoff_nl, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
+  h->grid_nl = n_items;
+  h->items_nl = n_items;
   h->plan_version++;
   drop_graphs(h);
   return PCV_OK;
@@ -357,6 +432,11 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, hipSetDevice(h->opt.device));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   drop_graphs(h);
+  h->nlpmem.release();
+  h->nlmem.release();
+  h->nl_M = 0;
+  h->nl_stride = 0;
+  h->nl_step = 0;
   h->pmem.release();
   h->mem.release();
   h->n = n_atoms;
@@ -452,7 +532,8 @@ extern "C" pcv_status pcv_path_lambda(pcv_handle* h, double factor, double* lamb
 // ---------------------------------------------------------------- Algorithm 1
 // Engine launch bracketed by events when kernel timing is on.
 template <typename T>
-static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd) {
+static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd,
+                               bool nl = false) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     (void)hipEventCreate(&e0);
@@ -460,17 +541,20 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
     (void)hipEventRecord(e0, st);
   }
   const Plan& p = h->plan;
+  const Problem* probs = (nl ? h->d_prob_nl : h->d_prob) + mode;
+  const Item* items = nl ? h->d_items_nl : h->d_items;
+  const int* wgoff = nl ? h->d_wgoff_nl : h->d_wgoff;
+  const int grid = nl ? h->grid_nl : p.grid;
   hipError_t e;
   if (p.engine == 4)
-    e = launch_engine4<T>(p.spw, p.grid, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if, msd, st);
+    e = launch_engine4<T>(p.spw, grid, probs, items, wgoff, mode, flag, run_if, msd, st);
   else if (p.engine == 3)
-    e = launch_engine3<T>(p.bpw, p.grid, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if, msd, st);
+    e = launch_engine3<T>(p.bpw, grid, probs, items, wgoff, mode, flag, run_if, msd, st);
   else if (p.engine == 2)
-    e = launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, p.grid, p.lds, p.lbuf, p.B, h->d_prob + mode, h->d_items,
-                          h->d_wgoff, mode, flag, run_if, msd, st);
+    e = launch_engine2<T>(p.c2.ncw, p.c2.aptc, p.c2.aptg, grid, p.lds, p.lbuf, p.B, probs, items, wgoff, mode, flag,
+                          run_if, msd, st);
   else
-    e = launch_engine<T>(p.cfg, p.grid, p.lds, h->d_prob + mode, h->d_items, h->d_wgoff, mode, flag, run_if,
-                         msd, st);
+    e = launch_engine<T>(p.cfg, grid, p.lds, probs, items, wgoff, mode, flag, run_if, msd, st);
   if (h->timing) {
     (void)hipEventRecord(e1, st);
     h->ev_pending.emplace_back(e0, e1);
@@ -507,6 +591,67 @@ static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, do
   e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
   if (e != hipSuccess) return e;
   return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
+}
+
+template <typename T>
+static hipError_t nl_gather(pcv_handle* h, hipStream_t st, const int* flag, int run_if) {
+  NlGather g{h->nl_members, h->nl_M, h->n_pad, h->A, h->ca, h->Ga, h->q, h->Rsave,
+             h->A_nl, h->ca_nl, h->Ga_nl, h->q_nl, h->Rsave_nl};
+  return launch_nl_gather<T>(g, flag, run_if, st);
+}
+
+// Algorithm 1 with a neighbour list: an update step evaluates every
+// reference (its CV uses all of them) and keeps the M nearest; the steps in
+// between evaluate the list only.
+template <typename T>
+static hipError_t enqueue_exact_nl(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds, void* dz,
+                                   bool update) {
+  Outs o{ds, dz, sz, nullptr};
+  if (update) {
+    hipError_t e = launch_prep<T>(h->d_prep, x, 1, st);
+    if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, h->dfull);
+    if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
+    if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
+    return e;
+  }
+  hipError_t e = launch_prep<T>(h->d_prep_nl, x, 1, st);
+  if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, nullptr, true);
+  if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob_nl + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+  return e;
+}
+
+// Algorithm 2 with a neighbour list (Section 3.2): a reassignment evaluates
+// every reference exactly (its CV uses all of them); an update step without
+// reassignment evaluates every reference by Eq. 5; both update steps keep the
+// M nearest by that step's distances.  Other steps evaluate the list by
+// Eq. 5; a reassignment between updates refreshes the members' rotations.
+template <typename T>
+static hipError_t enqueue_close_nl(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds, void* dz,
+                                   int* rec, bool update) {
+  PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, nullptr, h->n, h->n_pad, h->L};
+  pa.xw32 = h->xw32;
+  pa.n_x = h->n_x;
+  CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+  Outs o{ds, dz, sz, rec};
+  hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
+  if (e != hipSuccess) return e;
+  if (update) {
+    e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, h->dfull);
+    if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, h->dfull);
+    if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+    if (e == hipSuccess) e = launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
+    if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
+    if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
+    return e;
+  }
+  e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, nullptr);
+  if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+  if (e == hipSuccess) e = nl_gather<T>(h, st, h->flag, 1);
+  if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, nullptr, true);
+  if (e == hipSuccess) e = launch_merge_close<T>(h->d_prob_nl + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
+  return e;
 }
 
 // Run an enqueue function directly or through a cached hipGraph keyed on the
@@ -554,6 +699,17 @@ extern "C" pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* d
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
   PrepArgs* d_pa = h->d_prep;
+  if (h->nl_M > 0) {
+    if (msd) return fail(h, PCV_EINVAL, "msd output is not available with a neighbour list");
+    const bool update = h->nl_step % h->nl_stride == 0;
+    const void* key[7] = {x, sz, ds_dx, dz_dx, nullptr, nullptr, (const void*)(update ? 3 : 4)};
+    pcv_status s = run_maybe_graph(h, key, [&](hipStream_t st) {
+      return h->fp64 ? enqueue_exact_nl<double>(h, st, x, sz, ds_dx, dz_dx, update)
+                     : enqueue_exact_nl<float>(h, st, x, sz, ds_dx, dz_dx, update);
+    });
+    if (s == PCV_OK) h->nl_step++;
+    return s;
+  }
   const void* key[7] = {x, sz, ds_dx, dz_dx, msd, nullptr, (const void*)1};
   return run_maybe_graph(h, key, [&](hipStream_t st) {
     return h->fp64 ? enqueue_exact<double>(h, st, x, sz, ds_dx, dz_dx, msd, d_pa)
@@ -562,16 +718,82 @@ extern "C" pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* d
 }
 
 // ---------------------------------------------------------------- Algorithm 2
-extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx,
-                                     double* msd, int* recomputed) {
+// advance: a simulation step (counts toward the neighbour-list stride).
+static pcv_status eval_close_impl(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx, double* msd,
+                                  int* recomputed, bool advance) {
   if (!h) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
+  if (h->nl_M > 0) {
+    if (msd) return fail(h, PCV_EINVAL, "msd output is not available with a neighbour list");
+    const bool update = advance && h->nl_step % h->nl_stride == 0;
+    const void* key[7] = {x, sz, ds_dx, dz_dx, nullptr, recomputed, (const void*)(update ? 5 : 6)};
+    pcv_status s = run_maybe_graph(h, key, [&](hipStream_t st) {
+      return h->fp64 ? enqueue_close_nl<double>(h, st, x, sz, ds_dx, dz_dx, recomputed, update)
+                     : enqueue_close_nl<float>(h, st, x, sz, ds_dx, dz_dx, recomputed, update);
+    });
+    if (s == PCV_OK && advance) h->nl_step++;
+    return s;
+  }
   const void* key[7] = {x, sz, ds_dx, dz_dx, msd, recomputed, (const void*)2};
   return run_maybe_graph(h, key, [&](hipStream_t st) {
     return h->fp64 ? enqueue_close<double>(h, st, x, sz, ds_dx, dz_dx, msd, recomputed)
                    : enqueue_close<float>(h, st, x, sz, ds_dx, dz_dx, msd, recomputed);
   });
+}
+
+extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx,
+                                     double* msd, int* recomputed) {
+  return eval_close_impl(h, x, sz, ds_dx, dz_dx, msd, recomputed, true);
+}
+
+extern "C" pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (M < 0 || (M > 0 && (M > h->L || stride < 1))) return fail(h, PCV_EINVAL, "need 1 <= M <= L and stride >= 1");
+  if (M > 0 && h->L > nl_select_max())
+    return fail(h, PCV_EUNSUPPORTED, "neighbour lists need L <= " + std::to_string(nl_select_max()));
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  drop_graphs(h);
+  h->nlpmem.release();
+  h->nlmem.release();
+  h->nl_M = 0;
+  h->nl_stride = 0;
+  h->nl_step = 0;
+  h->plan_version++;
+  if (M == 0) return PCV_OK;
+  const size_t tsz = h->fp64 ? 8 : 4;
+  DevMem& m = h->nlmem;
+  HIP_TRY(h, m.alloc((void**)&h->nl_members, (size_t)M * sizeof(int)));
+  HIP_TRY(h, m.alloc(&h->A_nl, (size_t)M * 3 * h->n_pad * tsz));
+  HIP_TRY(h, m.alloc((void**)&h->ca_nl, (size_t)M * 3 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Ga_nl, (size_t)M * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->q_nl, (size_t)M * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rsave_nl, (size_t)M * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->dfull, (size_t)h->L * sizeof(double)));
+  std::vector<int> first(M);
+  for (int k = 0; k < M; ++k) first[k] = k;
+  HIP_TRY(h, hipMemcpy(h->nl_members, first.data(), M * sizeof(int), hipMemcpyHostToDevice));
+  h->nl_M = M;
+  h->nl_stride = stride;
+  pcv_status s = build_plan(h);
+  if (s != PCV_OK) return s;
+  // Start from the first M references so that every buffer holds valid data.
+  hipError_t e = h->fp64 ? nl_gather<double>(h, h->stream, nullptr, 0) : nl_gather<float>(h, h->stream, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(h, e, "neighbour-list gather");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int capacity, int* count) {
+  if (!h || !count) return PCV_EINVAL;
+  *count = h->nl_M;
+  if (h->nl_M == 0 || !members) return PCV_OK;   // NULL members: size query
+  if (capacity < h->nl_M) return fail(h, PCV_EINVAL, "members buffer too small");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(members, h->nl_members, (size_t)h->nl_M * sizeof(int), hipMemcpyDeviceToHost));
+  return PCV_OK;
 }
 
 // Exact half of the surrogate's fallback step: the close-structure drift test
@@ -605,7 +827,7 @@ extern "C" pcv_status pcv_force_reassign(pcv_handle* h) {
 extern "C" pcv_status pcv_update_close(pcv_handle* h, const void* x) {
   pcv_status s = pcv_force_reassign(h);
   if (s != PCV_OK) return s;
-  return pcv_eval_close(h, x, h->scratch_sz, nullptr, nullptr, nullptr, nullptr);
+  return eval_close_impl(h, x, h->scratch_sz, nullptr, nullptr, nullptr, nullptr, false);
 }
 
 extern "C" pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out) {

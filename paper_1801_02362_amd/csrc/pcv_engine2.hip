@@ -39,7 +39,7 @@ template <typename T> struct UAcc { using type = float; };
 template <> struct UAcc<double> { using type = double; };
 
 constexpr int kWG2 = 512;
-constexpr int kRes = 12;    // doubles per landmark result: R[9], al, be, sc
+constexpr int kRes = 13;    // doubles per landmark result: R[9], al, be, sc, dq
 
 __device__ __forceinline__ double clamp0_2(double v) { return v < 0.0 ? 0.0 : v; }
 __device__ __forceinline__ double scale2(double m_from, double m_to, double lam) {
@@ -199,7 +199,10 @@ template <typename T, int NCW>
 __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
   const int lane = opaque(lane_in);
   const Problem& P = *c.P;
-  const double lam = c.lam, q0 = c.q0;
+  const double lam = c.lam;
+  // Reference property of U = sum e (q - q0) r: the property of the running
+  // minimum's landmark (keeps U small where the weights are large).
+  double q0 = c.q0;
   double m = INFINITY, Z = 0.0, S = 0.0, tU[3] = {0.0, 0.0, 0.0}, tV[3] = {0.0, 0.0, 0.0};
   for (int t = -1; t < c.nb + 2; ++t) {
     const int tb = t - 1;
@@ -278,6 +281,14 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
         for (int off = 32; off > 0; off >>= 1) mb = fmin(mb, __shfl_xor(mb, off, 64));
         const double mn = fmin(m, mb);
         const double sc = scale2(m, mn, lam);
+        double dq = 0.0;
+        if (mn < m) {
+          const unsigned long long hit = __ballot(act && D == mb);
+          const int src = hit ? __ffsll((long long)hit) - 1 : 0;   // lowest lane holding the minimum
+          const double qn = __shfl(qi, src, 64);
+          dq = q0 - qn;
+          q0 = qn;
+        }
         const double e = act ? exp(-lam * (D - mn)) : 0.0;
         const double al = e * (qi - q0);
         double sums[8];
@@ -294,7 +305,7 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
         S = S * sc + sums[1];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          tU[d] = tU[d] * sc + sums[2 + d];
+          tU[d] = fma(dq, tV[d], tU[d]) * sc + sums[2 + d];
           tV[d] = tV[d] * sc + sums[5 + d];
         }
         m = mn;
@@ -305,6 +316,7 @@ __device__ __forceinline__ void e2_solve(const E2Item<T>& c, int lane_in) {
           r[9] = al;
           r[10] = e;
           r[11] = (b == b0) ? sc : 1.0;   // rescale once, before the sub-batch's first landmark
+          r[12] = (b == b0) ? dq : 0.0;
         }
       }
     }
@@ -353,10 +365,17 @@ __device__ __forceinline__ void e2_grad(const E2Item<T>& c, int gw, int lane_in)
         const double* r = rs + (size_t)b * kRes;
         const double sc = r[11];
         if (sc != 1.0) {
+          // The running minimum moved: rescale, and move U's reference
+          // property with it, U' = U + (q0 - q0') V (V is FP64).
+          const double dq = r[12];
 #pragma unroll
           for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int k = 0; k < APTG; ++k) { U[d][k] *= (uacc)sc; V[d][k] *= sc; }
+            for (int k = 0; k < APTG; ++k) {
+              const double v = V[d][k];
+              U[d][k] = (uacc)(fma(dq, v, (double)U[d][k]) * sc);
+              V[d][k] = v * sc;
+            }
         }
         // r = R (a - c) in the coordinate type (its rounding is independent
         // per atom and landmark); V accumulates it in FP64.

@@ -181,13 +181,19 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
       const double* rs = e3_res[(t - 1) & 1];
       const double sc = rs[11];
       if (sc != 1.0) {
-        const float scf = (float)sc;
+        // The running minimum moved: rescale, and move U's reference
+        // property with it, U' = U + (q0 - q0') V (V is FP64).
+        const double dq = rs[15];
 #pragma unroll
         for (int k = 0; k < BPW; ++k)
 #pragma unroll
           for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { U[k][d][e] *= scf; V[k][d][e] *= sc; }
+            for (int e = 0; e < 4; ++e) {
+              const double v = V[k][d][e];
+              U[k][d][e] = (float)(fma(dq, v, (double)U[k][d][e]) * sc);
+              V[k][d][e] = v * sc;
+            }
       }
       float Rt[9];
 #pragma unroll
@@ -253,7 +259,10 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
 // ------------------------------------------------------------------ solver
 __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, double* dout) {
   const Problem& P = *c.P;
-  const double lam = c.lam, q0 = c.q0;
+  const double lam = c.lam;
+  // Reference property of U = sum e (q - q0) r: the property of the running
+  // minimum's landmark (keeps U small where the weights are large).
+  double q0 = c.q0;
   const int nL = c.nL;
   const double Gxx = ldg(P.Gx32);
   double xres[3], Rx[9];
@@ -329,6 +338,11 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
       if (dout != nullptr && lane == 0) stg(dout + i, D);
       const double mn = fmin(m, D);
       const double sc = (m == INFINITY) ? 0.0 : ((mn == m) ? 1.0 : exp(-lam * (m - mn)));
+      double dq = 0.0;
+      if (mn < m) {
+        dq = q0 - qv;
+        q0 = qv;
+      }
       const double e = exp(-lam * (D - mn));
       const double al = e * (qv - q0);
       Z = Z * sc + e;
@@ -339,7 +353,7 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
         const double c3[3] = {cc[0] - (double)(float)cc[0], cc[1] - (double)(float)cc[1],
                               cc[2] - (double)(float)cc[2]};
         const double rc = R[d * 3 + 0] * c3[0] + R[d * 3 + 1] * c3[1] + R[d * 3 + 2] * c3[2];
-        tU[d] = tU[d] * sc + al * rc;
+        tU[d] = fma(dq, tV[d], tU[d]) * sc + al * rc;
         tV[d] = tV[d] * sc + e * rc;
       }
       m = mn;
@@ -352,6 +366,7 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
       v = (lane == 11) ? sc : v;
 #pragma unroll
       for (int d = 0; d < 3; ++d) v = (lane == 12 + d) ? cc[d] : v;
+      v = (lane == 15) ? dq : v;
       if (lane < 16) e3_res[t & 1][lane] = v;
     }
   }

@@ -54,6 +54,7 @@ static_assert(kW4 * kRing4 * kBF4 * 4 + kMaxBlk4 * kBF4 * 4 +
 __shared__ double e4_part[2][kMaxUnits4][10];      // unit correlation sums (row padded to 80 B)
 __shared__ double e4_res[2][kMaxUnits4][kRes4];    // per landmark lane
 __shared__ double e4_sc[2];                        // rescale factor of the step
+__shared__ double e4_dq[2];                        // shift of the reference property q0 in the step
 __shared__ double e4_misc[16];                     // item totals
 
 static_assert(kMaxUnits4 * kBF4 * 8 <= kW4 * kRing4 * kBF4 * 4, "unit sums (FP64) fit in the copy rings");
@@ -214,13 +215,19 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
       const int limp = min(K, nL - tp * K) * nblk;
       const double sc = e4_sc[tp & 1];
       if (sc != 1.0) {
-        const float scf = (float)sc;
+        // The running minimum moved: rescale, and move U's reference
+        // property with it, U' = U + (q0 - q0') V (V is FP64).
+        const double dq = e4_dq[tp & 1];
 #pragma unroll
         for (int s = 0; s < SPW; ++s)
 #pragma unroll
           for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { U[s][d][e] *= scf; V[s][d][e] *= sc; }
+            for (int e = 0; e < 4; ++e) {
+              const double v = V[s][d][e];
+              U[s][d][e] = (float)(fma(dq, v, (double)U[s][d][e]) * sc);
+              V[s][d][e] = v * sc;
+            }
       }
 #pragma unroll
       for (int s = 0; s < SPW; ++s) {
@@ -369,7 +376,11 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
 // ------------------------------------------------------------------ solver
 __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, double* dout) {
   const Problem& P = *c.P;
-  const double lam = c.lam, q0 = c.q0;
+  const double lam = c.lam;
+  // Reference property of U = sum e (q - q0) r: the property of the running
+  // minimum's landmark, so that U stays small where the weights are large
+  // and the merge's U + (q0 - s) V does not cancel.
+  double q0 = c.q0;
   const int nL = c.nL, K = c.K, nblk = c.nblk;
   const int T = (nL + K - 1) / K;
   bar_lds();   // structure copy staged by the workers
@@ -458,6 +469,14 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
       const double mb = fmin(fmin(__shfl(rm, 0, 64), __shfl(rm, 16, 64)), fmin(__shfl(rm, 32, 64), __shfl(rm, 48, 64)));
       const double mn = fmin(m, mb);
       const double sc = (m == INFINITY) ? 0.0 : ((mn == m) ? 1.0 : exp(-lam * (m - mn)));
+      double dq = 0.0;
+      if (mn < m) {
+        const unsigned long long hit = __ballot(act && D == mb);
+        const int src = hit ? __ffsll((long long)hit) - 1 : 0;   // lowest lane holding the minimum
+        const double qn = __shfl(qv, src, 64);
+        dq = q0 - qn;
+        q0 = qn;
+      }
       const double e = act ? exp(-lam * (D - mn)) : 0.0;
       const double al = e * (qv - q0);
       Z = Z * sc + e;
@@ -468,7 +487,7 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const double rc = R[d * 3 + 0] * c3[0] + R[d * 3 + 1] * c3[1] + R[d * 3 + 2] * c3[2];
-        tU[d] = tU[d] * sc + al * rc;
+        tU[d] = fma(dq, tV[d], tU[d]) * sc + al * rc;
         tV[d] = tV[d] * sc + e * rc;
       }
       m = mn;
@@ -481,10 +500,14 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
 #pragma unroll
         for (int d = 0; d < 3; ++d) r[12 + d] = cc[d];
       }
-      if (lane == 0) e4_sc[t & 1] = sc;
+      if (lane == 0) {
+        e4_sc[t & 1] = sc;
+        e4_dq[t & 1] = dq;
+      }
     }
   }
-  // Item totals: the per-lane sums added over the wave in a fixed order.
+  // Item totals: the per-lane sums added over the wave in a fixed order; the
+  // header carries the final reference property.
   Z = wave_sum_to63(Z);
   S = wave_sum_to63(S);
 #pragma unroll

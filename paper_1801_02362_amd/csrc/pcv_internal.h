@@ -181,6 +181,30 @@ hipError_t launch_engine4(int spw, int grid, const Problem* probs, const Item* i
 int engine4_lanes(int n_pad, int spw);
 
 
+// Neighbour list: the full landmark set's stored data and the compact list
+// set the members are gathered into.
+struct NlGather {
+  const int* members;   // [M] indices into the full set
+  int M, n_pad;
+  const void* A;        // [L][3][n_pad] coordinate type
+  const double* ca;     // [L][3]
+  const double* Ga;     // [L]
+  const double* q;      // [L]
+  const double* Rsave;  // [L][9]
+  void* A_nl;           // [M][3][n_pad]
+  double* ca_nl;        // [M][3]
+  double* Ga_nl;        // [M]
+  double* q_nl;         // [M]
+  double* Rsave_nl;     // [M][9]
+};
+// The M smallest of D[0..N) (nearest first, ties to the lower index) into
+// members; N <= nl_select_max().
+hipError_t launch_nl_select(const double* D, int N, int M, int* members, hipStream_t st);
+int nl_select_max();
+// Gather the members' rows; skipped unless flag is null or *flag == run_if.
+template <typename T>
+hipError_t launch_nl_gather(const NlGather& g, const int* flag, int run_if, hipStream_t st);
+
 bool engine_supported(EngineCfg cfg, bool fp64);
 void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu
 hipError_t engine_init_attributes();

@@ -249,3 +249,18 @@ def test_argument_errors(torch):
     assert ei.value.status == -1
     with pytest.raises(pcv.PcvError):
         pcv.PathCV(dev(sysm.landmarks, torch.float64), 1.0, w=-np.ones(22))
+
+
+@pytest.mark.parametrize("plan", [None, dict(engine=3, wg=512, apt=4, team=0, aptg=0, batch=0),
+                                  dict(engine=2, wg=512, apt=4, team=16, aptg=2, batch=64),
+                                  dict(engine=1, wg=256, apt=1, team=64)])
+def test_structure_on_a_landmark(torch, plan):
+    """A structure equal to a landmark (D = 0 for it, large lambda): the
+    partials' reference property follows the running minimum, so the merge's
+    U + (q0 - s) V does not cancel (this case once lost a factor of 20)."""
+    from gpu_util import TOL32
+    sp = wl.small_path(40, 60, 5, dtype=np.float32)
+    lam = landmark_lambda(sp.landmarks)
+    frames = np.stack([sp.landmarks[2], sp.landmarks[41]])
+    _run_exact(torch, sp.landmarks, frames, lam, dtype=torch.float32, tol=TOL32,
+               name=f"on_landmark_{plan['engine'] if plan else 'default'}", plan=plan)
