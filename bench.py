@@ -15,7 +15,8 @@ duration from HIP events recorded on its own stream) and ``cpu_baseline``
 Other workloads: ``--workload close`` (300 atoms x 500 landmarks, Algorithm 2
 along a random walk, steps/s), ``--workload batch`` (64 uneven walkers in one
 persistent launch), ``--workload mtd`` (close-structure CVs plus the Eq. 1
-grid bias and its atom gradient every step), ``--workload surrogate`` (train the MLP surrogate on
+grid bias and its atom gradient every step), ``--workload nl`` (neighbour
+lists, 304 atoms x 2120 references, with and without the close structure), ``--workload surrogate`` (train the MLP surrogate on
 exact-labelled walks, then compare exact, close-structure and surrogate
 steps/s and |ds| on the test walk) and ``--workload copy`` (a plain device
 copy used to calibrate the traffic counters).
@@ -262,6 +263,72 @@ def bench_mtd(args):
     return out
 
 
+def bench_nl(args):
+    """Neighbour lists (Section 2) with the paper's second system's sizes:
+    304 atoms, 2120 references, 50 members refreshed every 50 steps, on a
+    walk that slides along the path.  Four runs over the same frames: exact
+    without and with the list, close structure (eps 0.01 nm^2) without and
+    with the list; steps/s, expensive MSDs per step (device counters) next to
+    Section 6.2's averages, and |ds| against the exact run without a list."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    M, stride, eps = 50, 50, 0.01
+    sysm, frames = wl.nl_path(args.warmup + args.steps)
+    N = sysm.n_landmarks
+    dev = torch.device("cuda", 0)
+    lm = torch.as_tensor(sysm.landmarks, device=dev)
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])
+    lam = None
+    runs = {}
+    s_ref = None
+    for name, close, nl in (("exact", False, False), ("exact+nl", False, True),
+                            ("close", True, False), ("close+nl", True, True)):
+        cv = pcv.PathCV(lm, lam, eps=eps)
+        lam = cv.lam
+        if nl:
+            cv.set_neighbour_list(M, stride)
+        step = cv.eval_close if close else cv.eval
+        x.copy_(x_all[0])
+        o = step(x)
+        s_hist = torch.empty(args.steps, dtype=torch.float64, device=dev)
+        for t in range(1, args.warmup):
+            x.copy_(x_all[t])
+            step(x, out=o)
+        cv.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(args.steps):
+            x.copy_(x_all[args.warmup + t])
+            step(x, out=o)
+            s_hist[t:t + 1].copy_(o["sz"][0:1])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = cv.stats()
+        s_np = s_hist.cpu().numpy()
+        if s_ref is None:
+            s_ref = s_np
+        ds = np.abs(s_np - s_ref)
+        runs[name] = {"steps_per_s": round(args.steps / dt, 1), "ms_per_step": round(dt / args.steps * 1e3, 4),
+                      "expensive_msd_per_step": round(st["expensive_msd"] / args.steps, 3),
+                      "recomputes": st["recomputes"], "max_abs_ds": float(ds.max()), "mean_abs_ds": float(ds.mean())}
+        cv.close()
+        log(f"[bench] nl {name}: {runs[name]}")
+    K = args.steps / max(1, runs["close"]["recomputes"])
+    out = {"metric": "neighbour-list steps/s", "value": runs["close+nl"]["steps_per_s"], "unit": "steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": runs["close+nl"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 coords, f64 correlation/eigen/lse", "data": "synthetic",
+           "config": {"workload": f"{sysm.n_atoms} atoms x {N} references, list of {M} every {stride} steps, "
+                                  f"close structure eps {eps} nm^2, walk sliding along the path",
+                      "runs": runs,
+                      "section_6_2_expensive_per_step": {"original_with_list": M + (N - M) / stride,
+                                                         "close": 1 + N / K}}}
+    return out
+
+
 def bench_batch(args):
     import numpy as np
     import torch
@@ -463,7 +530,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate", "mtd"], default="exact")
+    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate", "mtd", "nl"],
+                    default="exact")
     ap.add_argument("--hill-stride", type=int, default=50)
     ap.add_argument("--train-walks", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -494,6 +562,8 @@ def main():
         out = bench_surrogate(args)
     elif args.workload == "mtd":
         out = bench_mtd(args)
+    elif args.workload == "nl":
+        out = bench_nl(args)
     else:
         out = bench_batch(args)
     print(json.dumps(out), flush=True)

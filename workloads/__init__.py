@@ -30,12 +30,12 @@ import numpy as np
 from scipy.spatial.transform import Rotation
 
 ROOT_SEED = 20180107
-N_CONFIGS = 5
+N_CONFIGS = 6
 
 __all__ = [
     "ROOT_SEED", "PathSystem", "Walker", "config_rng", "path_system",
     "random_walk", "cfg0", "cfg1", "cfg2", "cfg2_frames", "cfg3",
-    "cfg4_training_walks", "small_path", "rigid_copy", "mlp_sizes", "mlp_init", "mlp_unflatten",
+    "cfg4_training_walks", "nl_path", "small_path", "rigid_copy", "mlp_sizes", "mlp_init", "mlp_unflatten",
     "minibatch_order",
 ]
 
@@ -164,6 +164,29 @@ def cfg3(n_walkers: int = 64, n_frames: int = 4, *, atom_range=(50, 2000),
         fr = random_walk(s.waypoints[0], n_frames, rng=sub)
         out.append(Walker(s, fr))
     return out
+
+
+def nl_path(n_frames: int = 3000, *, steps_per_segment: int = 4000) -> tuple[PathSystem, np.ndarray]:
+    """Neighbour-list workload with the sizes of the paper's second system
+    (304 atoms, 2120 references; a 50-member list refreshed every 50 steps):
+    references through 8 waypoints (as ``path_system``), and a walk that
+    slides along the path (one waypoint segment per ``steps_per_segment``
+    frames, starting at waypoint 0) with mean-reverting thermal noise
+    (x_noise <- 0.99 x_noise + N(0, 0.005) per coordinate and frame, about
+    0.035 nm stationary), so the nearest references change over the walk."""
+    sysm = path_system(304, 2120, 8, rng=config_rng(5, 0), dtype=np.float32, name="nl_path")
+    rng = config_rng(5, 1)
+    way = sysm.waypoints
+    frames = np.empty((n_frames, 304, 3), dtype=np.float32)
+    noise = np.zeros((304, 3))
+    for t in range(n_frames):
+        if t:
+            noise = 0.99 * noise + rng.normal(0.0, 0.005, size=noise.shape)
+        u = min(t / steps_per_segment, way.shape[0] - 1.0)
+        k = min(int(u), way.shape[0] - 2)
+        f = u - k
+        frames[t] = ((1.0 - f) * way[k] + f * way[k + 1] + noise).astype(np.float32)
+    return sysm, frames
 
 
 def cfg4_training_walks(n_walks: int = 1000, steps: int = 1000,
