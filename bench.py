@@ -460,6 +460,35 @@ def bench_surrogate(args):
         return {"max": float(d.max()), "p99": float(np.quantile(d, 0.99)), "mean": float(d.mean()),
                 "frac_le_1e-3": float((d <= 1e-3).mean())}
 
+    # Drift-threshold sweep: the fallback (and the close structure) at
+    # smaller eps trade speed for accuracy; the operating point is the
+    # largest eps whose max abs(ds) on the test walk is <= 1e-3.
+    sweep = []
+    for eps in args.eps_sweep:
+        h1, h2 = pcv.PathCV(lm, lam, eps=eps), pcv.PathCV(lm, lam, eps=eps)
+        sps = timed(lambda v: sur.step(h1, v, out=so), K)
+        sur.reset_stats()
+        e_s = err(recorded(lambda v: sur.step(h2, v, out=so), K))
+        frac = sur.stats()["surrogate_steps"] / K
+        c1, c2 = pcv.PathCV(lm, lam, eps=eps), pcv.PathCV(lm, lam, eps=eps)
+        sps_c = timed(lambda v: c1.eval_close(v), K)
+        e_c = err(recorded(lambda v: c2.eval_close(v), K))
+        for h in (h1, h2, c1, c2):
+            h.close()
+        sweep.append({"eps": eps, "surrogate_steps_per_s": round(sps, 1), "surrogate_fraction": round(frac, 4),
+                      "surrogate_max_abs_ds": e_s["max"], "surrogate_mean_abs_ds": e_s["mean"],
+                      "close_steps_per_s": round(sps_c, 1), "close_max_abs_ds": e_c["max"],
+                      "close_mean_abs_ds": e_c["mean"]})
+        log(f"[surrogate] sweep {sweep[-1]}")
+
+    def operating_point(kind):
+        ok = [r for r in sweep if r[f"{kind}_max_abs_ds"] <= 1e-3]
+        if not ok:
+            return None
+        best = max(ok, key=lambda r: r["eps"])
+        return {"eps": best["eps"], "steps_per_s": best[f"{kind}_steps_per_s"],
+                "max_abs_ds": best[f"{kind}_max_abs_ds"]}
+
     # batched inference: many structures at once (frames of the test walk)
     B = min(args.batch, K)
     xb = walk_dev[:B].contiguous()
@@ -493,6 +522,9 @@ def bench_surrogate(args):
                       "surrogate_fraction": round(st_sur["surrogate_steps"] / max(1, st_sur["steps"]), 4),
                       "ds_surrogate_vs_exact": e_sur, "ds_close_vs_exact": e_close,
                       "meets_ds_1e-3": bool(e_sur["max"] <= 1e-3),
+                      "eps_sweep": sweep,
+                      "at_ds_1e-3": {"surrogate": operating_point("surrogate"), "close": operating_point("close"),
+                                     "exact_steps_per_s": round(sps_exact, 1)},
                       "close_recomputes": st_close["recomputes"], "judge": st_sur,
                       "batched": {"frames": B, "surrogate_frames_per_s": round(sur_batched, 1),
                                   "exact_frames_per_s": round(exact_batched, 1)},
@@ -541,6 +573,7 @@ def main():
     ap.add_argument("--hidden", type=int, default=512)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eps", type=float, default=0.01)
+    ap.add_argument("--eps-sweep", type=float, nargs="*", default=[0.01, 0.003, 0.001, 3e-4, 1e-4, 3e-5, 1e-5])
     ap.add_argument("--copy-mb", type=float, default=600.0)
     ap.add_argument("--atoms", type=int, default=5000)
     ap.add_argument("--landmarks", type=int, default=10000)

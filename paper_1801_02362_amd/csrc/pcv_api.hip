@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,7 +42,12 @@ struct Plan {
 }  // namespace
 
 // ============================================================ single handle
+// Serial numbers of handles: with the plan version they name the handle's
+// current device buffers (a host address can be reused after destruction).
+static std::atomic<unsigned long long> g_handle_serial{0};
+
 struct pcv_handle {
+  unsigned long long serial = 0;
   pcv_options opt{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -155,6 +161,7 @@ extern "C" pcv_status pcv_create(pcv_handle** out, const pcv_options* opt) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) return PCV_EHIP;
   if (hipSetDevice(o.device) != hipSuccess) return PCV_EHIP;
   pcv_handle* h = new pcv_handle();
+  h->serial = ++g_handle_serial;
   h->opt = o;
   h->fp64 = (o.precision == PCV_FP64);
   h->stream = (hipStream_t)o.stream;
@@ -794,6 +801,12 @@ extern "C" pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int ca
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   HIP_TRY(h, hipMemcpy(members, h->nl_members, (size_t)h->nl_M * sizeof(int), hipMemcpyDeviceToHost));
   return PCV_OK;
+}
+
+// Token naming a handle and its current buffers (for callers that cache
+// hipGraphs capturing the handle's kernels).
+extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h) {
+  return (h->serial << 32) ^ (unsigned long long)(unsigned)h->plan_version;
 }
 
 // Exact half of the surrogate's fallback step: the close-structure drift test

@@ -897,11 +897,15 @@ extern "C" pcv_status pcv_mlp_eval(pcv_mlp* m, const float* x, int B, double* sz
 // ---- fallback step (uses the exact handle's close-structure drift test)
 extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
                                                        double* sz, void* ds, void* dz, const int** flag);
+extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h);
 
 extern "C" pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, double* sz, float* ds_dx,
                                    float* dz_dx, int* used_surrogate) {
   if (!m || !h || !x || !sz) return PCV_EINVAL;
-  const void* key[8] = {x, sz, ds_dx, dz_dx, used_surrogate, h, nullptr, (const void*)2};
+  // The exact handle enters the key by its token, not its address: a graph
+  // captured with a destroyed handle's buffers must never be replayed.
+  const void* key[8] = {x, sz, ds_dx, dz_dx, used_surrogate, h,
+                        (const void*)(uintptr_t)pcv_internal_handle_token(h), (const void*)2};
   return mlp_run_graph(m, key, [&](hipStream_t st) -> hipError_t {
     const int* flag = nullptr;
     MTRY(pcv_internal_exact_for_surrogate(h, m->n, st, x, sz, ds_dx, dz_dx, &flag));

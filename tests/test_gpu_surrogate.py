@@ -236,3 +236,44 @@ def test_full_size_network_single_structure(torch):
     assert abs(host(many["sz"])[0, 0] - host(one["sz"])[0, 0]) <= 2e-3 * net.std[0]
     assert np.abs(host(many["ds_dx"])[0] - host(one["ds_dx"])[0]).max() <= 1e-2 * np.abs(rgs).max()
     sur.close()
+
+
+def test_fallback_step_with_replaced_exact_handles(torch):
+    """Exact handles destroyed and recreated between fallback steps (their
+    host addresses may repeat) while the surrogate replays cached graphs:
+    every step must use the live handle's buffers.  Each run starts with an
+    exact step (a new handle has no close structure), which resets the
+    anchor, so every run equals the same run on a fresh surrogate."""
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev, host
+    n, hidden = 20, 64
+    s, ref, _, net, params, _ = _setup(n=n, hidden=hidden, seed=21)
+    lam = landmark_lambda(s.landmarks)
+    lm = dev(s.landmarks, torch.float32)
+    walk = wl.random_walk(s.waypoints[0].astype(np.float32), 12, rng=np.random.default_rng(22))
+    x = torch.empty(n, 3, dtype=torch.float32, device="cuda")
+
+    def surrogate():
+        m = pcv.Surrogate(ref, hidden=hidden, max_batch=64, use_graph=True)
+        m.set_params(params)
+        m.set_scaling(net.mean, net.std)
+        return m
+
+    def run(m, eps):
+        h = pcv.PathCV(lm, lam, eps=eps)
+        out = []
+        for f in walk:
+            x.copy_(torch.as_tensor(f))
+            o = m.step(h, x)
+            out.append(np.concatenate([host(o["sz"]), host(o["ds_dx"]).ravel()]))
+        h.close()
+        return np.array(out)
+
+    shared = surrogate()
+    for eps in (0.002, 0.001, 0.002, 0.0005):
+        got = run(shared, eps)
+        fresh = surrogate()
+        want = run(fresh, eps)
+        fresh.close()
+        assert np.array_equal(got, want), eps
+    shared.close()
