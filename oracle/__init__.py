@@ -18,6 +18,8 @@ implementation written from the paper (arXiv:1801.02362):
   a grid with bicubic Hermite interpolation, and its gradient on the atoms.
 * ``oracle.nl``    -- O7: neighbour lists (Section 2) with Algorithm 1 and
   with the close structure (selection by Eq. 5 at list updates, Section 3.2).
+* ``oracle.props`` -- O8: property maps with several properties per
+  reference (Eq. 2 with a vector q_i).
 
 Everything is FP64 NumPy on FP64 copies of the caller's (possibly FP32)
 inputs.  The oracle shares no code, header, table or constant with the HIP

@@ -203,3 +203,21 @@ def test_nl_stale_list_is_caught(monkeypatch):
     monkeypatch.setattr(onl, "nearest", wrapped)
     with pytest.raises(AssertionError):
         tn.test_members_are_the_brute_force_nearest_of_the_update_frame()
+
+
+# --- property maps (oracle/props.py)
+import oracle.props as opr
+import test_oracle_props as tpr
+
+
+def test_props_gradient_sign_is_caught(monkeypatch):
+    orig = opr.path_cv
+
+    def bad(*a, **k):
+        r = orig(*a, **k)
+        r.ds_dx = -r.ds_dx
+        return r
+
+    monkeypatch.setattr(opr, "path_cv", bad)
+    with pytest.raises(AssertionError):
+        tpr.test_gradients_match_finite_differences()
