@@ -176,6 +176,22 @@ pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride);
  * stream. */
 pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int capacity, int* count);
 
+/*
+ * Property maps with several properties per reference (Eq. 2 with a vector
+ * q_i; Section 2): S_k = sum_i q_ik e^{-lambda D_i} / sum_i e^{-lambda D_i}
+ * and dS_k/dx for k < P, from the exact distances (Algorithm 1, every
+ * reference, whether or not a neighbour list is set).
+ *   q      device double [L][P], row i = properties of landmark i
+ *   S      device double [P]
+ *   dS_dx  device [P][n][3] in the coordinate type, or NULL
+ *   P      1..8
+ * Counts as one exact evaluation (expensive_msd += L).  The first call
+ * allocates L P + (chunks P 3 n_pad) doubles of scratch (kept until the next
+ * landmark load); later calls allocate nothing.  Two passes over the
+ * landmarks: the exact pass (rotations kept) and the gradient pass.
+ */
+pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, const double* q, double* S, void* dS_dx);
+
 /* Counters (synchronises the stream). */
 pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out);
 pcv_status pcv_reset_stats(pcv_handle* h);

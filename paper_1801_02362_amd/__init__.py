@@ -117,6 +117,7 @@ def load_library():
         "pcv_mlp_reset_stats": (st, [vp]),
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
         "pcv_set_neighbour_list": (st, [vp, i, i]),
+        "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
         "pcv_get_neighbour_list": (st, [vp, vp, i, ctypes.POINTER(i)]),
         "pcv_bias_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_BiasOptions)]),
         "pcv_bias_destroy": (st, [vp]),
@@ -257,6 +258,25 @@ class PathCV:
 
     def force_reassign(self):
         self._check(self._L.pcv_force_reassign(self._h))
+
+    def eval_properties(self, x, q, *, grad: bool = True, out: dict | None = None) -> dict:
+        """Property-map components S [P] and gradients [P][n][3] for the
+        device properties ``q`` (float64 [L][P], P <= 8); see
+        ``pcv_eval_properties``."""
+        import torch
+        self._check_x(x)
+        if not (q.is_cuda and q.dtype == torch.float64 and q.dim() == 2 and q.shape[0] == self.n_landmarks
+                and q.is_contiguous()):
+            raise ValueError("q must be a contiguous CUDA float64 tensor [L][P]")
+        P = int(q.shape[1])
+        o = out or {}
+        S = o.get("S") if o.get("S") is not None else torch.empty(P, dtype=torch.float64, device=x.device)
+        dS = None
+        if grad:
+            dS = o.get("dS_dx") if o.get("dS_dx") is not None else torch.empty(P, x.shape[0], 3, dtype=x.dtype,
+                                                                                device=x.device)
+        self._check(self._L.pcv_eval_properties(self._h, _ptr(x), P, _ptr(q), _ptr(S), _ptr(dS)))
+        return {"S": S, "dS_dx": dS}
 
     def set_neighbour_list(self, M: int, stride: int = 1):
         """Neighbour list of the ``M`` nearest references refreshed every

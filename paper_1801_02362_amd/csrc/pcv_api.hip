@@ -85,6 +85,9 @@ struct pcv_handle {
   int plan_version = 0;
   // neighbour list (Section 2): members, their compact landmark set and its
   // work items (the engine configuration is the full set's)
+  // property maps: rotations and distances of their exact pass, scratch
+  double *Rprop = nullptr, *Dprop = nullptr, *Wprop = nullptr, *part_prop = nullptr;
+  DevMem propmem;
   int nl_M = 0, nl_stride = 0;
   long long nl_step = 0;
   DevMem nlmem, nlpmem;
@@ -185,6 +188,7 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   collect_timing(h);
   drop_graphs(h);
+  h->propmem.release();
   h->nlpmem.release();
   h->nlmem.release();
   h->pmem.release();
@@ -222,7 +226,7 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, n_slots * 4 * sizeof(double)));
   HIP_TRY(h, h->pmem.alloc(&h->vec, n_slots * (h->fp64 ? partial_bytes<double>(h->n_pad)
                                                        : partial_bytes<float>(h->n_pad))));
-  HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 3 * sizeof(Problem)));
+  HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 4 * sizeof(Problem)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prep, sizeof(PrepArgs)));
@@ -269,7 +273,10 @@ static pcv_status build_plan(pcv_handle* h) {
   base.lam = h->lam;
   base.xw32 = h->xw32;
   base.n_x = h->n_x;
-  Problem probs[3] = {base, base, base};
+  // Entry 3: the property maps' exact pass (rotations saved to their own buffer).
+  Problem props_prob = base;
+  props_prob.Rsave = h->Rprop;
+  Problem probs[4] = {base, base, base, props_prob};
   HIP_TRY(h, hipMemcpy(h->d_prob, probs, sizeof(probs), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_wgoff, wgoff.data(), wgoff.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -444,6 +451,8 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   h->nl_M = 0;
   h->nl_stride = 0;
   h->nl_step = 0;
+  h->propmem.release();
+  h->Wprop = h->part_prop = nullptr;
   h->pmem.release();
   h->mem.release();
   h->n = n_atoms;
@@ -477,6 +486,8 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->Rxy, 9 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Dxy, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Rsave, L * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rprop, L * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Dprop, L * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->gtmp, 12 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->scratch_sz, 2 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->flag, sizeof(int)));
@@ -540,7 +551,7 @@ extern "C" pcv_status pcv_path_lambda(pcv_handle* h, double factor, double* lamb
 // Engine launch bracketed by events when kernel timing is on.
 template <typename T>
 static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd,
-                               bool nl = false) {
+                               bool nl = false, int prob_slot = -1) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     (void)hipEventCreate(&e0);
@@ -548,7 +559,7 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
     (void)hipEventRecord(e0, st);
   }
   const Plan& p = h->plan;
-  const Problem* probs = (nl ? h->d_prob_nl : h->d_prob) + mode;
+  const Problem* probs = (nl ? h->d_prob_nl : h->d_prob) + (prob_slot >= 0 ? prob_slot : mode);
   const Item* items = nl ? h->d_items_nl : h->d_items;
   const int* wgoff = nl ? h->d_wgoff_nl : h->d_wgoff;
   const int grid = nl ? h->grid_nl : p.grid;
@@ -752,6 +763,38 @@ static pcv_status eval_close_impl(pcv_handle* h, const void* x, double* sz, void
 extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx,
                                      double* msd, int* recomputed) {
   return eval_close_impl(h, x, sz, ds_dx, dz_dx, msd, recomputed, true);
+}
+
+// Property maps: the exact pass with rotations and distances saved, then the
+// shared weights, every component and all P gradients (pcv_props.hip).
+template <typename T>
+static hipError_t enqueue_props(pcv_handle* h, hipStream_t st, const void* x, int P, const double* q, double* S,
+                                void* dS) {
+  hipError_t e = launch_prep<T>(h->d_prep, x, 1, st);
+  if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
+  if (e != hipSuccess) return e;
+  PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+  return launch_props<T>(a, q, h->lam, S, h->Wprop, h->part_prop, dS, st);
+}
+
+extern "C" pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, const double* q, double* S,
+                                          void* dS_dx) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (!x || !q || !S) return fail(h, PCV_EINVAL, "x, q and S are required");
+  if (P < 1 || P > kPropsMax) return fail(h, PCV_EINVAL, "need 1 <= P <= " + std::to_string(kPropsMax));
+  if (!h->Wprop) {
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const size_t chunks = props_chunks(h->n_pad, h->L);
+    HIP_TRY(h, h->propmem.alloc((void**)&h->Wprop, (size_t)h->L * kPropsMax * sizeof(double)));
+    HIP_TRY(h, h->propmem.alloc((void**)&h->part_prop, chunks * kPropsMax * 3 * (size_t)h->n_pad * sizeof(double)));
+  }
+  const void* key[7] = {x, q, S, dS_dx, (const void*)(uintptr_t)P, nullptr, (const void*)7};
+  return run_maybe_graph(h, key, [&](hipStream_t st) {
+    return h->fp64 ? enqueue_props<double>(h, st, x, P, q, S, dS_dx)
+                   : enqueue_props<float>(h, st, x, P, q, S, dS_dx);
+  });
 }
 
 extern "C" pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride) {

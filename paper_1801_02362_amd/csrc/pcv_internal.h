@@ -205,6 +205,24 @@ int nl_select_max();
 template <typename T>
 hipError_t launch_nl_gather(const NlGather& g, const int* flag, int run_if, hipStream_t st);
 
+// Property maps (several properties per reference): the exact pass's
+// distances D and rotations R, the landmark set and the properties.
+constexpr int kPropsMax = 8;
+struct PropsArgs {
+  const void* A;        // [L][3][n_pad] coordinate type
+  const double* ca;     // [L][3]
+  const double* R;      // [L][9] rotations of the exact pass
+  const double* D;      // [L] distances of the exact pass
+  const double* w;      // [n_pad] normalised weights
+  int L, n, n_pad, P;
+};
+// Landmark chunks of the gradient pass (its partials: chunks x P x 3 x n_pad doubles).
+int props_chunks(int n_pad, int L);
+// S [P] (device), W [L][P] scratch, part scratch, dS [P][n][3] or null.
+template <typename T>
+hipError_t launch_props(const PropsArgs& a, const double* q, double lam, double* S, double* W, double* part,
+                        void* dS, hipStream_t st);
+
 bool engine_supported(EngineCfg cfg, bool fp64);
 void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu
 hipError_t engine_init_attributes();
