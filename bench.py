@@ -16,7 +16,9 @@ Other workloads: ``--workload close`` (300 atoms x 500 landmarks, Algorithm 2
 along a random walk, steps/s), ``--workload batch`` (64 uneven walkers in one
 persistent launch), ``--workload mtd`` (close-structure CVs plus the Eq. 1
 grid bias and its atom gradient every step), ``--workload nl`` (neighbour
-lists, 304 atoms x 2120 references, with and without the close structure), ``--workload surrogate`` (train the MLP surrogate on
+lists, 304 atoms x 2120 references, with and without the close structure),
+``--workload props`` (8 properties per reference with gradients), ``--workload f2``
+(separate displacement and alignment weights), ``--workload surrogate`` (train the MLP surrogate on
 exact-labelled walks, then compare exact, close-structure and surrogate
 steps/s and |ds| on the test walk) and ``--workload copy`` (a plain device
 copy used to calibrate the traffic counters).
@@ -329,6 +331,81 @@ def bench_nl(args):
     return out
 
 
+def _steps_per_s(args, x_all, x, fn):
+    """Warm up, then time ``args.steps`` calls of ``fn(x, out)`` on successive
+    frames (frame copy included, as a simulation would hand them over)."""
+    import torch
+    x.copy_(x_all[0])
+    o = fn(x, None)
+    for t in range(1, args.warmup):
+        x.copy_(x_all[t])
+        fn(x, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        x.copy_(x_all[args.warmup + t])
+        fn(x, o)
+    torch.cuda.synchronize()
+    return args.steps / (time.perf_counter() - t0)
+
+
+def bench_f2(args):
+    """Separate displacement and alignment weights on the 300-atom,
+    500-landmark path: s, z and both gradients per step through the
+    three-pass path, against the same handle with w = w' (the engine)."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(11)
+    wa = rng.uniform(0.5, 1.5, sysm.n_atoms)
+    wd = rng.uniform(0.0, 2.0, sysm.n_atoms)
+    cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, w=wa)
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])
+    sps_same = _steps_per_s(args, x_all, x, lambda v, o: cv.eval(v, out=o))
+    cv.set_displacement_weights(wd)
+    sps_f2 = _steps_per_s(args, x_all, x, lambda v, o: cv.eval(v, out=o))
+    cv.close()
+    return {"metric": "separate-weights exact steps/s", "value": round(sps_f2, 1), "unit": "steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 / sps_f2, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 coords, f64 accumulation", "data": "synthetic",
+            "config": {"workload": "300 atoms x 500 landmarks, displacement weights != alignment weights",
+                       "equal_weights_engine_steps_per_s": round(sps_same, 1)}}
+
+
+def bench_props(args):
+    """Property maps on the 300-atom, 500-landmark path: P = 8 properties per
+    reference (the first is the landmark index, i.e. s) and all their
+    gradients per step, against the plain exact evaluation of s and z."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    P = 8
+    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    dev = torch.device("cuda", 0)
+    cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None)
+    L = sysm.n_landmarks
+    Q = np.random.default_rng(7).normal(size=(L, P))
+    Q[:, 0] = np.arange(1, L + 1)
+    q = torch.as_tensor(Q, device=dev)
+    x_all = torch.as_tensor(frames, device=dev)
+    x = torch.empty_like(x_all[0])
+    sps_props = _steps_per_s(args, x_all, x, lambda v, o: cv.eval_properties(v, q, out=o))
+    sps_exact = _steps_per_s(args, x_all, x, lambda v, o: cv.eval(v, out=o))
+    cv.close()
+    return {"metric": "property-map steps/s", "value": round(sps_props, 1), "unit": "steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 / sps_props, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 coords, f64 correlation/eigen/lse/property gradients", "data": "synthetic",
+            "config": {"workload": f"300 atoms x 500 landmarks, {P} properties per reference with gradients",
+                       "exact_s_z_steps_per_s": round(sps_exact, 1)}}
+
+
 def bench_batch(args):
     import numpy as np
     import torch
@@ -562,8 +639,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["exact", "close", "batch", "copy", "surrogate", "mtd", "nl"],
-                    default="exact")
+    ap.add_argument("--workload", default="exact",
+                    choices=["exact", "close", "batch", "copy", "surrogate", "mtd", "nl", "props", "f2"])
     ap.add_argument("--hill-stride", type=int, default=50)
     ap.add_argument("--train-walks", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -597,6 +674,10 @@ def main():
         out = bench_mtd(args)
     elif args.workload == "nl":
         out = bench_nl(args)
+    elif args.workload == "props":
+        out = bench_props(args)
+    elif args.workload == "f2":
+        out = bench_f2(args)
     else:
         out = bench_batch(args)
     print(json.dumps(out), flush=True)

@@ -192,6 +192,24 @@ pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int capacity, int
  */
 pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, const double* q, double* S, void* dS_dx);
 
+/*
+ * Separate displacement weights w (Section 3.1, Eq. 4 with w != w'): the
+ * weights given to pcv_load_landmarks stay the alignment weights w' (centre
+ * of mass and rotation); w_disp sets the per-atom weights of the distance,
+ *   D_i = sum_j w_j |x_c,j - R_i a_c,ij|^2   (R_i, centres by w'),
+ * and its gradient then keeps the centre-of-mass and rotation terms of Eq. 4.
+ *   w_disp  host [n] finite, >= 0, positive sum (normalised to sum to one),
+ *           copied; NULL switches the separate weights off (D by w' again)
+ * While set, pcv_eval takes a three-pass FP64-accumulating path (outputs and
+ * graph reuse as before; msd receives these D_i), and pcv_eval_close,
+ * pcv_update_close, pcv_eval_properties, pcv_set_neighbour_list and the
+ * surrogate's fallback step return PCV_EUNSUPPORTED (pcv_set_displacement_weights
+ * itself refuses while a neighbour list is on).  Allocates about
+ * L (31 doubles) + 3 n_pad + chunks 12 n_pad doubles (chunks <= 64) and
+ * synchronises the stream; loading landmarks switches it off.
+ */
+pcv_status pcv_set_displacement_weights(pcv_handle* h, const double* w_disp);
+
 /* Counters (synchronises the stream). */
 pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out);
 pcv_status pcv_reset_stats(pcv_handle* h);

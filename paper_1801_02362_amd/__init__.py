@@ -118,6 +118,7 @@ def load_library():
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
         "pcv_set_neighbour_list": (st, [vp, i, i]),
         "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
+        "pcv_set_displacement_weights": (st, [vp, vp]),
         "pcv_get_neighbour_list": (st, [vp, vp, i, ctypes.POINTER(i)]),
         "pcv_bias_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_BiasOptions)]),
         "pcv_bias_destroy": (st, [vp]),
@@ -189,11 +190,12 @@ class PathCV:
         self._check(L.pcv_create(ctypes.byref(h), ctypes.byref(opt)), None)
         self._h = h
         lm = landmarks.contiguous()
-        _, qp = _as_host_f64(q, self.n_landmarks, "q")
+        qa, qp = _as_host_f64(q, self.n_landmarks, "q")   # qa, wa keep the buffers alive for the call
         self._q_keep = q
-        _, wp = _as_host_f64(w, self.n_atoms, "w")
+        wa, wp = _as_host_f64(w, self.n_atoms, "w")
         self._check(L.pcv_load_landmarks(h, self.n_atoms, self.n_landmarks, _ptr(lm), qp, wp,
                                          ctypes.c_double(1.0 if lam is None else float(lam))))
+        del qa, wa
         if lam is None:
             out = ctypes.c_double()
             self._check(L.pcv_path_lambda(h, ctypes.c_double(lambda_factor), ctypes.byref(out)))
@@ -277,6 +279,14 @@ class PathCV:
                                                                                 device=x.device)
         self._check(self._L.pcv_eval_properties(self._h, _ptr(x), P, _ptr(q), _ptr(S), _ptr(dS)))
         return {"S": S, "dS_dx": dS}
+
+    def set_displacement_weights(self, w_disp=None):
+        """Per-atom displacement weights ``w`` of the distance, separate from
+        the alignment weights given at construction (``None``: off).  See
+        ``pcv_set_displacement_weights``."""
+        arr, wp = _as_host_f64(w_disp, self.n_atoms, "w_disp")
+        self._check(self._L.pcv_set_displacement_weights(self._h, wp))
+        del arr
 
     def set_neighbour_list(self, M: int, stride: int = 1):
         """Neighbour list of the ``M`` nearest references refreshed every

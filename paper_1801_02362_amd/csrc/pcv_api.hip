@@ -88,6 +88,12 @@ struct pcv_handle {
   // property maps: rotations and distances of their exact pass, scratch
   double *Rprop = nullptr, *Dprop = nullptr, *Wprop = nullptr, *part_prop = nullptr;
   DevMem propmem;
+  // separate displacement weights (w != w'; off while wd is null): the
+  // weights, per-landmark statistics and the three-pass scratch
+  DevMem f2mem;
+  double *wd = nullptr, *Gaw = nullptr, *mua = nullptr, *Caa = nullptr, *xc2 = nullptr, *fs2 = nullptr,
+         *Rl2 = nullptr, *Gl2 = nullptr, *Rmu2 = nullptr, *cw2 = nullptr, *pw2 = nullptr, *part2 = nullptr,
+         *D2 = nullptr;
   int nl_M = 0, nl_stride = 0;
   long long nl_step = 0;
   DevMem nlmem, nlpmem;
@@ -188,6 +194,7 @@ extern "C" pcv_status pcv_destroy(pcv_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   collect_timing(h);
   drop_graphs(h);
+  h->f2mem.release();
   h->propmem.release();
   h->nlpmem.release();
   h->nlmem.release();
@@ -453,6 +460,8 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   h->nl_step = 0;
   h->propmem.release();
   h->Wprop = h->part_prop = nullptr;
+  h->f2mem.release();
+  h->wd = nullptr;
   h->pmem.release();
   h->mem.release();
   h->n = n_atoms;
@@ -712,11 +721,101 @@ static pcv_status run_maybe_graph(pcv_handle* h, const void* const key[7], F&& e
   return PCV_OK;
 }
 
+// ------------------------------------------- separate displacement weights
+static F2Args f2_args(pcv_handle* h) {
+  F2Args a{};
+  a.A = h->A;
+  a.ca = h->ca;
+  a.Ga = h->Ga;
+  a.Gaw = h->Gaw;
+  a.mua = h->mua;
+  a.Caa = h->Caa;
+  a.wa = h->w;
+  a.wd = h->wd;
+  a.xc = h->xc2;
+  a.fs = h->fs2;
+  a.Rl = h->Rl2;
+  a.Gl = h->Gl2;
+  a.Rmu = h->Rmu2;
+  a.cw = h->cw2;
+  a.pw = h->pw2;
+  a.part = h->part2;
+  a.q = h->q;
+  a.status = h->status;
+  a.fallbacks = h->counters + CNT_FALLBACK;
+  a.lam = h->lam;
+  a.L = h->L;
+  a.n = h->n;
+  a.n_pad = h->n_pad;
+  return a;
+}
+
+extern "C" pcv_status pcv_set_displacement_weights(pcv_handle* h, const double* w_disp) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  std::vector<double> hw;
+  if (w_disp) {
+    if (h->nl_M > 0) return fail(h, PCV_EUNSUPPORTED, "displacement weights with a neighbour list");
+    double s = 0.0;
+    for (int j = 0; j < h->n; ++j) {
+      if (!(w_disp[j] >= 0.0) || !std::isfinite(w_disp[j]))
+        return fail(h, PCV_EINVAL, "displacement weights must be finite and >= 0");
+      s += w_disp[j];
+    }
+    if (!(s > 0.0)) return fail(h, PCV_EINVAL, "displacement weights must have a positive sum");
+    hw.assign(h->n_pad, 0.0);
+    for (int j = 0; j < h->n; ++j) hw[j] = w_disp[j] / s;
+  }
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  drop_graphs(h);
+  h->plan_version++;
+  h->f2mem.release();
+  h->wd = nullptr;
+  if (!w_disp) return PCV_OK;
+  const size_t np = h->n_pad, L = h->L, chunks = f2_chunks(h->n_pad, h->L);
+  DevMem& m = h->f2mem;
+  double* wd = nullptr;
+  HIP_TRY(h, m.alloc((void**)&wd, np * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Gaw, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->mua, L * 3 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Caa, L * 6 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->xc2, 3 * np * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->fs2, 11 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rl2, L * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Gl2, L * 9 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->Rmu2, L * 3 * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->cw2, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->pw2, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->D2, L * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->part2, chunks * 12 * np * sizeof(double)));
+  HIP_TRY(h, hipMemcpy(wd, hw.data(), np * sizeof(double), hipMemcpyHostToDevice));
+  h->wd = wd;
+  const F2Args a = f2_args(h);
+  hipError_t e = h->fp64 ? launch_f2_stats<double>(a, h->stream) : launch_f2_stats<float>(a, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->f2mem.release();
+    h->wd = nullptr;
+    return hip_fail(h, e, "f2_stats");
+  }
+  return PCV_OK;
+}
+
 extern "C" pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx, double* msd) {
   if (!h) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
   PrepArgs* d_pa = h->d_prep;
+  if (h->wd) {
+    const void* key[7] = {x, sz, ds_dx, dz_dx, msd, nullptr, (const void*)8};
+    return run_maybe_graph(h, key, [&](hipStream_t st) {
+      const F2Args a = f2_args(h);
+      double* dout = msd ? msd : h->D2;
+      return h->fp64 ? launch_f2_eval<double>(a, x, sz, ds_dx, dz_dx, dout, h->counters, st)
+                     : launch_f2_eval<float>(a, x, sz, ds_dx, dz_dx, dout, h->counters, st);
+    });
+  }
   if (h->nl_M > 0) {
     if (msd) return fail(h, PCV_EINVAL, "msd output is not available with a neighbour list");
     const bool update = h->nl_step % h->nl_stride == 0;
@@ -742,6 +841,7 @@ static pcv_status eval_close_impl(pcv_handle* h, const void* x, double* sz, void
   if (!h) return PCV_EINVAL;
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   if (!x || !sz) return fail(h, PCV_EINVAL, "x and sz are required");
+  if (h->wd) return fail(h, PCV_EUNSUPPORTED, "the close structure with displacement weights");
   if (h->nl_M > 0) {
     if (msd) return fail(h, PCV_EINVAL, "msd output is not available with a neighbour list");
     const bool update = advance && h->nl_step % h->nl_stride == 0;
@@ -783,6 +883,7 @@ extern "C" pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, c
   if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
   if (!x || !q || !S) return fail(h, PCV_EINVAL, "x, q and S are required");
   if (P < 1 || P > kPropsMax) return fail(h, PCV_EINVAL, "need 1 <= P <= " + std::to_string(kPropsMax));
+  if (h->wd) return fail(h, PCV_EUNSUPPORTED, "property maps with displacement weights");
   if (!h->Wprop) {
     HIP_TRY(h, hipSetDevice(h->opt.device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -803,6 +904,7 @@ extern "C" pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride) {
   if (M < 0 || (M > 0 && (M > h->L || stride < 1))) return fail(h, PCV_EINVAL, "need 1 <= M <= L and stride >= 1");
   if (M > 0 && h->L > nl_select_max())
     return fail(h, PCV_EUNSUPPORTED, "neighbour lists need L <= " + std::to_string(nl_select_max()));
+  if (M > 0 && h->wd) return fail(h, PCV_EUNSUPPORTED, "a neighbour list with displacement weights");
   HIP_TRY(h, hipSetDevice(h->opt.device));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   drop_graphs(h);
@@ -858,6 +960,7 @@ extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h) {
 extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
                                                        double* sz, void* ds, void* dz, const int** flag) {
   if (h->fp64 || h->L == 0 || h->n != n_atoms) return hipErrorInvalidValue;
+  if (h->wd) return hipErrorNotSupported;
   PrepArgs pa{0, h->w, h->xw, h->Gx, h->Gx32, h->xres, h->status, nullptr, h->n, h->n_pad, h->L};
   pa.xw32 = h->xw32;
   pa.n_x = h->n_x;

@@ -223,6 +223,37 @@ template <typename T>
 hipError_t launch_props(const PropsArgs& a, const double* q, double lam, double* S, double* W, double* part,
                         void* dS, hipStream_t st);
 
+// Separate displacement weights (w != w'): device buffers of the handle.
+struct F2Args {
+  const void* A;           // [L][3][n_pad] coordinate type
+  const double* ca;        // [L][3] centroids by the alignment weights
+  const double* Ga;        // [L] sum w' |a_c|^2
+  double* Gaw;             // [L] sum w |a_c|^2
+  double* mua;             // [L][3] sum w a_c
+  double* Caa;             // [L][6] sum w a_c a_c^T (xx xy xz yy yz zz)
+  const double* wa;        // [n_pad] alignment weights w' (normalised)
+  const double* wd;        // [n_pad] displacement weights w (normalised)
+  double* xc;              // [3][n_pad] centred frame (FP64)
+  double* fs;              // [11]: G_x^{w'}, G_x^w, mu_x[3], K_c[3], K_p[3]
+  double* Rl;              // [L][9] rotations
+  double* Gl;              // [L][9] rotation adjoints Gamma
+  double* Rmu;             // [L][3] R mu_a
+  double* cw;              // [L] ds weights c_i
+  double* pw;              // [L] dz weights p_i
+  double* part;            // [chunks][12][n_pad]
+  const double* q;         // [L] properties
+  int* status;             // sticky non-finite flag
+  long long* fallbacks;    // Jacobi fallbacks (may be null)
+  double lam;
+  int L, n, n_pad;
+};
+int f2_chunks(int n_pad, int L);
+template <typename T>
+hipError_t launch_f2_stats(const F2Args& a, hipStream_t st);
+template <typename T>
+hipError_t launch_f2_eval(const F2Args& a, const void* x, double* sz, void* ds, void* dz, double* dout,
+                          long long* counters, hipStream_t st);
+
 bool engine_supported(EngineCfg cfg, bool fp64);
 void engine_configs(bool fp64, EngineCfg* out, int* count);   // the compiled menu
 hipError_t engine_init_attributes();

@@ -66,6 +66,20 @@ def test_matches_svd_superposition(n, seed):
         assert np.abs(sp.R - Rk).max() < 1e-9
 
 
+@pytest.mark.parametrize("n,seed", [(5, 25), (30, 26)])
+def test_two_weight_sets_match_alignment_superposition(n, seed):
+    """w != w': centring and rotation by the alignment weights (an SVD fit
+    under w'), then the distance by the displacement weights w."""
+    x, a = _pair(n, seed, noise=0.2)
+    rng = np.random.default_rng(seed)
+    w, wp = normalise_weights(rng.uniform(0.0, 1.0, n), n), normalise_weights(rng.uniform(0.2, 1.0, n), n)
+    sp = superpose(x, a, w, wp)
+    _, Rk = _kabsch(x, a, wp)
+    d = (x - wp @ x) - (a - wp @ a) @ Rk.T
+    assert abs(float(sp.D) - float(np.sum(w[:, None] * d * d))) < 1e-13
+    assert float(sp.D) > float(superpose(x, a, w, w).D) - 1e-15   # w's own fit is the minimum
+
+
 @pytest.mark.parametrize("seed", [31, 32, 33])
 def test_top_eigenvalue_is_largest_characteristic_root(seed):
     n = 10
