@@ -42,17 +42,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_NAMES = {1: "engine_kernel", 2: "engine2_kernel", 3: "engine3_kernel"}
+KERNEL_NAMES = {1: "engine_kernel", 2: "engine2_kernel", 3: "engine3_kernel", 4: "engine4_kernel"}
+
+# The translation unit of each engine kernel: its source and the headers it
+# includes (a counter summary is valid only for the code it was taken on).
+KERNEL_SOURCES = {
+    "engine_kernel": ["pcv_kernels.hip", "pcv_internal.h", "pcv_math.h"],
+    "engine2_kernel": ["pcv_engine2.hip", "pcv_internal.h", "pcv_math.h"],
+    "engine3_kernel": ["pcv_engine3.hip", "pcv_internal.h", "pcv_math.h", "pcv_stream.h"],
+    "engine4_kernel": ["pcv_engine4.hip", "pcv_internal.h", "pcv_math.h", "pcv_stream.h"],
+}
 
 
-def kernel_source_hash() -> str:
-    """Hash of every device source (the counter summary is only valid for it)."""
+def kernel_source_hash(kernel: str = "engine3_kernel") -> str:
+    """Hash of the kernel's translation unit (source plus included headers)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1801_02362_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -63,7 +71,7 @@ def counted_traffic(name: str):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_sha") != kernel_source_hash():
+    if d.get("kernel_source_sha") != kernel_source_hash(d.get("kernel", "engine3_kernel")):
         return None
     return d.get("bytes_per_launch")
 

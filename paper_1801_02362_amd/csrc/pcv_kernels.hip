@@ -173,45 +173,72 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
 }
 
 // ------------------------------------------------------------ frame prep
-template <typename T, int BS>
+// CACHE: atoms per thread whose x and w the first pass keeps in registers
+// for the second (one global round trip fewer); atoms past CACHE * BS are
+// loaded again.  The sums are taken in the same order either way.
+template <typename T, int BS, int CACHE = 0>
 __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& Gx, bool& finite,
                              double c[3], double g32[4]) {
+  constexpr int KC = CACHE > 0 ? CACHE : 1;
+  T xk[KC][3];
+  double wk[KC];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < a.n; j += BS) {
-    const double wj = a.w[j];
+  auto acc1 = [&](double wj, const T* xv) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double xv = (double)x[3 * j + d];
-      if (!isfinite(xv)) v[3] += 1.0;
-      v[d] = fma(wj, xv, v[d]);
+      const double xd = (double)xv[d];
+      if (!isfinite(xd)) v[3] += 1.0;
+      v[d] = fma(wj, xd, v[d]);
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < CACHE; ++k) {
+    const int j = threadIdx.x + k * BS;
+    if (j < a.n) {
+      wk[k] = a.w[j];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xk[k][d] = x[3 * j + d];
     }
   }
+#pragma unroll
+  for (int k = 0; k < CACHE; ++k)
+    if (threadIdx.x + k * BS < a.n) acc1(wk[k], xk[k]);
+  for (int j = threadIdx.x + CACHE * BS; j < a.n; j += BS) acc1(a.w[j], x + 3 * j);
   block_sum<4, BS>(v, sh);
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
   // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x rounded to T.
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < a.n_pad; j += BS) {
-    if (j < a.n) {
-      const double wj = a.w[j];
+  auto acc2 = [&](int j, double wj, const T* xv) {
+    const double iw = wj > 0.0 ? 1.0 / wj : 0.0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double xv = (double)x[3 * j + d] - c[d];
-        const double xwv = wj * xv;
-        a.xw[(size_t)d * a.n_pad + j] = xwv;
-        if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = (float)xwv;
-        g[0] = fma(wj * xv, xv, g[0]);
-        const double r = (double)(T)xwv;
-        if (wj > 0.0) g[1] += r * r / wj;
-        g[2 + d] += r;
-      }
-    } else {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        a.xw[(size_t)d * a.n_pad + j] = 0.0;
-        if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = 0.f;
-      }
+    for (int d = 0; d < 3; ++d) {
+      const double xd = (double)xv[d] - c[d];
+      const double xwv = wj * xd;
+      a.xw[(size_t)d * a.n_pad + j] = xwv;
+      if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = (float)xwv;
+      g[0] = fma(wj * xd, xd, g[0]);
+      const double r = (double)(T)xwv;
+      g[1] = fma(r * r, iw, g[1]);
+      g[2 + d] += r;
     }
+  };
+  auto pad = [&](int j) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a.xw[(size_t)d * a.n_pad + j] = 0.0;
+      if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = 0.f;
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < CACHE; ++k) {
+    const int j = threadIdx.x + k * BS;
+    if (j < a.n) acc2(j, wk[k], xk[k]);
+    else if (j < a.n_pad) pad(j);
+  }
+  for (int j = threadIdx.x + CACHE * BS; j < a.n_pad; j += BS) {
+    if (j < a.n) acc2(j, a.w[j], x + 3 * j);
+    else pad(j);
   }
   block_sum<5, BS>(g, sh);
   Gx = g[0];
@@ -230,7 +257,7 @@ __global__ __launch_bounds__(1024) void prep_kernel(const PrepArgs* __restrict__
   const T* x = (const T*)x_base + 3 * a.x_off;
   double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, 1024>(a, x, sh, Gx, finite, c, g32);
+  centre_frame<T, 1024, 4>(a, x, sh, Gx, finite, c, g32);
   if (threadIdx.x == 0) {
     *a.Gx = Gx;
     *a.Gx32 = g32[0];
@@ -642,8 +669,24 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
-#pragma unroll 4
-      for (int t = sg; t < gn; t += 4) {
+      // Slots t = sg, sg + 4, ... in order; 16 of them are loaded before
+      // any is added, so a wave waits for one round trip per 16 slots.
+      int t = sg;
+      for (; t + 60 < gn; t += 64) {
+        double u[16], v[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          u[b] = (double)ldg(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+          v[b] = ldg(partial_v<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+        }
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const double f = fq[0][t + 4 * b];
+          gs = fma(f, fma(fq[1][t + 4 * b], v[b], u[b]), gs);
+          gz = fma(f, v[b], gz);
+        }
+      }
+      for (; t < gn; t += 4) {
         const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = fq[0][t];
