@@ -673,19 +673,21 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
       // any is added, so a wave waits for one round trip per 16 slots.
       int t = sg;
       for (; t + 60 < gn; t += 64) {
-        double u[16], v[16];
+        acc u[16];
+        double v[16];
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
-          u[b] = (double)ldg(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+          u[b] = ldg(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
           v[b] = ldg(partial_v<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
         }
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
           const double f = fq[0][t + 4 * b];
-          gs = fma(f, fma(fq[1][t + 4 * b], v[b], u[b]), gs);
+          gs = fma(f, fma(fq[1][t + 4 * b], v[b], (double)u[b]), gs);
           gz = fma(f, v[b], gz);
         }
       }
+#pragma unroll 4
       for (; t < gn; t += 4) {
         const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);

@@ -54,3 +54,29 @@ def test_batch_equals_single_handles():
         assert np.abs(g - ds[b.atom_off[i]:b.atom_off[i + 1]]).max() <= 1e-5 * np.abs(g).max()
         cv.close()
     b.close()
+
+
+def test_full_64_walker_batch_sampled_walkers():
+    """The 64-walker batch the bench times (atoms U[50, 2000], landmarks
+    U[200, 5000], one persistent launch, default plan): eight walkers
+    spread over the launch checked against the oracle in full, and every
+    walker's s within [1, L] with finite gradients."""
+    import paper_1801_02362_amd as pcv
+    import torch
+    from gpu_util import TOL32, check_cv, dev, host, say
+    ws = wl.cfg3(n_walkers=64, n_frames=1)
+    lams = [landmark_lambda(w.system.landmarks) for w in ws]
+    b = pcv.BatchPathCV([dev(w.system.landmarks, torch.float32) for w in ws], lams)
+    say(f"[batch] full 64 walkers, plan {b.plan}")
+    x = dev(np.concatenate([w.frames[0] for w in ws]), torch.float32)
+    sz, ds, dz = b.eval(x)
+    sz, ds, dz = host(sz), host(ds), host(dz)
+    b.close()
+    for i, w in enumerate(ws):
+        assert 1.0 <= sz[i][0] <= w.system.n_landmarks, f"walker{i}: s out of range"
+    assert np.isfinite(ds).all() and np.isfinite(dz).all()
+    for i in (0, 9, 18, 27, 36, 45, 54, 63):
+        w = ws[i]
+        ref = path_cv(w.frames[0].astype(np.float64), w.system.landmarks.astype(np.float64), lams[i])
+        a0, a1 = b.atom_off[i], b.atom_off[i + 1]
+        check_cv(f"walker{i}", TOL32, sz[i], ds[a0:a1], dz[a0:a1], None, ref)

@@ -41,6 +41,25 @@ def test_cfg0_fp64(torch):
     _run_exact(torch, sysm.landmarks, frames[::50], lam, dtype=torch.float64, tol=TOL64, name="cfg0")
 
 
+def test_cfg2_full_size_in_the_bench_configuration(torch):
+    """5,000 atoms x 10,000 landmarks (600 MB), the plan the bench times
+    (engine 3, one item per CU): every D_i, s, z and both gradients of one
+    frame against the oracle."""
+    import paper_1801_02362_amd as pcv
+    from gpu_util import TOL32, check_cv, dev, host, say
+    sysm, base = wl.cfg2(n_atoms=5000, n_landmarks=10000)
+    f = wl.cfg2_frames(base, 1)[0]
+    cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), None)
+    say(f"[exact] cfg2 full size: plan={cv.plan} lambda={cv.lam:.4f}")
+    assert cv.plan["engine"] == 3 and cv.plan["items"] == cv.plan["grid"]
+    o = cv.eval(dev(f, torch.float32), msd=True)
+    got = host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"])
+    cv.check()
+    cv.close()
+    ref = path_cv(f.astype(np.float64), sysm.landmarks.astype(np.float64), cv.lam)
+    check_cv("cfg2_full", TOL32, *got, ref)
+
+
 def test_cfg1_fp32_near_and_far_frames(torch):
     from gpu_util import TOL32
     sysm, frames = wl.cfg1(100_000)
