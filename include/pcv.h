@@ -210,6 +210,27 @@ pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, const double
  */
 pcv_status pcv_set_displacement_weights(pcv_handle* h, const double* w_disp);
 
+/*
+ * Checkpoint and resume of the state that carries between steps (Algorithm 2
+ * and the neighbour list of Section 2): the close structure y, G_y, the saved
+ * rotations R_{a_i y} (Section 3.2), the first-frame and forced-reassignment
+ * flags, the counters, and the neighbour list (M, stride, call count,
+ * members and their saved rotations).  Landmarks, lambda, eps, weights and
+ * the plan are configuration and are not part of the state.
+ *   pcv_save_state: buf = host buffer of *bytes bytes, or NULL to query the
+ *     size (*bytes receives it); PCV_EINVAL (and the size in *bytes) when
+ *     the buffer is too small.
+ *   pcv_load_state: buf = host bytes written by pcv_save_state for a handle
+ *     with the same precision, atom count and landmark set (checked against
+ *     a fingerprint of the landmarks: PCV_ESHAPE / PCV_EINVAL otherwise).  A
+ *     saved neighbour list replaces the handle's (allocating as
+ *     pcv_set_neighbour_list does).  Evaluations after a load continue
+ *     exactly as they would have on the saved handle.
+ * Both synchronise the stream.
+ */
+pcv_status pcv_save_state(pcv_handle* h, void* buf, size_t* bytes);
+pcv_status pcv_load_state(pcv_handle* h, const void* buf, size_t bytes);
+
 /* Counters (synchronises the stream). */
 pcv_status pcv_get_stats(pcv_handle* h, pcv_stats* out);
 pcv_status pcv_reset_stats(pcv_handle* h);

@@ -119,6 +119,8 @@ def load_library():
         "pcv_set_neighbour_list": (st, [vp, i, i]),
         "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
         "pcv_set_displacement_weights": (st, [vp, vp]),
+        "pcv_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "pcv_load_state": (st, [vp, vp, ctypes.c_size_t]),
         "pcv_get_neighbour_list": (st, [vp, vp, i, ctypes.POINTER(i)]),
         "pcv_bias_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_BiasOptions)]),
         "pcv_bias_destroy": (st, [vp]),
@@ -287,6 +289,20 @@ class PathCV:
         arr, wp = _as_host_f64(w_disp, self.n_atoms, "w_disp")
         self._check(self._L.pcv_set_displacement_weights(self._h, wp))
         del arr
+
+    def save_state(self) -> bytes:
+        """Checkpoint of the close structure, counters and neighbour list
+        (``pcv_save_state``)."""
+        n = ctypes.c_size_t(0)
+        self._check(self._L.pcv_save_state(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._L.pcv_save_state(self._h, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def load_state(self, state: bytes):
+        """Resume from ``save_state`` output (``pcv_load_state``)."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        self._check(self._L.pcv_load_state(self._h, ctypes.cast(buf, ctypes.c_void_p), len(state)))
 
     def set_neighbour_list(self, M: int, stride: int = 1):
         """Neighbour list of the ``M`` nearest references refreshed every

@@ -948,6 +948,140 @@ extern "C" pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int ca
   return PCV_OK;
 }
 
+// ------------------------------------------------------- checkpoint / resume
+// The state that carries over between steps: the close structure y (centred,
+// FP64), G_y, the saved rotations R_{a_i y}, the first-frame and forced
+// flags, the counters, and the neighbour list (size, stride, step count,
+// members and their saved rotations).  A fingerprint of the landmark set
+// (sums of G_a and of the centroids' squared norms) guards against loading
+// a state into a handle with other landmarks.
+namespace {
+constexpr unsigned long long kStateMagic = 0x3130455441545350ull;   // "PSTATE01"
+constexpr int kStateVersion = 1;
+struct StateHeader {
+  unsigned long long magic;
+  int version, precision, n, L, nl_M, nl_stride, init, force;
+  long long nl_step;
+  double ga_sum, ca_sum;
+};
+}  // namespace
+
+static size_t state_bytes(const pcv_handle* h, int nl_M) {
+  return sizeof(StateHeader) + (3 * (size_t)h->n_pad + 1 + 9 * (size_t)h->L) * sizeof(double) +
+         CNT_N * sizeof(long long) + (size_t)nl_M * (sizeof(int) + 9 * sizeof(double));
+}
+
+static pcv_status landmark_fingerprint(pcv_handle* h, double& ga_sum, double& ca_sum) {
+  std::vector<double> ga(h->L), ca(3 * (size_t)h->L);
+  HIP_TRY(h, hipMemcpy(ga.data(), h->Ga, ga.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(ca.data(), h->ca, ca.size() * sizeof(double), hipMemcpyDeviceToHost));
+  ga_sum = 0.0;
+  ca_sum = 0.0;
+  for (double v : ga) ga_sum += v;
+  for (double v : ca) ca_sum += v * v;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_save_state(pcv_handle* h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  const size_t need = state_bytes(h, h->nl_M);
+  if (!buf) {
+    *bytes = need;
+    return PCV_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(h, PCV_EINVAL, "state buffer too small");
+  }
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  StateHeader hd{};
+  hd.magic = kStateMagic;
+  hd.version = kStateVersion;
+  hd.precision = h->fp64 ? PCV_FP64 : PCV_FP32;
+  hd.n = h->n;
+  hd.L = h->L;
+  hd.nl_M = h->nl_M;
+  hd.nl_stride = h->nl_stride;
+  hd.nl_step = h->nl_step;
+  HIP_TRY(h, hipMemcpy(&hd.init, h->init, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&hd.force, h->force, sizeof(int), hipMemcpyDeviceToHost));
+  pcv_status st = landmark_fingerprint(h, hd.ga_sum, hd.ca_sum);
+  if (st != PCV_OK) return st;
+  char* p = (char*)buf;
+  std::memcpy(p, &hd, sizeof(hd));
+  p += sizeof(hd);
+  const size_t ny = 3 * (size_t)h->n_pad * sizeof(double), nr = 9 * (size_t)h->L * sizeof(double);
+  HIP_TRY(h, hipMemcpy(p, h->y64, ny, hipMemcpyDeviceToHost));
+  p += ny;
+  HIP_TRY(h, hipMemcpy(p, h->Gy, sizeof(double), hipMemcpyDeviceToHost));
+  p += sizeof(double);
+  HIP_TRY(h, hipMemcpy(p, h->Rsave, nr, hipMemcpyDeviceToHost));
+  p += nr;
+  HIP_TRY(h, hipMemcpy(p, h->counters, CNT_N * sizeof(long long), hipMemcpyDeviceToHost));
+  p += CNT_N * sizeof(long long);
+  if (h->nl_M > 0) {
+    HIP_TRY(h, hipMemcpy(p, h->nl_members, (size_t)h->nl_M * sizeof(int), hipMemcpyDeviceToHost));
+    p += (size_t)h->nl_M * sizeof(int);
+    HIP_TRY(h, hipMemcpy(p, h->Rsave_nl, (size_t)h->nl_M * 9 * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  *bytes = need;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_load_state(pcv_handle* h, const void* buf, size_t bytes) {
+  if (!h || !buf) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (bytes < sizeof(StateHeader)) return fail(h, PCV_EINVAL, "state buffer too small");
+  StateHeader hd;
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != kStateMagic || hd.version != kStateVersion) return fail(h, PCV_EINVAL, "not a saved state");
+  if (hd.precision != (h->fp64 ? PCV_FP64 : PCV_FP32) || hd.n != h->n || hd.L != h->L)
+    return fail(h, PCV_ESHAPE, "state saved for another precision, atom count or landmark count");
+  if (hd.nl_M < 0 || hd.nl_M > h->L || (hd.nl_M > 0 && hd.nl_stride < 1))
+    return fail(h, PCV_EINVAL, "corrupt neighbour-list fields");
+  if (bytes < state_bytes(h, hd.nl_M)) return fail(h, PCV_EINVAL, "state buffer too small");
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  double ga_sum, ca_sum;
+  pcv_status st = landmark_fingerprint(h, ga_sum, ca_sum);
+  if (st != PCV_OK) return st;
+  auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-12 * std::max(1.0, std::fabs(b)); };
+  if (!close(hd.ga_sum, ga_sum) || !close(hd.ca_sum, ca_sum))
+    return fail(h, PCV_EINVAL, "state saved for another landmark set");
+  if (hd.nl_M != h->nl_M || (hd.nl_M > 0 && hd.nl_stride != h->nl_stride)) {
+    st = pcv_set_neighbour_list(h, hd.nl_M, hd.nl_M > 0 ? hd.nl_stride : 1);
+    if (st != PCV_OK) return st;
+  }
+  const char* p = (const char*)buf + sizeof(hd);
+  const size_t ny = 3 * (size_t)h->n_pad * sizeof(double), nr = 9 * (size_t)h->L * sizeof(double);
+  HIP_TRY(h, hipMemcpy(h->y64, p, ny, hipMemcpyHostToDevice));
+  p += ny;
+  HIP_TRY(h, hipMemcpy(h->Gy, p, sizeof(double), hipMemcpyHostToDevice));
+  p += sizeof(double);
+  HIP_TRY(h, hipMemcpy(h->Rsave, p, nr, hipMemcpyHostToDevice));
+  p += nr;
+  HIP_TRY(h, hipMemcpy(h->counters, p, CNT_N * sizeof(long long), hipMemcpyHostToDevice));
+  p += CNT_N * sizeof(long long);
+  HIP_TRY(h, hipMemcpy(h->init, &hd.init, sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->force, &hd.force, sizeof(int), hipMemcpyHostToDevice));
+  if (hd.nl_M > 0) {
+    std::vector<int> mem(hd.nl_M);
+    std::memcpy(mem.data(), p, mem.size() * sizeof(int));
+    p += mem.size() * sizeof(int);
+    for (int v : mem)
+      if (v < 0 || v >= h->L) return fail(h, PCV_EINVAL, "corrupt neighbour-list members");
+    HIP_TRY(h, hipMemcpy(h->nl_members, mem.data(), mem.size() * sizeof(int), hipMemcpyHostToDevice));
+    hipError_t e = h->fp64 ? nl_gather<double>(h, h->stream, nullptr, 0) : nl_gather<float>(h, h->stream, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(h, e, "neighbour-list gather");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(h->Rsave_nl, p, (size_t)hd.nl_M * 9 * sizeof(double), hipMemcpyHostToDevice));
+    h->nl_step = hd.nl_step;
+  }
+  return PCV_OK;
+}
+
 // Token naming a handle and its current buffers (for callers that cache
 // hipGraphs capturing the handle's kernels).
 extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h) {
