@@ -445,7 +445,9 @@ def bench_batch(args):
            "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 coords, f64 correlation/eigen/lse", "data": "synthetic",
            "config": {"workload": "64 walkers, atoms U[50,2000], landmarks U[200,5000], one persistent launch",
-                      "bytes_per_step": pairs * 12, "plan": b.plan, "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}}
+                      "bytes_per_step": pairs * 12, "plan": b.plan,
+                      "plan_source": "autotuner" if args.tune else "heuristic",
+                      "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}}
     b.close()
     return out
 
@@ -664,7 +666,8 @@ def main():
     ap.add_argument("--landmarks", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="batch workload: take the heuristic plan instead of the autotuner's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "

@@ -609,10 +609,10 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   int nw[16], ac[16], ag[16], cnt2 = 0;
   engine2_configs(b->fp64, nw, ac, ag, &cnt2);
   const int maxn = *std::max_element(b->n.begin(), b->n.end());
-  std::vector<BatchPlan> cands;
+  std::vector<BatchPlan> cands{base};   // the heuristic plan competes too
   if (!b->fp64)
     for (int spw : {3, 2})
-      for (int per : {8, 16, 32, 64})
+      for (int per : {8, 16, 24, 32, 64})
         for (int lpt : {1, 0}) {
           BatchPlan c;
           c.engine = 4;
@@ -650,27 +650,46 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   hipEvent_t e0, e1;
   BHIP_TRY(b, hipEventCreate(&e0));
   BHIP_TRY(b, hipEventCreate(&e1));
-  BatchPlan best = base;
-  float best_ms = 1e30f;
-  for (const BatchPlan& c : cands) {
-    if (batch_apply(b, c) != PCV_OK) continue;
+  // Time `reps` back-to-back runs of the applied plan (ms per run).
+  auto time_runs = [&](int reps) {
+    (void)hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps; ++r) batch_run(b, x, sz, ds, nullptr, false);
+    (void)hipEventRecord(e1, b->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms / reps;
+  };
+  // Screen: every candidate whose s and z match the heuristic plan's, three
+  // runs each.  Then the three fastest are timed again, ten runs in each of
+  // three interleaved rounds, and the best round decides.
+  std::vector<std::pair<float, int>> screened;
+  for (int k = 0; k < (int)cands.size(); ++k) {
+    if (batch_apply(b, cands[k]) != PCV_OK) continue;
     if (batch_run(b, x, sz, ds, nullptr, false) != PCV_OK) continue;
     if (hipStreamSynchronize(b->stream) != hipSuccess) continue;
     if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) continue;
     bool ok = true;
     for (int i = 0; i < 2 * b->W && ok; ++i) ok = std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i]));
     if (!ok) continue;
-    (void)hipEventRecord(e0, b->stream);
-    for (int r = 0; r < 3; ++r) batch_run(b, x, sz, ds, nullptr, false);
-    (void)hipEventRecord(e1, b->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
-    }
+    screened.emplace_back(time_runs(3), k);
   }
+  std::sort(screened.begin(), screened.end());
+  if (screened.size() > 3) screened.resize(3);
+  std::vector<float> best_round(screened.size(), 1e30f);
+  for (int round = 0; round < 3; ++round)
+    for (size_t r = 0; r < screened.size(); ++r) {
+      if (batch_apply(b, cands[screened[r].second]) != PCV_OK) continue;
+      batch_run(b, x, sz, ds, nullptr, false);
+      best_round[r] = std::min(best_round[r], time_runs(10));
+    }
+  BatchPlan best = base;
+  float best_ms = 1e30f;
+  for (size_t r = 0; r < screened.size(); ++r)
+    if (best_round[r] < best_ms) {
+      best_ms = best_round[r];
+      best = cands[screened[r].second];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   tmp.release();
