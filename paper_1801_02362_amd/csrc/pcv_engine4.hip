@@ -194,12 +194,7 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
           const bool last = (s == SPW - 1) || (u + 1 >= lim) || (uk[s < SPW - 1 ? s + 1 : s] != uk[s]);
           double* pp = e4_part[t & 1][u];
           if (last) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) M[q] = wave_sum_to63(M[q]);
-            if (lane == 63) {
-#pragma unroll
-              for (int q = 0; q < 9; ++q) pp[q] = M[q];
-            }
+            wave_sum9_store(M, pp, lane);
 #pragma unroll
             for (int q = 0; q < 9; ++q) M[q] = 0.0;
           } else if (lane == 63) {

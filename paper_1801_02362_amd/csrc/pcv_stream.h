@@ -76,6 +76,63 @@ __device__ __forceinline__ double wave_sum_to63(double v) {
   return v;
 }
 
+// 64-bit lane exchanges through gfx950's swap instructions.  swap32: lanes
+// 32-63 of a trade places with lanes 0-31 of b, so afterwards a holds
+// (a[0..31], b[0..31]) and b holds (a[32..63], b[32..63]).  swap16: the same
+// between the odd rows of a and the even rows of b (rows of 16 lanes), so a
+// holds rows (a0, b0, a2, b2) and b rows (a1, b1, a3, b3).
+__device__ __forceinline__ double join_f64(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | (unsigned long long)lo);
+}
+__device__ __forceinline__ void swap32_f64(double& a, double& b) {
+  const unsigned long long ia = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ib = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ia, (unsigned)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+  a = join_f64(lo[0], hi[0]);
+  b = join_f64(lo[1], hi[1]);
+}
+__device__ __forceinline__ void swap16_f64(double& a, double& b) {
+  const unsigned long long ia = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ib = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ia, (unsigned)ib, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ia >> 32), (unsigned)(ib >> 32), false, false);
+  a = join_f64(lo[0], hi[0]);
+  b = join_f64(lo[1], hi[1]);
+}
+
+// Wave sums of nine values, stored to out[0..8] by the lanes that end up
+// holding them.  Transposed halving: a swap32 and one add fold a pair of
+// values into one register (value 2k in lanes 0-31, 2k+1 in lanes 32-63),
+// a swap16 and one add fold two of those into one register holding four
+// values (rows: 4k, 4k+2, 4k+1, 4k+3), and a row sum finishes each row, so
+// 9 values cost 5 + 3 folds and 3 row sums instead of 9 full-wave sums.
+__device__ __forceinline__ void wave_sum9_store(const double v[9], double* out, int lane) {
+  double w[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double a = v[2 * k], b = (2 * k + 1 < 9) ? v[2 * k + 1] : 0.0;
+    swap32_f64(a, b);
+    w[k] = a + b;
+  }
+  double u[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double a = w[2 * k], b = (2 * k + 1 < 5) ? w[2 * k + 1] : 0.0;
+    swap16_f64(a, b);
+    u[k] = a + b;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) u[k] = row_sum16(u[k]);
+  if ((lane & 15) == 15) {
+    const int r = lane >> 4;
+    const int off = r == 1 ? 2 : (r == 2 ? 1 : r);   // rows hold values (0, 2, 1, 3) of each group of four
+    out[off] = u[0];
+    out[4 + off] = u[1];
+    if (r == 0) out[8] = u[2];
+  }
+}
+
 // Minimum over each row of 16 lanes (every lane of the row receives it).
 // Lanes must hold finite values or +inf.
 __device__ __forceinline__ double row_min16(double v) {
