@@ -22,9 +22,9 @@
 //     gradient-plus-correlation step; correlation and result slots are
 //     double-buffered by landmark parity.
 //
-// Workers reduce their 9 correlation sums over each 16-lane row with DPP
-// moves; the solver adds the 4 x 7 row sums in a fixed order, so results do
-// not depend on timing.  Each work item writes one partial (m, Z, S, q0, U, V)
+// Workers reduce their 9 correlation sums over the wave by transposed
+// halving (lane swaps, then DPP row sums); the solver adds the 7 worker sums
+// in a fixed order, so results do not depend on timing.  Each work item writes one partial (m, Z, S, q0, U, V)
 // in the format of the other engines, so the merge kernels are shared.
 //
 // Synchronisation: the copies are the only vector-memory operations the
@@ -50,7 +50,7 @@ constexpr int kBlkFloats3 = 3 * kBlk3;          // one block of one landmark (x,
 // ring and the wave's FP32 structure share about 150 KB of LDS.
 constexpr int ring_slots(int bpw) { return bpw >= 3 ? 4 : (bpw == 2 ? 5 : 6); }
 
-__shared__ double e3_part[2][kWorkers3 * 4][9];
+__shared__ double e3_part[2][kWorkers3][9];
 __shared__ double e3_res[2][16];
 __shared__ double e3_misc[16];
 
@@ -168,13 +168,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
           }
         }
       }
-#pragma unroll
-      for (int q = 0; q < 9; ++q) M[q] = row_sum16(M[q]);
-      if ((lane & 15) == 0) {
-        double* pp = e3_part[t & 1][w * 4 + (lane >> 4)];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) pp[q] = M[q];
-      }
+      wave_sum9_store(M, e3_part[t & 1][w], lane);
     }
     bar_lds();
     if (t >= 1) {
@@ -293,11 +287,11 @@ __device__ __forceinline__ void e3_solver(const E3Item& c, int lane, int mode, d
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rsv[k] = Rs[k];
       if (t + 1 < nL) fetch(t + 1, cap, Ga, qi, Rs);
-      // Correlation of landmark t: 28 row sums added in a fixed order.
+      // Correlation of landmark t: the seven worker sums added in a fixed order.
       double ssum = 0.0;
       if (lane < 9) {
         const double(*pp)[9] = e3_part[t & 1];
-        for (int p = 0; p < kWorkers3 * 4; ++p) ssum += pp[p][lane];
+        for (int p = 0; p < kWorkers3; ++p) ssum += pp[p][lane];
       }
       double Mc[9];
 #pragma unroll
