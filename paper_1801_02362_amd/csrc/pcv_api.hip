@@ -611,13 +611,11 @@ static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, do
   Outs o{ds, dz, sz, rec};
   hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
   if (e != hipSuccess) return e;
-  e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, msd);
+  // One engine launch and one merge serve both branches (the flag decides
+  // on the device which problem they take).
+  e = engine_timed<T>(h, st, MODE_APPROX, h->flag, kRunDual, msd, false, 0);
   if (e != hipSuccess) return e;
-  e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, msd);
-  if (e != hipSuccess) return e;
-  e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
-  if (e != hipSuccess) return e;
-  return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
+  return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE);
 }
 
 template <typename T>
@@ -665,10 +663,9 @@ static hipError_t enqueue_close_nl(pcv_handle* h, hipStream_t st, const void* x,
   hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
   if (e != hipSuccess) return e;
   if (update) {
-    e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, h->dfull);
-    if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, h->dfull);
-    if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
-    if (e == hipSuccess) e = launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
+    e = engine_timed<T>(h, st, MODE_APPROX, h->flag, kRunDual, h->dfull, false, 0);
+    if (e == hipSuccess)
+      e = launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE);
     if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
     if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
     return e;

@@ -436,7 +436,11 @@ __global__ __launch_bounds__(kWG2) void engine2_kernel(const Problem* __restrict
                                                        const int* __restrict__ wg_off, int mode,
                                                        const int* __restrict__ flag, int run_if,
                                                        double* __restrict__ dout, int lbuf_bytes, int bmax) {
-  if (flag != nullptr && *flag != run_if) return;
+  {
+    const Problem* pr = probs;
+    if (!gate_launch(flag, run_if, mode, pr)) return;
+    probs = pr;
+  }
   extern __shared__ double smem[];
   // The role is uniform per wave (scalar), so each wave runs exactly the
   // barriers of its own role loop; every role executes nb + 4 per item.

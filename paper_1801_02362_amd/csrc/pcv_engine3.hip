@@ -393,7 +393,11 @@ __global__ __launch_bounds__(kWG3) void engine3_kernel(const Problem* __restrict
   constexpr int RS = ring_slots(BPW);
   __shared__ float ring[kWorkers3 * RS * kBlkFloats3];
   __shared__ float xs[kWorkers3 * BPW * kBlkFloats3];
-  if (flag != nullptr && *flag != run_if) return;
+  {
+    const Problem* pr = probs;
+    if (!gate_launch(flag, run_if, mode, pr)) return;
+    probs = pr;
+  }
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int it_end = wg_off[blockIdx.x + 1];

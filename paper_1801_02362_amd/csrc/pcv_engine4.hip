@@ -545,7 +545,11 @@ __global__ __launch_bounds__(kWG4) void engine4_kernel(const Problem* __restrict
                                                        double* __restrict__ dout) {
   __shared__ float ring[kW4 * kRing4 * kBF4];
   __shared__ float xs[kMaxBlk4 * kBF4];
-  if (flag != nullptr && *flag != run_if) return;
+  {
+    const Problem* pr = probs;
+    if (!gate_launch(flag, run_if, mode, pr)) return;
+    probs = pr;
+  }
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int it_end = wg_off[blockIdx.x + 1];

@@ -75,6 +75,29 @@ __host__ __device__ inline double* partial_v(void* vec, int slot, int n_pad) {
                                    (size_t)3 * n_pad * sizeof(T));
 }
 
+// Launches gated by the close-structure flag (Algorithm 2).  run_if = 0 or
+// 1: the launch works only when the flag equals it.  run_if = kRunDual: one
+// launch serves both branches, the reassignment (probs + MODE_EXACT_SAVE)
+// when the flag is 1 and the approximate step (probs + MODE_APPROX) when it
+// is 0, with probs pointing at the handle's problem array; nothing for -1.
+constexpr int kRunDual = -2;
+__device__ __forceinline__ bool gate_launch(const int* flag, int run_if, int& mode, const Problem*& probs) {
+  if (flag == nullptr) return true;
+  const int f = __builtin_amdgcn_readfirstlane(*flag);   // one value for the whole wave
+  if (run_if != kRunDual) return f == run_if;
+  if (f == 1) {
+    mode = MODE_EXACT_SAVE;
+    probs += MODE_EXACT_SAVE;
+    return true;
+  }
+  if (f == 0) {
+    mode = MODE_APPROX;
+    probs += MODE_APPROX;
+    return true;
+  }
+  return false;
+}
+
 // Output base pointers of one call (problem p writes at atom offset
 // out_off and (s, z) pair out_idx).
 struct Outs {
@@ -150,9 +173,12 @@ hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds_bytes, const Proble
 template <typename T>
 hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
                               const int* flag, int run_if, hipStream_t st);
+// prob_exact (may be null): the reassignment's problem; when given, the
+// same launch also performs the exact merge on reassignment steps, so the
+// separate flag-gated launch_merge_exact is not needed.
 template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
-                              hipStream_t st);
+                              hipStream_t st, const Problem* prob_exact = nullptr);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);
 

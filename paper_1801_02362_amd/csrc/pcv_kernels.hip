@@ -395,7 +395,11 @@ __global__ __launch_bounds__(WG) void engine_kernel(const Problem* __restrict__ 
                                                     const int* __restrict__ flag, int run_if,
                                                     double* __restrict__ dout) {
   using part_t = typename AccT<T>::type;
-  if (flag != nullptr && *flag != run_if) return;
+  {
+    const Problem* pr = probs;
+    if (!gate_launch(flag, run_if, mode, pr)) return;
+    probs = pr;
+  }
   extern __shared__ double smem[];
   double* red = smem;                       // (WG/64)*9
   double* mh = smem + (WG / 64) * 9;        // (WG/32)*3
@@ -730,18 +734,94 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
 // order, the two rotation adjoints, the outputs.
 // gtmp layout: [0, 3 n_pad) explicit ds, [3 n_pad, 6 n_pad) explicit dz,
 // [6 n_pad, 6 n_pad + 18 * tiles) G shares.
+// 64 atoms x 8 slot groups per workgroup: a tile's slots are spread over
+// eight waves, so each waits for a few round trips only.
+constexpr int kBetaThreads = 512;
+
+// The exact merge (as merge_exact_kernel) of one tile of 64 atoms, all three
+// coordinates, with the workgroup's BS / 64 slot groups: the reassignment
+// branch of a close-structure step served by the same launch.
+template <typename T, int BS>
+__device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile) {
+  using acc = typename AccT<T>::type;
+  constexpr int NG = BS / 64;
+  __shared__ double xsh[2 * NG];
+  __shared__ double xfq[2][256];
+  __shared__ double xred[2][NG][64];
+  double m, Z, S;
+  global_lse<BS>(P, xsh, m, Z, S);
+  const double s = S / Z;
+  const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int j = tile * 64 + a;
+  const int n_pad = P.n_pad;
+  double gs[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
+    __syncthreads();
+    const int g = g0 + threadIdx.x;
+    if (threadIdx.x < 256 && g < P.n_slots) {
+      xfq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, P.lam);
+      xfq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
+    }
+    __syncthreads();
+    const int gn = min(256, P.n_slots - g0);
+    if (j < n_pad) {
+      for (int t = sg; t < gn; t += NG) {
+        const acc* pu = partial_u<acc>(P.vec, g0 + t, n_pad);
+        const double* pv = partial_v<acc>(P.vec, g0 + t, n_pad);
+        const double f = xfq[0][t], dq = xfq[1][t];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double u = (double)ldg(pu + (size_t)c * n_pad + j);
+          const double v = ldg(pv + (size_t)c * n_pad + j);
+          gs[c] = fma(f, fma(dq, v, u), gs[c]);
+          gz[c] = fma(f, v, gz[c]);
+        }
+      }
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();
+    xred[0][sg][a] = gs[c];
+    xred[1][sg][a] = gz[c];
+    __syncthreads();
+    if (sg == 0 && j < P.n) {
+      double ts = 0.0, tz = 0.0;
+      for (int q = 0; q < NG; ++q) {
+        ts += xred[0][q][a];
+        tz += xred[1][q][a];
+      }
+      const double wj = P.w[j];
+      const size_t at = 3 * ((size_t)P.out_off + j) + c;
+      if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * ts / Z);
+      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * tz / Z));
+    }
+  }
+  if (tile == 0 && threadIdx.x == 0) {
+    o.sz[2 * P.out_idx + 0] = s;
+    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
-                                                               double* __restrict__ gtmp) {
+__global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
+                                                               double* __restrict__ gtmp,
+                                                               const Problem* __restrict__ prob_exact, Outs o) {
   using acc = typename AccT<T>::type;  // partial storage type
-  if (*cs.flag != 0) return;
-  __shared__ double sh[8];
+  const int flag = __builtin_amdgcn_readfirstlane(*cs.flag);
+  if (flag == 1 && prob_exact != nullptr) {
+    merge_exact_tile<T, kBetaThreads>(*prob_exact, o, blockIdx.x);
+    return;
+  }
+  // Otherwise the flag is tested after the slot headers have been read (they
+  // are valid memory either way), so the two loads overlap.
+  __shared__ double sh[2 * (kBetaThreads / 64)];
+  constexpr int NG = kBetaThreads / 64;   // slot groups
   __shared__ double fq[2][256];
-  __shared__ double red[4][64][6];
-  __shared__ double gsh[4 * 18];
+  __shared__ double red[NG][64][6];
   const Problem& P = *prob;
   double m, Z, S;
-  global_lse<256>(P, sh, m, Z, S);
+  global_lse<kBetaThreads>(P, sh, m, Z, S);
+  if (flag != 0) return;
   const double s = S / Z;
   const double lam = P.lam;
   const int n_pad = P.n_pad;
@@ -751,14 +831,14 @@ __global__ __launch_bounds__(256) void merge_close_beta_kernel(const Problem* __
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
     const int g = g0 + threadIdx.x;
-    if (g < P.n_slots) {
+    if (threadIdx.x < 256 && g < P.n_slots) {
       fq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
       fq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
     }
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
-      for (int t = sg; t < gn; t += 4) {
+      for (int t = sg; t < gn; t += NG) {
         const acc* pu = partial_u<acc>(P.vec, g0 + t, n_pad);
         const double* pv = partial_v<acc>(P.vec, g0 + t, n_pad);
         const double f = fq[0][t], dq = fq[1][t];
@@ -785,8 +865,11 @@ __global__ __launch_bounds__(256) void merge_close_beta_kernel(const Problem* __
     double be[3], bz[3], xw[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double a0 = ((red[0][a][c] + red[1][a][c]) + red[2][a][c]) + red[3][a][c];
-      const double b0 = ((red[0][a][3 + c] + red[1][a][3 + c]) + red[2][a][3 + c]) + red[3][a][3 + c];
+      double a0 = 0.0, b0 = 0.0;
+      for (int q = 0; q < NG; ++q) {
+        a0 += red[q][a][c];
+        b0 += red[q][a][3 + c];
+      }
       be[c] = -lam / Z * a0;
       bz[c] = b0 / Z;
       xw[c] = P.xw[(size_t)c * n_pad + j];
@@ -808,7 +891,7 @@ __global__ __launch_bounds__(256) void merge_close_beta_kernel(const Problem* __
         G[9 + r0 * 3 + c0] = -2.0 * xw[r0] * bz[c0];
       }
   }
-  // G share of this tile (64 atoms; waves 1..3 contribute zeros).
+  // G share of this tile (64 atoms; the other waves contribute zeros).
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int k = 0; k < 18; ++k) G[k] += __shfl_xor(G[k], off, 64);
@@ -824,23 +907,31 @@ __global__ __launch_bounds__(1024) void merge_close_final_kernel(const Problem* 
                                                                  CloseArgs cs, const double* __restrict__ gtmp,
                                                                  int tiles) {
   constexpr int BS = 1024;
-  if (*cs.flag != 0) return;
+  const int flag = *cs.flag;   // tested once the independent loads below are in flight
   __shared__ double sh[16 * 18];
   __shared__ double gam[18];
   const Problem& P = *prob;
   const int n = P.n, n_pad = P.n_pad;
+  double F[10], qv[4], lv = 0.0;
+  if (threadIdx.x == 0 || threadIdx.x == 64) {
+    for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
+    for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
+    lv = *cs.lamxy;
+  }
   if (threadIdx.x < 18) {
     double g = 0.0;
     for (int t = 0; t < tiles; ++t) g += gtmp[6 * (size_t)n_pad + (size_t)t * 18 + threadIdx.x];
     sh[threadIdx.x] = g;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double G[18], Gs[9], Gz[9];
-    for (int k = 0; k < 18; ++k) G[k] = sh[k];
-    rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G, Gs);
-    rotation_adjoint(cs.Fxy, *cs.lamxy, cs.qxy, G + 9, Gz);
-    for (int k = 0; k < 9; ++k) { gam[k] = Gs[k]; gam[9 + k] = Gz[k]; }
+  if (flag != 0) return;
+  // The two adjoints (for s and for z) are independent: one wave each.
+  if (threadIdx.x == 0 || threadIdx.x == 64) {
+    const int h = threadIdx.x == 0 ? 0 : 9;
+    double G[9], Gm[9];
+    for (int k = 0; k < 9; ++k) G[k] = sh[h + k];
+    rotation_adjoint(F, lv, qv, G, Gm);
+    for (int k = 0; k < 9; ++k) gam[h + k] = Gm[k];
   }
   double m, Z, S;
   global_lse<BS>(P, sh + 32, m, Z, S);   // also orders gam[] before its use below
@@ -975,9 +1066,10 @@ hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int m
 
 template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
-                              hipStream_t st) {
+                              hipStream_t st, const Problem* prob_exact) {
   const int tiles = (n_pad + 63) / 64;
-  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles), dim3(256), 0, st, prob, ca, gtmp);
+  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles), dim3(kBetaThreads), 0, st, prob, ca, gtmp, prob_exact,
+                     outs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(1024), 0, st, prob, outs, ca, gtmp, tiles);
@@ -1005,7 +1097,8 @@ hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) 
                                        const int*, int, const int*, int, double*, hipStream_t);    \
   template hipError_t launch_merge_exact<T>(const Problem*, Outs, int, int, const int*, int,       \
                                             hipStream_t);                                          \
-  template hipError_t launch_merge_close<T>(const Problem*, int, Outs, CloseArgs, double*, hipStream_t);
+  template hipError_t launch_merge_close<T>(const Problem*, int, Outs, CloseArgs, double*, hipStream_t, \
+                                            const Problem*);
 PCV_INST(float)
 PCV_INST(double)
 
