@@ -592,7 +592,7 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
 template <typename T>
 static hipError_t enqueue_exact(pcv_handle* h, hipStream_t st, const void* x, double* sz, void* ds,
                                 void* dz, double* msd, PrepArgs* d_pa) {
-  hipError_t e = launch_prep<T>(d_pa, x, 1, st);
+  hipError_t e = launch_prep<T>(d_pa, x, 1, h->n, st);
   if (e != hipSuccess) return e;
   e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, msd);
   if (e != hipSuccess) return e;
@@ -633,14 +633,14 @@ static hipError_t enqueue_exact_nl(pcv_handle* h, hipStream_t st, const void* x,
                                    bool update) {
   Outs o{ds, dz, sz, nullptr};
   if (update) {
-    hipError_t e = launch_prep<T>(h->d_prep, x, 1, st);
+    hipError_t e = launch_prep<T>(h->d_prep, x, 1, h->n, st);
     if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, h->dfull);
     if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
     if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
     if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
     return e;
   }
-  hipError_t e = launch_prep<T>(h->d_prep_nl, x, 1, st);
+  hipError_t e = launch_prep<T>(h->d_prep_nl, x, 1, h->n, st);
   if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, nullptr, true);
   if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob_nl + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
   return e;
@@ -867,7 +867,7 @@ extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, v
 template <typename T>
 static hipError_t enqueue_props(pcv_handle* h, hipStream_t st, const void* x, int P, const double* q, double* S,
                                 void* dS) {
-  hipError_t e = launch_prep<T>(h->d_prep, x, 1, st);
+  hipError_t e = launch_prep<T>(h->d_prep, x, 1, h->n, st);
   if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
   if (e != hipSuccess) return e;
   PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};

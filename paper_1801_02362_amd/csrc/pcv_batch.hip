@@ -383,7 +383,7 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
 
 template <typename T>
 static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, double* sz, void* ds, void* dz) {
-  hipError_t e = launch_prep<T>(b->d_prep, x, b->W, st);
+  hipError_t e = launch_prep<T>(b->d_prep, x, b->W, *std::max_element(b->n.begin(), b->n.end()), st);
   if (e != hipSuccess) return e;
   if (b->plan.engine == 4)
     e = launch_engine4<T>(b->plan.spw, b->grid, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st);

@@ -163,7 +163,7 @@ template <typename T>
 hipError_t launch_pair_msd(const T* A, const double* ca, const double* Ga, const double* w,
                            int n, int n_pad, int L, double* out, hipStream_t st);
 template <typename T>
-hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, hipStream_t st);
+hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, int max_n, hipStream_t st);
 template <typename T>
 hipError_t launch_prep_close(PrepArgs pa, const void* x, CloseArgs ca, Outs outs, hipStream_t st);
 template <typename T>

@@ -248,16 +248,18 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   g32[3] = g[4];
 }
 
-// One workgroup per problem (the batched path and Algorithm 1).
-template <typename T>
-__global__ __launch_bounds__(1024) void prep_kernel(const PrepArgs* __restrict__ args,
-                                                    const void* __restrict__ x_base) {
-  __shared__ double sh[16 * 5];
+// One workgroup per problem (the batched path and Algorithm 1); BS threads
+// (256 when every structure has at most 1,024 atoms, else 512), each
+// keeping up to 8,192 / BS of its atoms in registers between the passes.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void prep_kernel(const PrepArgs* __restrict__ args,
+                                                  const void* __restrict__ x_base) {
+  __shared__ double sh[(BS / 64) * 5];
   const PrepArgs a = args[blockIdx.x];
   const T* x = (const T*)x_base + 3 * a.x_off;
   double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, 1024, 4>(a, x, sh, Gx, finite, c, g32);
+  centre_frame<T, BS, (BS >= 512 ? 16 : 4)>(a, x, sh, Gx, finite, c, g32);
   if (threadIdx.x == 0) {
     *a.Gx = Gx;
     *a.Gx32 = g32[0];
@@ -903,10 +905,10 @@ __global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Pr
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void merge_close_final_kernel(const Problem* __restrict__ prob, Outs o,
-                                                                 CloseArgs cs, const double* __restrict__ gtmp,
-                                                                 int tiles) {
-  constexpr int BS = 1024;
+__global__ __launch_bounds__(256) void merge_close_final_kernel(const Problem* __restrict__ prob, Outs o,
+                                                                CloseArgs cs, const double* __restrict__ gtmp,
+                                                                int tiles) {
+  constexpr int BS = 256;
   const int flag = *cs.flag;   // tested once the independent loads below are in flight
   __shared__ double sh[16 * 18];
   __shared__ double gam[18];
@@ -977,8 +979,11 @@ hipError_t launch_pair_msd(const T* A, const double* ca, const double* Ga, const
 }
 
 template <typename T>
-hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, hipStream_t st) {
-  hipLaunchKernelGGL((prep_kernel<T>), dim3(n_prob), dim3(1024), 0, st, d_args, x_base);
+hipError_t launch_prep(const PrepArgs* d_args, const void* x_base, int n_prob, int max_n, hipStream_t st) {
+  if (max_n <= 1024)
+    hipLaunchKernelGGL((prep_kernel<T, 256>), dim3(n_prob), dim3(256), 0, st, d_args, x_base);
+  else
+    hipLaunchKernelGGL((prep_kernel<T, 512>), dim3(n_prob), dim3(512), 0, st, d_args, x_base);
   return hipGetLastError();
 }
 
@@ -1072,7 +1077,7 @@ hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseAr
                      outs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(1024), 0, st, prob, outs, ca, gtmp, tiles);
+  hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(256), 0, st, prob, outs, ca, gtmp, tiles);
   return hipGetLastError();
 }
 
@@ -1091,7 +1096,7 @@ hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) 
                                                int, int, hipStream_t);                             \
   template hipError_t launch_pair_msd<T>(const T*, const double*, const double*, const double*,    \
                                          int, int, int, double*, hipStream_t);                     \
-  template hipError_t launch_prep<T>(const PrepArgs*, const void*, int, hipStream_t);              \
+  template hipError_t launch_prep<T>(const PrepArgs*, const void*, int, int, hipStream_t);              \
   template hipError_t launch_prep_close<T>(PrepArgs, const void*, CloseArgs, Outs, hipStream_t);   \
   template hipError_t launch_engine<T>(EngineCfg, int, size_t, const Problem*, const Item*,        \
                                        const int*, int, const int*, int, double*, hipStream_t);    \
