@@ -730,21 +730,21 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
 // has no tangent component), Gamma = d(G:R_xy)/dM_xy and the contribution
 // w_k sum_a Gamma_ac y_k[a].
 //
-// Stage 1 (one workgroup per 64 atoms, 4 slot groups): beta, betaz and the
-// explicit terms of its atoms, and its share of G (18 values, written per
-// workgroup).  Stage 2 (one workgroup): G summed over workgroups in a fixed
-// order, the two rotation adjoints, the outputs.
-// gtmp layout: [0, 3 n_pad) explicit ds, [3 n_pad, 6 n_pad) explicit dz,
-// [6 n_pad, 6 n_pad + 18 * tiles) G shares.
-// 64 atoms x 8 slot groups per workgroup: a tile's slots are spread over
-// eight waves, so each waits for a few round trips only.
-constexpr int kBetaThreads = 512;
+// Stage 1 (one workgroup per 64 atoms and coordinate c, 4 slot groups):
+// beta_c and betaz_c of its atoms and its share of column c of the two 3x3
+// contractions G (6 values).  Stage 2 (one workgroup): G summed over the
+// tiles in a fixed order, the two rotation adjoints, and per atom the
+// explicit terms (R_xy beta, R_xy betaz) plus the rotation terms.
+// gtmp layout: [0, 3 n_pad) beta, [3 n_pad, 6 n_pad) betaz,
+// [6 n_pad, 6 n_pad + 18 * tiles) G shares (entry r * 3 + c of G_s, then of
+// G_z, per tile).
+constexpr int kBetaThreads = 256;
 
-// The exact merge (as merge_exact_kernel) of one tile of 64 atoms, all three
-// coordinates, with the workgroup's BS / 64 slot groups: the reassignment
-// branch of a close-structure step served by the same launch.
+// The exact merge (as merge_exact_kernel) of one tile of 64 atoms and
+// coordinate c: the reassignment branch of a close-structure step served by
+// the same launch.
 template <typename T, int BS>
-__device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile) {
+__device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int c) {
   using acc = typename AccT<T>::type;
   constexpr int NG = BS / 64;
   __shared__ double xsh[2 * NG];
@@ -756,7 +756,7 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile) {
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = tile * 64 + a;
   const int n_pad = P.n_pad;
-  double gs[3] = {0.0, 0.0, 0.0}, gz[3] = {0.0, 0.0, 0.0};
+  double gs = 0.0, gz = 0.0;
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
     const int g = g0 + threadIdx.x;
@@ -767,38 +767,31 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile) {
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
+#pragma unroll 4
       for (int t = sg; t < gn; t += NG) {
-        const acc* pu = partial_u<acc>(P.vec, g0 + t, n_pad);
-        const double* pv = partial_v<acc>(P.vec, g0 + t, n_pad);
-        const double f = xfq[0][t], dq = xfq[1][t];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double u = (double)ldg(pu + (size_t)c * n_pad + j);
-          const double v = ldg(pv + (size_t)c * n_pad + j);
-          gs[c] = fma(f, fma(dq, v, u), gs[c]);
-          gz[c] = fma(f, v, gz[c]);
-        }
+        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double f = xfq[0][t];
+        gs = fma(f, fma(xfq[1][t], v, u), gs);
+        gz = fma(f, v, gz);
       }
     }
   }
-  for (int c = 0; c < 3; ++c) {
-    __syncthreads();
-    xred[0][sg][a] = gs[c];
-    xred[1][sg][a] = gz[c];
-    __syncthreads();
-    if (sg == 0 && j < P.n) {
-      double ts = 0.0, tz = 0.0;
-      for (int q = 0; q < NG; ++q) {
-        ts += xred[0][q][a];
-        tz += xred[1][q][a];
-      }
-      const double wj = P.w[j];
-      const size_t at = 3 * ((size_t)P.out_off + j) + c;
-      if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * ts / Z);
-      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * tz / Z));
+  xred[0][sg][a] = gs;
+  xred[1][sg][a] = gz;
+  __syncthreads();
+  if (sg == 0 && j < P.n) {
+    double ts = 0.0, tz = 0.0;
+    for (int q = 0; q < NG; ++q) {
+      ts += xred[0][q][a];
+      tz += xred[1][q][a];
     }
+    const double wj = P.w[j];
+    const size_t at = 3 * ((size_t)P.out_off + j) + c;
+    if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * ts / Z);
+    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * tz / Z));
   }
-  if (tile == 0 && threadIdx.x == 0) {
+  if (tile == 0 && c == 0 && threadIdx.x == 0) {
     o.sz[2 * P.out_idx + 0] = s;
     o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
   }
@@ -806,101 +799,83 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile) {
 
 template <typename T>
 __global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
-                                                               double* __restrict__ gtmp,
-                                                               const Problem* __restrict__ prob_exact, Outs o) {
+                                                                       double* __restrict__ gtmp,
+                                                                       const Problem* __restrict__ prob_exact, Outs o) {
   using acc = typename AccT<T>::type;  // partial storage type
+  constexpr int NG = kBetaThreads / 64;   // slot groups
+  const int c = blockIdx.y;
   const int flag = __builtin_amdgcn_readfirstlane(*cs.flag);
   if (flag == 1 && prob_exact != nullptr) {
-    merge_exact_tile<T, kBetaThreads>(*prob_exact, o, blockIdx.x);
+    merge_exact_tile<T, kBetaThreads>(*prob_exact, o, blockIdx.x, c);
     return;
   }
-  // Otherwise the flag is tested after the slot headers have been read (they
-  // are valid memory either way), so the two loads overlap.
-  __shared__ double sh[2 * (kBetaThreads / 64)];
-  constexpr int NG = kBetaThreads / 64;   // slot groups
+  if (flag != 0) return;
+  __shared__ double sh[2 * NG];
   __shared__ double fq[2][256];
-  __shared__ double red[NG][64][6];
+  __shared__ double red[2][NG][64];
   const Problem& P = *prob;
   double m, Z, S;
   global_lse<kBetaThreads>(P, sh, m, Z, S);
-  if (flag != 0) return;
   const double s = S / Z;
   const double lam = P.lam;
   const int n_pad = P.n_pad;
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + a;
-  double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
+  double su = 0.0, sv = 0.0;
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
     const int g = g0 + threadIdx.x;
-    if (threadIdx.x < 256 && g < P.n_slots) {
+    if (g < P.n_slots) {
       fq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
       fq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
     }
     __syncthreads();
     const int gn = min(256, P.n_slots - g0);
     if (j < n_pad) {
+#pragma unroll 4
       for (int t = sg; t < gn; t += NG) {
-        const acc* pu = partial_u<acc>(P.vec, g0 + t, n_pad);
-        const double* pv = partial_v<acc>(P.vec, g0 + t, n_pad);
-        const double f = fq[0][t], dq = fq[1][t];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double u = (double)ldg(pu + (size_t)c * n_pad + j);
-          const double v = ldg(pv + (size_t)c * n_pad + j);
-          su[c] = fma(f, fma(dq, v, u), su[c]);
-          sv[c] = fma(f, v, sv[c]);
-        }
+        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double f = fq[0][t];
+        su = fma(f, fma(fq[1][t], v, u), su);
+        sv = fma(f, v, sv);
       }
     }
   }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    red[sg][a][c] = su[c];
-    red[sg][a][3 + c] = sv[c];
-  }
+  red[0][sg][a] = su;
+  red[1][sg][a] = sv;
   __syncthreads();
-  double G[18];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) G[k] = 0.0;
-  if (sg == 0 && j < P.n) {
-    double be[3], bz[3], xw[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double a0 = 0.0, b0 = 0.0;
-      for (int q = 0; q < NG; ++q) {
-        a0 += red[q][a][c];
-        b0 += red[q][a][3 + c];
-      }
-      be[c] = -lam / Z * a0;
-      bz[c] = b0 / Z;
-      xw[c] = P.xw[(size_t)c * n_pad + j];
+  if (sg != 0) return;
+  // Wave 0: beta_c, betaz_c of the tile's atoms and column c of its G share.
+  double G[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < n_pad) {
+    double a0 = 0.0, b0 = 0.0;
+    for (int q = 0; q < NG; ++q) {
+      a0 += red[0][q][a];
+      b0 += red[1][q][a];
     }
-    const double* Rx = cs.Rxy;
-    const double wj = P.w[j];
+    const double be = -lam / Z * a0, bz = b0 / Z;
+    gtmp[(size_t)c * n_pad + j] = be;
+    gtmp[3 * (size_t)n_pad + (size_t)c * n_pad + j] = bz;
+    if (j < P.n) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double rb = Rx[d * 3 + 0] * be[0] + Rx[d * 3 + 1] * be[1] + Rx[d * 3 + 2] * be[2];
-      const double rz = Rx[d * 3 + 0] * bz[0] + Rx[d * 3 + 1] * bz[1] + Rx[d * 3 + 2] * bz[2];
-      gtmp[(size_t)d * n_pad + j] = -2.0 * wj * rb;
-      gtmp[3 * (size_t)n_pad + (size_t)d * n_pad + j] = 2.0 * (xw[d] - wj * rz);
-    }
-#pragma unroll
-    for (int r0 = 0; r0 < 3; ++r0)
-#pragma unroll
-      for (int c0 = 0; c0 < 3; ++c0) {
-        G[r0 * 3 + c0] = -2.0 * xw[r0] * be[c0];
-        G[9 + r0 * 3 + c0] = -2.0 * xw[r0] * bz[c0];
+      for (int r0 = 0; r0 < 3; ++r0) {
+        const double xw = P.xw[(size_t)r0 * n_pad + j];
+        G[r0] = -2.0 * xw * be;
+        G[3 + r0] = -2.0 * xw * bz;
       }
+    }
   }
-  // G share of this tile (64 atoms; the other waves contribute zeros).
-  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int k = 0; k < 18; ++k) G[k] += __shfl_xor(G[k], off, 64);
-  if (threadIdx.x == 0) {
+  for (int k = 0; k < 6; ++k)
+    for (int off = 32; off > 0; off >>= 1) G[k] += __shfl_xor(G[k], off, 64);
+  if (a == 0) {
     double* gs = gtmp + 6 * (size_t)n_pad + (size_t)blockIdx.x * 18;
 #pragma unroll
-    for (int k = 0; k < 18; ++k) gs[k] = G[k];
+    for (int r0 = 0; r0 < 3; ++r0) {
+      gs[r0 * 3 + c] = G[r0];
+      gs[9 + r0 * 3 + c] = G[3 + r0];
+    }
   }
 }
 
@@ -939,17 +914,26 @@ __global__ __launch_bounds__(256) void merge_close_final_kernel(const Problem* _
   global_lse<BS>(P, sh + 32, m, Z, S);   // also orders gam[] before its use below
   T* ds = (T*)o.ds;
   T* dz = (T*)o.dz;
+  const double* Rx = cs.Rxy;
   for (int j = threadIdx.x; j < n; j += BS) {
-    double y[3];
+    double y[3], be[3], bz[3], xw[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) y[d] = cs.y64[(size_t)d * n_pad + j];
+    for (int d = 0; d < 3; ++d) {
+      y[d] = cs.y64[(size_t)d * n_pad + j];
+      be[d] = gtmp[(size_t)d * n_pad + j];
+      bz[d] = gtmp[3 * (size_t)n_pad + (size_t)d * n_pad + j];
+      xw[d] = P.xw[(size_t)d * n_pad + j];
+    }
     const double wj = P.w[j];
 #pragma unroll
     for (int c0 = 0; c0 < 3; ++c0) {
+      // explicit Eq. 6 terms -2 w R_xy beta and 2 (w x - w R_xy betaz)
+      const double rb = Rx[c0 * 3 + 0] * be[0] + Rx[c0 * 3 + 1] * be[1] + Rx[c0 * 3 + 2] * be[2];
+      const double rzb = Rx[c0 * 3 + 0] * bz[0] + Rx[c0 * 3 + 1] * bz[1] + Rx[c0 * 3 + 2] * bz[2];
       const double rs = wj * (gam[0 * 3 + c0] * y[0] + gam[1 * 3 + c0] * y[1] + gam[2 * 3 + c0] * y[2]);
       const double rz = wj * (gam[9 + 0 * 3 + c0] * y[0] + gam[9 + 1 * 3 + c0] * y[1] + gam[9 + 2 * 3 + c0] * y[2]);
-      if (ds) ds[3 * j + c0] = (T)(gtmp[(size_t)c0 * n_pad + j] + rs);
-      if (dz) dz[3 * j + c0] = (T)(gtmp[3 * (size_t)n_pad + (size_t)c0 * n_pad + j] + rz);
+      if (ds) ds[3 * j + c0] = (T)(-2.0 * wj * rb + rs);
+      if (dz) dz[3 * j + c0] = (T)(2.0 * (xw[c0] - wj * rzb) + rz);
     }
   }
   if (threadIdx.x == 0) {
@@ -1073,8 +1057,8 @@ template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
                               hipStream_t st, const Problem* prob_exact) {
   const int tiles = (n_pad + 63) / 64;
-  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles), dim3(kBetaThreads), 0, st, prob, ca, gtmp, prob_exact,
-                     outs);
+  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles, 3), dim3(kBetaThreads), 0, st, prob, ca, gtmp,
+                     prob_exact, outs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(256), 0, st, prob, outs, ca, gtmp, tiles);
