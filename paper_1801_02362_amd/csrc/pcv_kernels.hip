@@ -175,10 +175,12 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
 // ------------------------------------------------------------ frame prep
 // CACHE: atoms per thread whose x and w the first pass keeps in registers
 // for the second (one global round trip fewer); atoms past CACHE * BS are
-// loaded again.  The sums are taken in the same order either way.
+// loaded again.  The sums are taken in the same order either way.  With y
+// (a centred structure [3][n_pad], FP64) the second pass also forms the
+// correlation My = sum_j y_j (w_j x_c,j)^T (row-major, 9 values).
 template <typename T, int BS, int CACHE = 0>
 __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& Gx, bool& finite,
-                             double c[3], double g32[4]) {
+                             double c[3], double g32[4], const double* y = nullptr, double* My = nullptr) {
   constexpr int KC = CACHE > 0 ? CACHE : 1;
   T xk[KC][3];
   double wk[KC];
@@ -207,20 +209,29 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   block_sum<4, BS>(v, sh);
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
-  // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x rounded to T.
-  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x
+  // rounded to T; g[5..13]: the correlation with y.
+  double g[14] = {0.0};
   auto acc2 = [&](int j, double wj, const T* xv) {
     const double iw = wj > 0.0 ? 1.0 / wj : 0.0;
+    double xwv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double xd = (double)xv[d] - c[d];
-      const double xwv = wj * xd;
-      a.xw[(size_t)d * a.n_pad + j] = xwv;
-      if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = (float)xwv;
+      xwv[d] = wj * xd;
+      a.xw[(size_t)d * a.n_pad + j] = xwv[d];
+      if (a.xw32) a.xw32[(size_t)d * a.n_x + j] = (float)xwv[d];
       g[0] = fma(wj * xd, xd, g[0]);
-      const double r = (double)(T)xwv;
+      const double r = (double)(T)xwv[d];
       g[1] = fma(r * r, iw, g[1]);
       g[2 + d] += r;
+    }
+    if (y) {
+      const double yv[3] = {y[j], y[(size_t)a.n_pad + j], y[2 * (size_t)a.n_pad + j]};
+#pragma unroll
+      for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+        for (int c0 = 0; c0 < 3; ++c0) g[5 + r0 * 3 + c0] = fma(yv[r0], xwv[c0], g[5 + r0 * 3 + c0]);
     }
   };
   auto pad = [&](int j) {
@@ -240,7 +251,13 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
     if (j < a.n) acc2(j, a.w[j], x + 3 * j);
     else pad(j);
   }
-  block_sum<5, BS>(g, sh);
+  if (y) {
+    block_sum<14, BS>(g, sh);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) My[k] = g[5 + k];
+  } else {
+    block_sum<5, BS>(g, sh);
+  }
   Gx = g[0];
   g32[0] = g[1] - (g[2] * g[2] + g[3] * g[3] + g[4] * g[4]);
   g32[1] = g[2];
@@ -285,31 +302,34 @@ template <typename T>
 __global__ __launch_bounds__(256) void prep_close_kernel(PrepArgs a, const T* __restrict__ x,
                                                          CloseArgs cs, Outs nan_outs) {
   constexpr int BS = 256;
-  __shared__ double sh[16 * 9];
+  __shared__ double sh[16 * 14];
   __shared__ int s_flag;
   double Gx, c[3], g32[4];
   bool finite;
-  centre_frame<T, BS>(a, x, sh, Gx, finite, c, g32);
-  const int init = *cs.init;
+  // With a close structure, its correlation with x is formed in the same
+  // pass that writes the centred x.
+  const int init = __builtin_amdgcn_readfirstlane(*cs.init);
+  // Thread 0's scalars (G_y, the forced flag, the counters) are fetched now,
+  // so their latency hides behind the frame pass; no other kernel touches
+  // them while this one runs.
+  double gy0 = 0.0;
+  int force0 = 0;
+  long long cnt[4] = {0, 0, 0, 0};   // frames, recomputes, expensive, approx
+  if (threadIdx.x == 0) {
+    gy0 = *cs.Gy;
+    force0 = *cs.force;
+    cnt[0] = cs.counters[CNT_FRAMES];
+    cnt[1] = cs.counters[CNT_RECOMPUTES];
+    cnt[2] = cs.counters[CNT_EXPENSIVE];
+    cnt[3] = cs.counters[CNT_APPROX];
+  }
+  double M[9];
+  centre_frame<T, BS>(a, x, sh, Gx, finite, c, g32, init ? cs.y64 : nullptr, M);
   double Dxy = NAN;
   if (init) {
-    double M[9] = {0.0};
-    for (int j = threadIdx.x; j < a.n; j += BS) {
-      double yv[3], xv[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        yv[d] = cs.y64[(size_t)d * a.n_pad + j];
-        xv[d] = a.xw[(size_t)d * a.n_pad + j];
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = fma(yv[r], xv[cc], M[r * 3 + cc]);
-    }
-    block_sum<9, BS>(M, sh);
     if (threadIdx.x == 0) {
       double F[10], lam, q[4], R[9];
-      const double G = Gx + *cs.Gy;
+      const double G = Gx + gy0;
       top_eigenpair(M, 0.5 * G, F, lam, q);
       Dxy = clamp0(G - 2.0 * lam);
       quat_to_rot(q, R);
@@ -322,7 +342,7 @@ __global__ __launch_bounds__(256) void prep_close_kernel(PrepArgs a, const T* __
   if (threadIdx.x == 0) {
     int flag;
     if (!finite) flag = -1;
-    else if (!init || *cs.force || Dxy > cs.eps) flag = 1;
+    else if (!init || force0 || Dxy > cs.eps) flag = 1;
     else flag = 0;
     *cs.Dxy = Dxy;
     *cs.flag = flag;
@@ -336,16 +356,17 @@ __global__ __launch_bounds__(256) void prep_close_kernel(PrepArgs a, const T* __
     if (nan_outs.rec) *nan_outs.rec = flag;
     s_flag = flag;
     if (flag >= 0) {
-      cs.counters[CNT_FRAMES] += 1;
-      if (init) cs.counters[CNT_EXPENSIVE] += 1;
+      cs.counters[CNT_FRAMES] = cnt[0] + 1;
+      long long expensive = cnt[2] + (init ? 1 : 0);
       if (flag == 1) {
-        cs.counters[CNT_RECOMPUTES] += 1;
-        cs.counters[CNT_EXPENSIVE] += cs.L;
+        cs.counters[CNT_RECOMPUTES] = cnt[1] + 1;
+        expensive += cs.L;
         *cs.Gy = Gx;
         *cs.init = 1;
       } else {
-        cs.counters[CNT_APPROX] += 1;
+        cs.counters[CNT_APPROX] = cnt[3] + 1;
       }
+      cs.counters[CNT_EXPENSIVE] = expensive;
     }
   }
   __syncthreads();
