@@ -108,9 +108,9 @@ def bench_exact(args):
     import workloads as wl
 
     n, L = args.atoms, args.landmarks
-    log(f"[bench] generating cfg2 workload: {n} atoms x {L} landmarks")
-    sysm, base = wl.cfg2(n_atoms=n, n_landmarks=L)
-    frames = wl.cfg2_frames(base, args.warmup + args.steps)
+    log(f"[bench] generating rigid_5000x10000 workload: {n} atoms x {L} landmarks")
+    sysm, base = wl.rigid_5000x10000(n_atoms=n, n_landmarks=L)
+    frames = wl.rigid_frames(base, args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     lm = torch.as_tensor(sysm.landmarks, device=dev)
     cv = pcv.PathCV(lm, None, use_graph=True)
@@ -180,7 +180,7 @@ def bench_close(args):
     import torch
     import paper_1801_02362_amd as pcv
     import workloads as wl
-    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    sysm, frames = wl.path_300x500(args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, eps=0.01)
     x_all = torch.as_tensor(frames, device=dev)
@@ -226,7 +226,7 @@ def bench_mtd(args):
     import torch
     import paper_1801_02362_amd as pcv
     import workloads as wl
-    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    sysm, frames = wl.path_300x500(args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     L = sysm.n_landmarks
     cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, eps=0.01)
@@ -365,7 +365,7 @@ def bench_f2(args):
     import torch
     import paper_1801_02362_amd as pcv
     import workloads as wl
-    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    sysm, frames = wl.path_300x500(args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     rng = np.random.default_rng(11)
     wa = rng.uniform(0.5, 1.5, sysm.n_atoms)
@@ -394,7 +394,7 @@ def bench_props(args):
     import paper_1801_02362_amd as pcv
     import workloads as wl
     P = 8
-    sysm, frames = wl.cfg1(args.warmup + args.steps)
+    sysm, frames = wl.path_300x500(args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None)
     L = sysm.n_landmarks
@@ -419,7 +419,7 @@ def bench_batch(args):
     import torch
     import paper_1801_02362_amd as pcv
     import workloads as wl
-    ws = wl.cfg3(n_walkers=64, n_frames=1)
+    ws = wl.walkers(n_walkers=64, n_frames=1)
     dev = torch.device("cuda", 0)
     lams = []
     for w in ws:
@@ -464,7 +464,7 @@ def bench_surrogate(args):
     import workloads as wl
     dev = torch.device("cuda", 0)
     K = args.test_frames
-    sysm, walk = wl.cfg1(K)
+    sysm, walk = wl.path_300x500(K)
     n = sysm.n_atoms
     lm = torch.as_tensor(sysm.landmarks, device=dev)
     probe = pcv.PathCV(lm, None, eps=args.eps)
@@ -472,7 +472,7 @@ def bench_surrogate(args):
     probe.close()
     t_start = time.perf_counter()
     log(f"[surrogate] generating {args.train_walks} x {args.train_steps} training frames")
-    frames = wl.cfg4_training_walks(args.train_walks, args.train_steps, sysm)
+    frames = wl.surrogate_training_walks(args.train_walks, args.train_steps, sysm)
     frames = frames[wl.minibatch_order(frames.shape[0], 0)]
     fd = torch.as_tensor(frames, device=dev)
     del frames

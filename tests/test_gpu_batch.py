@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _walkers(k, atom_range, landmark_range, stream):
-    ws = wl.cfg3(n_walkers=k, n_frames=2, atom_range=atom_range, landmark_range=landmark_range, stream=stream)
+    ws = wl.walkers(n_walkers=k, n_frames=2, atom_range=atom_range, landmark_range=landmark_range, stream=stream)
     lams = [landmark_lambda(w.system.landmarks) for w in ws]
     return ws, lams
 
@@ -64,7 +64,7 @@ def test_full_64_walker_batch_sampled_walkers():
     import paper_1801_02362_amd as pcv
     import torch
     from gpu_util import TOL32, check_cv, dev, host, say
-    ws = wl.cfg3(n_walkers=64, n_frames=1)
+    ws = wl.walkers(n_walkers=64, n_frames=1)
     lams = [landmark_lambda(w.system.landmarks) for w in ws]
     b = pcv.BatchPathCV([dev(w.system.landmarks, torch.float32) for w in ws], lams)
     say(f"[batch] full 64 walkers, plan {b.plan}")

@@ -48,29 +48,29 @@ def _walk(torch, lm, frames, lam, eps, *, dtype, tol, name, every=1):
     return n_re
 
 
-def test_cfg1_walk_fp32():
+def test_path_300x500_walk_fp32():
     import torch
     from gpu_util import TOL32
-    sysm, frames = wl.cfg1(1500)
+    sysm, frames = wl.path_300x500(1500)
     lam = landmark_lambda(sysm.landmarks)
-    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float32, tol=TOL32, name="cfg1",
+    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float32, tol=TOL32, name="path_300x500",
                  every=5)
     assert n_re >= 2
 
 
-def test_cfg0_walk_fp64():
+def test_path_22x20_walk_fp64():
     import torch
     from gpu_util import TOL64
-    sysm, frames = wl.cfg0(1000)
+    sysm, frames = wl.path_22x20(1000)
     lam = landmark_lambda(sysm.landmarks)
-    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float64, tol=TOL64, name="cfg0")
+    n_re = _walk(torch, sysm.landmarks, frames, lam, 0.01, dtype=torch.float64, tol=TOL64, name="path_22x20")
     assert n_re >= 2
 
 
 def test_threshold_extremes():
     import torch
     from gpu_util import TOL32
-    sysm, frames = wl.cfg1(40)
+    sysm, frames = wl.path_300x500(40)
     lam = landmark_lambda(sysm.landmarks)
     assert _walk(torch, sysm.landmarks, frames, lam, -1.0, dtype=torch.float32, tol=TOL32, name="eps<0") == 40
     assert _walk(torch, sysm.landmarks, frames, lam, float("inf"), dtype=torch.float32, tol=TOL32,
@@ -81,7 +81,7 @@ def test_forced_reassignment_and_nonfinite_keep_state():
     import paper_1801_02362_amd as pcv
     import torch
     from gpu_util import dev, host
-    sysm, frames = wl.cfg1(30)
+    sysm, frames = wl.path_300x500(30)
     lam = landmark_lambda(sysm.landmarks)
     cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), lam, eps=0.01)
     x = torch.empty(300, 3, dtype=torch.float32, device="cuda")

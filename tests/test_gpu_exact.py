@@ -34,38 +34,38 @@ def _run_exact(torch, lm, frames, lam, *, dtype, tol, name, q=None, w=None, plan
     cv.close()
 
 
-def test_cfg0_fp64(torch):
+def test_path_22x20_fp64(torch):
     from gpu_util import TOL64
-    sysm, frames = wl.cfg0(1000)
+    sysm, frames = wl.path_22x20(1000)
     lam = landmark_lambda(sysm.landmarks)
-    _run_exact(torch, sysm.landmarks, frames[::50], lam, dtype=torch.float64, tol=TOL64, name="cfg0")
+    _run_exact(torch, sysm.landmarks, frames[::50], lam, dtype=torch.float64, tol=TOL64, name="path_22x20")
 
 
-def test_cfg2_full_size_in_the_bench_configuration(torch):
+def test_rigid_5000x10000_full_size_in_the_bench_configuration(torch):
     """5,000 atoms x 10,000 landmarks (600 MB), the plan the bench times
     (engine 3, one item per CU): every D_i, s, z and both gradients of one
     frame against the oracle."""
     import paper_1801_02362_amd as pcv
     from gpu_util import TOL32, check_cv, dev, host, say
-    sysm, base = wl.cfg2(n_atoms=5000, n_landmarks=10000)
-    f = wl.cfg2_frames(base, 1)[0]
+    sysm, base = wl.rigid_5000x10000(n_atoms=5000, n_landmarks=10000)
+    f = wl.rigid_frames(base, 1)[0]
     cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), None)
-    say(f"[exact] cfg2 full size: plan={cv.plan} lambda={cv.lam:.4f}")
+    say(f"[exact] rigid_5000x10000 full size: plan={cv.plan} lambda={cv.lam:.4f}")
     assert cv.plan["engine"] == 3 and cv.plan["items"] == cv.plan["grid"]
     o = cv.eval(dev(f, torch.float32), msd=True)
     got = host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"])
     cv.check()
     cv.close()
     ref = path_cv(f.astype(np.float64), sysm.landmarks.astype(np.float64), cv.lam)
-    check_cv("cfg2_full", TOL32, *got, ref)
+    check_cv("rigid_full", TOL32, *got, ref)
 
 
-def test_cfg1_fp32_near_and_far_frames(torch):
+def test_path_300x500_fp32_near_and_far_frames(torch):
     from gpu_util import TOL32
-    sysm, frames = wl.cfg1(100_000)
+    sysm, frames = wl.path_300x500(100_000)
     lam = landmark_lambda(sysm.landmarks)
     pick = [0, 1, 100, 1000, 5000, 20000, 50000, 99999]
-    _run_exact(torch, sysm.landmarks, frames[pick], lam, dtype=torch.float32, tol=TOL32, name="cfg1")
+    _run_exact(torch, sysm.landmarks, frames[pick], lam, dtype=torch.float32, tol=TOL32, name="path_300x500")
 
 
 @pytest.mark.parametrize("n,L,seed", [(1, 3, 1), (2, 4, 2), (3, 1, 3), (5, 2, 4), (17, 37, 5), (63, 64, 6),
@@ -123,7 +123,7 @@ def _plans(n, wg_apt, e2):
                                         [(3, 4, 2), (3, 8, 4), (3, 16, 8), (2, 40, 16)]))
 def test_every_tiling_matches(torch, plan):
     from gpu_util import TOL32
-    sysm, frames = wl.cfg1(3000)
+    sysm, frames = wl.path_300x500(3000)
     lam = landmark_lambda(sysm.landmarks)
     _run_exact(torch, sysm.landmarks, frames[[0, 2999]], lam, dtype=torch.float32, tol=TOL32,
                name="tiling", plan=plan)
@@ -216,7 +216,7 @@ def test_engine4_plan_reports_and_rejects(torch):
 def test_item_counts_and_graph_replay_are_bitwise_stable(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev, host
-    sysm, frames = wl.cfg1(50)
+    sysm, frames = wl.path_300x500(50)
     lam = landmark_lambda(sysm.landmarks)
     res = []
     for use_graph in (False, True):
@@ -233,7 +233,7 @@ def test_item_counts_and_graph_replay_are_bitwise_stable(torch):
 def test_path_lambda_matches_oracle(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev
-    sysm, _ = wl.cfg1(1)
+    sysm, _ = wl.path_300x500(1)
     cv = pcv.PathCV(dev(sysm.landmarks, torch.float32))
     ref = landmark_lambda(sysm.landmarks)
     assert abs(cv.lam - ref) <= 1e-9 * ref
@@ -243,7 +243,7 @@ def test_path_lambda_matches_oracle(torch):
 def test_nonfinite_input_is_reported(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev, host
-    sysm, frames = wl.cfg0(5)
+    sysm, frames = wl.path_22x20(5)
     cv = pcv.PathCV(dev(sysm.landmarks, torch.float64), 500.0)
     x = dev(frames[1], torch.float64)
     x[3, 1] = float("nan")
@@ -259,7 +259,7 @@ def test_nonfinite_input_is_reported(torch):
 def test_argument_errors(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev
-    sysm, _ = wl.cfg0(1)
+    sysm, _ = wl.path_22x20(1)
     with pytest.raises(pcv.PcvError) as ei:
         pcv.PathCV(dev(np.zeros((2, 9000, 3)), torch.float32), 1.0)
     assert ei.value.status == -3

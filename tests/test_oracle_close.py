@@ -11,7 +11,7 @@ from oracle.path import landmark_lambda, path_cv
 
 @pytest.fixture(scope="module")
 def small():
-    sysm, frames = wl.cfg0(300)
+    sysm, frames = wl.path_22x20(300)
     lam = landmark_lambda(sysm.landmarks)
     return sysm, frames, lam
 
@@ -125,7 +125,7 @@ def test_approximate_gradient_matches_finite_differences(weights):
 def test_distance_correlation_along_walk():
     """The approximate and exact distances are almost perfectly correlated
     over a trajectory (Section 6.1)."""
-    sysm, frames = wl.cfg1(1500)
+    sysm, frames = wl.path_300x500(1500)
     A = sysm.landmarks
     lam = landmark_lambda(A[:60])
     cs = CloseStructure(A[:60], lam, 0.01)

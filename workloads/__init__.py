@@ -9,14 +9,16 @@ The paper's own molecules (a 24-atom cyclooctane with 521 references and the
 304-atom Trp-cage with 2120 references, Section 5) are not available; the
 workloads below are path-shaped stand-ins of similar size:
 
-* ``cfg0``: 22 atoms, 20 landmarks on a 2-waypoint path, FP64.
-* ``cfg1``: 300 atoms, 500 landmarks through 5 random waypoints, FP32, a
+* ``path_22x20``: 22 atoms, 20 landmarks on a 2-waypoint path, FP64.
+* ``path_300x500``: 300 atoms, 500 landmarks through 5 random waypoints, FP32, a
   100,000-frame Gaussian random walk (the close-structure workload).
-* ``cfg2``: 5,000 atoms, 10,000 landmarks = 600 MB of FP32 coordinates,
+* ``rigid_5000x10000``: 5,000 atoms, 10,000 landmarks = 600 MB of FP32 coordinates,
   a fresh noisy copy of the base conformation every frame (bandwidth case).
-* ``cfg3``: 64 independent walkers with uniform random atom counts in
+* ``walkers``: 64 independent walkers with uniform random atom counts in
   [50, 2000] and landmark counts in [200, 5000].
-* ``cfg4``: the cfg1 system, with independent training walks.
+* ``surrogate_training_walks``: independent walks on the path_300x500 system.
+* ``nl_path``: 304 atoms, 2,120 references through 8 waypoints, a walk that
+  slides along the path (neighbour-list workload).
 
 Every landmark is a noisy point on a piecewise-linear path between random
 conformations (coordinates N(0, 0.3 nm)), then rotated by a Haar-random
@@ -30,19 +32,23 @@ import numpy as np
 from scipy.spatial.transform import Rotation
 
 ROOT_SEED = 20180107
-N_CONFIGS = 6
+N_WORKLOADS = 6
 
 __all__ = [
-    "ROOT_SEED", "PathSystem", "Walker", "config_rng", "path_system",
-    "random_walk", "cfg0", "cfg1", "cfg2", "cfg2_frames", "cfg3",
-    "cfg4_training_walks", "nl_path", "small_path", "rigid_copy", "mlp_sizes", "mlp_init", "mlp_unflatten",
+    "ROOT_SEED", "PathSystem", "Walker", "workload_rng", "path_system",
+    "random_walk", "path_22x20", "path_300x500", "rigid_5000x10000", "rigid_frames", "walkers",
+    "surrogate_training_walks", "nl_path", "small_path", "rigid_copy", "mlp_sizes", "mlp_init", "mlp_unflatten",
     "minibatch_order",
 ]
 
 
-def config_rng(k: int, stream: int = 0) -> np.random.Generator:
-    """Independent generator for config ``k`` and sub-stream ``stream``."""
-    ss = np.random.SeedSequence(ROOT_SEED).spawn(N_CONFIGS)[k]
+# Seed families of the workloads (one SeedSequence child each).
+W_PATH_22x20, W_PATH_300x500, W_RIGID, W_WALKERS, W_SURROGATE, W_NL = range(N_WORKLOADS)
+
+
+def workload_rng(k: int, stream: int = 0) -> np.random.Generator:
+    """Independent generator for workload family ``k`` and sub-stream ``stream``."""
+    ss = np.random.SeedSequence(ROOT_SEED).spawn(N_WORKLOADS)[k]
     return np.random.default_rng(ss.spawn(stream + 1)[stream])
 
 
@@ -102,26 +108,26 @@ def random_walk(start: np.ndarray, n_frames: int, *, rng: np.random.Generator,
     return np.ascontiguousarray(walk.astype(dtype))
 
 
-def cfg0(n_frames: int = 1000) -> tuple[PathSystem, np.ndarray]:
+def path_22x20(n_frames: int = 1000) -> tuple[PathSystem, np.ndarray]:
     """22 atoms, 20 landmarks on a 2-waypoint path, FP64, random-walk frames."""
-    sysm = path_system(22, 20, 2, rng=config_rng(0, 0), dtype=np.float64, name="cfg0")
-    frames = random_walk(sysm.waypoints[0], n_frames, rng=config_rng(0, 1),
+    sysm = path_system(22, 20, 2, rng=workload_rng(W_PATH_22x20, 0), dtype=np.float64, name="path_22x20")
+    frames = random_walk(sysm.waypoints[0], n_frames, rng=workload_rng(W_PATH_22x20, 1),
                          dtype=np.float64)
     return sysm, frames
 
 
-def cfg1(n_frames: int = 100_000) -> tuple[PathSystem, np.ndarray]:
+def path_300x500(n_frames: int = 100_000) -> tuple[PathSystem, np.ndarray]:
     """300 atoms, 500 landmarks through 5 waypoints, FP32, random-walk frames."""
-    sysm = path_system(300, 500, 5, rng=config_rng(1, 0), dtype=np.float32, name="cfg1")
-    frames = random_walk(sysm.waypoints[0], n_frames, rng=config_rng(1, 1))
+    sysm = path_system(300, 500, 5, rng=workload_rng(W_PATH_300x500, 0), dtype=np.float32, name="path_300x500")
+    frames = random_walk(sysm.waypoints[0], n_frames, rng=workload_rng(W_PATH_300x500, 1))
     return sysm, frames
 
 
-def cfg2(n_atoms: int = 5000, n_landmarks: int = 10_000) -> tuple[PathSystem, np.ndarray]:
+def rigid_5000x10000(n_atoms: int = 5000, n_landmarks: int = 10_000) -> tuple[PathSystem, np.ndarray]:
     """Bandwidth workload: landmarks are Haar-rotated, shifted copies of one
     base conformation (N(0, 0.3)) with N(0, 0.05) noise.  Returns the system
     and the base conformation that frames are drawn around."""
-    rng = config_rng(2, 0)
+    rng = workload_rng(W_RIGID, 0)
     base = rng.normal(0.0, 0.3, size=(n_atoms, 3))
     lm = np.empty((n_landmarks, n_atoms, 3), dtype=np.float32)
     chunk = 1000
@@ -132,13 +138,13 @@ def cfg2(n_atoms: int = 5000, n_landmarks: int = 10_000) -> tuple[PathSystem, np
         rot = _haar(rng, k)
         shift = rng.uniform(-1.0, 1.0, size=(k, 1, 3))
         lm[i0:i1] = (np.einsum("lab,ljb->lja", rot, noisy) + shift).astype(np.float32)
-    sysm = PathSystem(n_atoms, n_landmarks, lm, base[None], np.float32, "cfg2")
+    sysm = PathSystem(n_atoms, n_landmarks, lm, base[None], np.float32, "rigid_5000x10000")
     return sysm, base
 
 
-def cfg2_frames(base: np.ndarray, n_frames: int, seed_stream: int = 1) -> np.ndarray:
+def rigid_frames(base: np.ndarray, n_frames: int, seed_stream: int = 1) -> np.ndarray:
     """Fresh ``base + N(0, 0.05)`` frame per step, FP32 ``[F][n][3]``."""
-    rng = config_rng(2, seed_stream)
+    rng = workload_rng(W_RIGID, seed_stream)
     fr = base[None] + rng.normal(0.0, 0.05, size=(n_frames,) + base.shape)
     return np.ascontiguousarray(fr.astype(np.float32))
 
@@ -149,18 +155,18 @@ class Walker:
     frames: np.ndarray  # [F][n][3] FP32
 
 
-def cfg3(n_walkers: int = 64, n_frames: int = 4, *, atom_range=(50, 2000),
-         landmark_range=(200, 5000), stream: int = 0) -> list[Walker]:
+def walkers(n_walkers: int = 64, n_frames: int = 4, *, atom_range=(50, 2000),
+            landmark_range=(200, 5000), stream: int = 0) -> list[Walker]:
     """Independent walkers of uneven size, each a 2-waypoint path with its own
     random-walk frames."""
-    rng = config_rng(3, stream)
+    rng = workload_rng(W_WALKERS, stream)
     n_w = rng.integers(atom_range[0], atom_range[1] + 1, size=n_walkers)
     l_w = rng.integers(landmark_range[0], landmark_range[1] + 1, size=n_walkers)
     out = []
     for w in range(n_walkers):
         sub = np.random.default_rng(rng.integers(0, 2**63 - 1))
         s = path_system(int(n_w[w]), int(l_w[w]), 2, rng=sub, dtype=np.float32,
-                        name=f"cfg3.w{w}")
+                        name=f"walkers.w{w}")
         fr = random_walk(s.waypoints[0], n_frames, rng=sub)
         out.append(Walker(s, fr))
     return out
@@ -174,8 +180,8 @@ def nl_path(n_frames: int = 3000, *, steps_per_segment: int = 4000) -> tuple[Pat
     frames, starting at waypoint 0) with mean-reverting thermal noise
     (x_noise <- 0.99 x_noise + N(0, 0.005) per coordinate and frame, about
     0.035 nm stationary), so the nearest references change over the walk."""
-    sysm = path_system(304, 2120, 8, rng=config_rng(5, 0), dtype=np.float32, name="nl_path")
-    rng = config_rng(5, 1)
+    sysm = path_system(304, 2120, 8, rng=workload_rng(W_NL, 0), dtype=np.float32, name="nl_path")
+    rng = workload_rng(W_NL, 1)
     way = sysm.waypoints
     frames = np.empty((n_frames, 304, 3), dtype=np.float32)
     noise = np.zeros((304, 3))
@@ -189,15 +195,15 @@ def nl_path(n_frames: int = 3000, *, steps_per_segment: int = 4000) -> tuple[Pat
     return sysm, frames
 
 
-def cfg4_training_walks(n_walks: int = 1000, steps: int = 1000,
+def surrogate_training_walks(n_walks: int = 1000, steps: int = 1000,
                         system: PathSystem | None = None) -> np.ndarray:
     """Training frames for the surrogate: ``n_walks`` independent walks of
-    ``steps`` frames on the cfg1 system, each starting at a random landmark's
-    waypoint mixture (seeds differ from the cfg1 test walk).  FP32
+    ``steps`` frames on the path_300x500 system, each starting at a random landmark's
+    waypoint mixture (seeds differ from the path_300x500 test walk).  FP32
     ``[n_walks * steps][n][3]``."""
     if system is None:
-        system, _ = cfg1(n_frames=1)
-    rng = config_rng(4, 0)
+        system, _ = path_300x500(n_frames=1)
+    rng = workload_rng(W_SURROGATE, 0)
     out = np.empty((n_walks * steps, system.n_atoms, 3), dtype=np.float32)
     kway = system.waypoints.shape[0]
     for w in range(n_walks):
