@@ -13,11 +13,13 @@ from oracle.msd import superpose
 pytestmark = pytest.mark.gpu
 
 
-def _walk(torch, lm, frames, lam, eps, *, dtype, tol, name, every=1):
+def _walk(torch, lm, frames, lam, eps, *, dtype, tol, name, every=1, plan=None):
     import paper_1801_02362_amd as pcv
     from gpu_util import check_cv, dev, host, say
-    say(f"[close] {name}: L={lm.shape[0]} n={lm.shape[1]} frames={len(frames)} eps={eps}")
+    say(f"[close] {name}: L={lm.shape[0]} n={lm.shape[1]} frames={len(frames)} eps={eps} plan={plan}")
     cv = pcv.PathCV(dev(lm, dtype), lam, eps=eps)
+    if plan is not None:
+        cv.set_plan(**plan)
     orc = CloseStructure(lm.astype(np.float64), lam, eps)
     x = torch.empty(lm.shape[1], 3, dtype=dtype, device="cuda")
     ambiguous = 0
@@ -107,3 +109,22 @@ def test_forced_reassignment_and_nonfinite_keep_state():
     ref = path_cv(frames[19].astype(np.float64), sysm.landmarks.astype(np.float64), lam, grad=False)
     assert abs(host(o["sz"])[0] - ref.s) < 1e-6
     cv.close()
+
+
+# Every engine serves both branches of a close-structure step from one
+# launch (the device flag picks the reassignment or the approximate problem).
+_CLOSE_PLANS = [dict(engine=1, wg=256, apt=4, team=256), dict(engine=2, wg=512, apt=16, team=64, aptg=8, batch=5),
+                dict(engine=3, wg=512, apt=8, team=0, aptg=0, batch=0, items=9),
+                dict(engine=4, wg=512, apt=12, team=0, aptg=0, batch=0)]
+
+
+@pytest.mark.parametrize("plan", _CLOSE_PLANS, ids=["engine1", "engine2", "engine3", "engine4"])
+def test_close_walk_every_engine(plan):
+    import torch
+    from gpu_util import TOL32
+    s = wl.small_path(700, 40, 61, dtype=np.float32)
+    frames = wl.random_walk(s.waypoints[0].astype(np.float64), 30, rng=np.random.default_rng(62), step_sigma=0.01)
+    lam = landmark_lambda(s.landmarks)
+    n_re = _walk(torch, s.landmarks, frames, lam, 0.002, dtype=torch.float32, tol=TOL32,
+                 name=f"close_{plan['engine']}", plan=plan)
+    assert 2 <= n_re < len(frames)
