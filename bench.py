@@ -113,7 +113,7 @@ def bench_exact(args):
     frames = wl.rigid_frames(base, args.warmup + args.steps)
     dev = torch.device("cuda", 0)
     lm = torch.as_tensor(sysm.landmarks, device=dev)
-    cv = pcv.PathCV(lm, None, use_graph=True)
+    cv = pcv.PathCV(lm, None)            # direct launches (faster than graph replay here)
     del lm
     torch.cuda.empty_cache()
     x_all = torch.as_tensor(frames, device=dev)
@@ -165,6 +165,7 @@ def bench_exact(args):
         "config": {"workload": f"exact path CV, {n} atoms x {L} landmarks (FP32 SoA, "
                                f"{L * n * 12 / 1e6:.0f} MB), s, z, ds/dx, dz/dx per step, fresh frame per step",
                    "n_atoms": n, "n_landmarks": L, "lambda": round(cv.lam, 4), "plan": cv.plan,
+                   "launch": "direct (prep, engine, merge per step)",
                    "step_hbm_frac": round(alg_bytes / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roof,
     }

@@ -69,7 +69,11 @@ typedef struct pcv_options {
   void* stream;      /* hipStream_t to enqueue on; NULL = the null stream */
   int precision;     /* PCV_FP32 or PCV_FP64: coordinate and gradient type */
   double eps;        /* close-structure threshold on D(x, y), nm^2 (Section 5: 0.01) */
-  int use_graph;     /* nonzero: replay per-call kernel sequences from a hipGraph */
+  int use_graph;     /* nonzero: replay each call's kernel sequence from a cached
+                        hipGraph (keyed by the call's pointers); 0 (the default):
+                        launch the kernels directly, which on MI355X is faster for
+                        these short sequences (300 x 500 exact step 27.6 us direct,
+                        35.3 us through a graph) */
 } pcv_options;
 
 typedef struct pcv_stats {

@@ -169,7 +169,7 @@ class PathCV:
     """
 
     def __init__(self, landmarks, lam: float | None = None, *, q=None, w=None, eps: float = 0.01,
-                 lambda_factor: float = 2.3, use_graph: bool = True, stream=None, device: int | None = None):
+                 lambda_factor: float = 2.3, use_graph: bool = False, stream=None, device: int | None = None):
         import torch
         L = load_library()
         if not (landmarks.is_cuda and landmarks.dim() == 3 and landmarks.shape[2] == 3):
@@ -449,7 +449,7 @@ class Surrogate:
     the caller (``set_params``).
     """
 
-    def __init__(self, ref, *, hidden: int = 512, max_batch: int = 1024, w=None, use_graph: bool = True,
+    def __init__(self, ref, *, hidden: int = 512, max_batch: int = 1024, w=None, use_graph: bool = False,
                  stream=None, device: int = 0):
         import numpy as np
         self._L = load_library()

@@ -151,7 +151,7 @@ extern "C" void pcv_default_options(pcv_options* opt) {
   opt->stream = nullptr;
   opt->precision = PCV_FP32;
   opt->eps = 0.01;
-  opt->use_graph = 1;
+  opt->use_graph = 0;
 }
 
 extern "C" int pcv_max_atoms(int precision) {
