@@ -195,10 +195,17 @@ def test_engine4_tilings(torch, n, spw, K, items):
 def test_engine4_plan_reports_and_rejects(torch):
     import paper_1801_02362_amd as pcv
     from gpu_util import dev
+    # A long landmark set: three units per worker, 21 // 3 = 7 landmark lanes.
+    long_set = wl.small_path(700, 1500, 5, dtype=np.float32)
+    cv = pcv.PathCV(dev(long_set.landmarks, torch.float32), 10.0)
+    p = cv.plan
+    assert p["engine"] == 4 and p["apt"] == 12 and p["batch"] == 7
+    cv.close()
+    # A short one: two units per worker and fewer lanes, so more workgroups share it.
     s = wl.small_path(700, 3, 5, dtype=np.float32)
     cv = pcv.PathCV(dev(s.landmarks, torch.float32), 10.0)
     p = cv.plan
-    assert p["engine"] == 4 and p["apt"] == 12 and p["batch"] == 7   # 3 blocks: 21 // 3 landmark lanes
+    assert p["engine"] == 4 and p["apt"] == 8 and p["batch"] == 1
     cv.set_plan(engine=4, wg=512, apt=8, team=0, aptg=0, batch=0)
     assert cv.plan["batch"] == 4                                      # 14 // 3
     with pytest.raises(pcv.PcvError):
