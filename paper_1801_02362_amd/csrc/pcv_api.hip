@@ -302,7 +302,11 @@ static pcv_status build_plan(pcv_handle* h) {
 static pcv_status build_nl_plan(pcv_handle* h, const Problem& full) {
   const Plan& p = h->plan;
   const int M = h->nl_M;
-  const int unit = (p.engine == 2 || p.engine == 4) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
+  // Engine 4 on the short member set: fewer landmark lanes per step, so that
+  // up to 64 workgroups share the M members (the lanes per step are a
+  // per-problem value; the launch's units per worker stay the plan's).
+  const int K_nl = p.engine == 4 ? std::max(1, std::min(p.B, M / 64)) : p.B;
+  const int unit = (p.engine == 2 || p.engine == 4) ? K_nl : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
   const int units = (M + unit - 1) / unit;
   const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
   const int n_items = std::max(1, std::min(units, cap));
@@ -336,6 +340,7 @@ static pcv_status build_nl_plan(pcv_handle* h, const Problem& full) {
   b.hdr = h->hdr_nl;
   b.vec = h->vec_nl;
   b.L = M;
+  b.bsz = K_nl;
   b.n_slots = n_items;
   Problem probs[3] = {b, b, b};
   HIP_TRY(h, hipMemcpy(h->d_prob_nl, probs, sizeof(probs), hipMemcpyHostToDevice));
