@@ -19,8 +19,9 @@
  *              landmark rotations are recomputed and saved, otherwise each
  *              landmark rotation is approximated by R_xy R_{a_i y} (Eq. 5).
  *
- * Units: nm and nm^2; lambda in nm^-2.  Weights (one set, used for both
- * alignment and displacement, w = w') are normalised to sum to one.
+ * Units: nm and nm^2; lambda in nm^-2.  Weights are normalised to sum to
+ * one; by default one set serves alignment and displacement (w = w'), and
+ * pcv_set_displacement_weights() gives the distance its own set.
  *
  * Memory: every coordinate, gradient and result pointer named "device" is
  * HIP device memory owned by the caller (for example a torch tensor); the
