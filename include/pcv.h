@@ -28,7 +28,9 @@
  * library never frees it.  Coordinates are AoS [n][3] (or [L][n][3]) in the
  * handle's precision: float for PCV_FP32, double for PCV_FP64.  "host"
  * pointers are read during the call only.  The handle owns its own device
- * copies of the landmarks and all workspace; nothing is allocated per call.
+ * copies of the landmarks and all workspace; the evaluation calls allocate
+ * nothing (the stated exceptions: pcv_path_lambda, the first
+ * pcv_eval_properties call, and HIP events while kernel timing is on).
  *
  * Streams: all work is enqueued on the handle's stream and returns without
  * waiting (except where stated).  Results land in device memory; the caller
