@@ -1132,6 +1132,7 @@ extern "C" pcv_status pcv_force_reassign(pcv_handle* h) {
 }
 
 extern "C" pcv_status pcv_update_close(pcv_handle* h, const void* x) {
+  if (h && h->wd) return fail(h, PCV_EUNSUPPORTED, "the close structure with displacement weights");
   pcv_status s = pcv_force_reassign(h);
   if (s != PCV_OK) return s;
   return eval_close_impl(h, x, h->scratch_sz, nullptr, nullptr, nullptr, nullptr, false);
