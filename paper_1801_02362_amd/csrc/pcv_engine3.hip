@@ -96,7 +96,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)d * n_pad),
-                                       (__attribute__((address_space(3))) void*)(dst + d * kBlk3), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)(dst + d * kBlk3), 16, 0, kStreamPolicy);
     if (++it_k == nbw) { it_k = 0; ++it_t; }
     if (++it_slot == RS) it_slot = 0;
     ++issued;

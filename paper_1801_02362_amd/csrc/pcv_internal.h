@@ -58,6 +58,11 @@ template <typename T>
 __device__ __forceinline__ void stg(T* p, T v) {
   *((__attribute__((address_space(1))) T*)p) = v;
 }
+// Streaming (non-temporal) global load: data read once.
+template <typename T>
+__device__ __forceinline__ T ldg_nt(const T* p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
 
 // Partial accumulators of one work item: U = sum e (q - q0) r in the
 // coordinate type, V = sum e r in FP64 (the merge multiplies V by q0 - s).

@@ -704,8 +704,8 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
         double v[16];
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
-          u[b] = ldg(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
-          v[b] = ldg(partial_v<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+          u[b] = ldg_nt(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+          v[b] = ldg_nt(partial_v<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
         }
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
@@ -716,8 +716,8 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
       }
 #pragma unroll 4
       for (; t < gn; t += 4) {
-        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
-        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = fq[0][t];
         gs = fma(f, fma(fq[1][t], v, u), gs);
         gz = fma(f, v, gz);
@@ -790,8 +790,8 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int 
     if (j < n_pad) {
 #pragma unroll 4
       for (int t = sg; t < gn; t += NG) {
-        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
-        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = xfq[0][t];
         gs = fma(f, fma(xfq[1][t], v, u), gs);
         gz = fma(f, v, gz);
@@ -855,8 +855,8 @@ __global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Pr
     if (j < n_pad) {
 #pragma unroll 4
       for (int t = sg; t < gn; t += NG) {
-        const double u = (double)ldg(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
-        const double v = ldg(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
+        const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
         const double f = fq[0][t];
         su = fma(f, fma(fq[1][t], v, u), su);
         sv = fma(f, v, sv);
