@@ -28,6 +28,7 @@
 // format as engine_kernel, so the merge kernels are shared.
 #include "pcv_internal.h"
 #include "pcv_math.h"
+#include "pcv_stream.h"
 
 namespace pcv {
 
@@ -91,16 +92,15 @@ __device__ __forceinline__ void e2_issue(const E2Item<T>& c, int b, int cw, int 
   const size_t bytes = (size_t)cnt * c.lm_elems * sizeof(T);
   const int chunks = (int)(bytes / 1024);
   const int tails = (int)((bytes - (size_t)chunks * 1024) / 256);
-  constexpr int kCopyNT = 2;   // non-temporal: each landmark byte is read once per launch
   const char* src = reinterpret_cast<const char*>(c.A + (size_t)i0 * c.lm_elems);
   char* dst = c.lbase + (size_t)(b & 1) * c.lbuf_bytes;
   for (int ch = cw; ch < chunks; ch += NCW)
     __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)ch * 1024 + lane * 16),
-                                     (__attribute__((address_space(3))) void*)(dst + (size_t)ch * 1024), 16, 0, kCopyNT);
+                                     (__attribute__((address_space(3))) void*)(dst + (size_t)ch * 1024), 16, 0, kStreamPolicy);
   for (int tc = cw; tc < tails; tc += NCW) {
     const size_t off = (size_t)chunks * 1024 + (size_t)tc * 256;
     __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 4),
-                                     (__attribute__((address_space(3))) void*)(dst + off), 4, 0, kCopyNT);
+                                     (__attribute__((address_space(3))) void*)(dst + off), 4, 0, kStreamPolicy);
   }
 }
 
