@@ -259,7 +259,7 @@ pcv_status pcv_check(pcv_handle* h);
  *             `team` the lanes per landmark in the correlation stage
  *             (16, 32, 64 or 192).  Needs the landmark batch to fit in LDS.
  *   engine 3  large FP32 structures: seven worker waves each own up to `apt`/4
- *           blocks of 256 atoms (apt = 4, 8 or 12, so at most 7 * apt * 64
+ *           blocks of 256 atoms (apt = 4, 8, 12 or 16, so at most 7 * apt * 64
  *           atoms) and stream them through a private LDS copy ring; one solver
  *           wave; one barrier per landmark.  `team`, `aptg`, `batch` unused.
  * `grid` is an output; `items` <= 0 selects the default number of work items.

@@ -378,7 +378,7 @@ static bool default_plan2(pcv_handle* h) {
 // blocks of 256 atoms.
 static int e3_bpw_for(int n_pad) {
   const int nblk = (n_pad + 255) / 256;
-  for (int bpw = 1; bpw <= 3; ++bpw)
+  for (int bpw = 1; bpw <= 4; ++bpw)
     if (nblk <= engine3_max_blocks(bpw)) return bpw;
   return 0;
 }
@@ -1223,7 +1223,7 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
   } else if (q->engine == 3) {
     if (h->fp64) return fail(h, PCV_EUNSUPPORTED, "engine 3 is FP32 only");
     const int bpw = q->apt / 4;
-    if (q->apt % 4 != 0 || bpw < 1 || bpw > 3) return fail(h, PCV_EUNSUPPORTED, "engine 3 needs apt = 4, 8 or 12");
+    if (q->apt % 4 != 0 || bpw < 1 || bpw > 4) return fail(h, PCV_EUNSUPPORTED, "engine 3 needs apt = 4, 8, 12 or 16");
     if ((h->n_pad + 255) / 256 > engine3_max_blocks(bpw))
       return fail(h, PCV_EINVAL, "engine 3 tiling cannot hold the structure");
     p.engine = 3;

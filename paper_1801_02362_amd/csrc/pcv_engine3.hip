@@ -2,7 +2,7 @@
 //
 // One 512-thread workgroup per CU: seven worker waves and one solver wave.
 // The atoms are cut into blocks of 256 (64 lanes x 4 atoms); worker wave w
-// owns blocks w, w + 7, w + 14 (at most BPW of them) for every landmark of
+// owns blocks w, w + 7, w + 14, w + 21 (at most BPW of them) for every landmark of
 // its work item, so each worker keeps its atoms' share of the centred,
 // weighted structure in registers and streams only its own coordinates:
 //
@@ -17,8 +17,8 @@
 //     and publish its correlation; after it, the solver wave solves the
 //     quaternion eigenproblem of t (Section 3) and folds it into the running
 //     log-sum-exp (Eq. 2) while the workers add the gradient terms of t - 1,
-//     U += e (q - q0) R (a - c) in FP32 and V += e R (a - c) in FP64, and go
-//     on to contract t + 1.  The solve is thus hidden behind a whole
+//     U += e (q - q0) R (a - c) in FP32 and V += e R (a - c) in FP64 (FP32
+//     over the item at four blocks per wave), and go on to contract t + 1.  The solve is thus hidden behind a whole
 //     gradient-plus-correlation step; correlation and result slots are
 //     double-buffered by landmark parity.
 //
@@ -48,7 +48,15 @@ constexpr int kBlkFloats3 = 3 * kBlk3;          // one block of one landmark (x,
 
 // Copy-ring depth (block slots per worker wave) for BPW blocks per wave: the
 // ring and the wave's FP32 structure share about 150 KB of LDS.
-constexpr int ring_slots(int bpw) { return bpw >= 3 ? 4 : (bpw == 2 ? 5 : 6); }
+constexpr int ring_slots(int bpw) { return bpw >= 4 ? 3 : (bpw == 3 ? 4 : (bpw == 2 ? 5 : 6)); }
+
+// Accumulator of V = sum e R (a - c): FP64, except at four blocks per wave,
+// where the registers of a wave hold 16 atoms per lane and V is kept in FP32
+// over the item (the merge adds the item partials in FP64).
+template <int BPW>
+struct E3VAcc { typedef double type; };
+template <>
+struct E3VAcc<4> { typedef float type; };
 
 __shared__ double e3_part[2][kWorkers3][9];
 __shared__ double e3_res[2][16];
@@ -59,7 +67,8 @@ __device__ __forceinline__ void read_xblock(int k, unsigned addr, f4v& p0, f4v& 
   switch (k) {
     case 0: read_block<0>(addr, p0, p1, p2); break;
     case 1: read_block<kBlkFloats3 * 4>(addr, p0, p1, p2); break;
-    default: read_block<2 * kBlkFloats3 * 4>(addr, p0, p1, p2); break;
+    case 2: read_block<2 * kBlkFloats3 * 4>(addr, p0, p1, p2); break;
+    default: read_block<3 * kBlkFloats3 * 4>(addr, p0, p1, p2); break;
   }
 }
 
@@ -127,14 +136,15 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
   const unsigned xs_addr = (unsigned)(size_t)((__attribute__((address_space(3))) float*)xs) + lane * 16;
   for (int b = 0; b < RS && b < NB; ++b) issue_next();
 
+  using VT = typename E3VAcc<BPW>::type;
   float U[BPW][3][4];
-  double V[BPW][3][4];
+  VT V[BPW][3][4];
 #pragma unroll
   for (int k = 0; k < BPW; ++k)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) { U[k][d][e] = 0.f; V[k][d][e] = 0.0; }
+      for (int e = 0; e < 4; ++e) { U[k][d][e] = 0.f; V[k][d][e] = VT(0); }
 
   float a0[BPW][3][4], a1[BPW][3][4];
   int rd_slot = 0, consumed = 0;
@@ -176,7 +186,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
       const double sc = rs[11];
       if (sc != 1.0) {
         // The running minimum moved: rescale, and move U's reference
-        // property with it, U' = U + (q0 - q0') V (V is FP64).
+        // property with it, U' = U + (q0 - q0') V.
         const double dq = rs[15];
 #pragma unroll
         for (int k = 0; k < BPW; ++k)
@@ -184,9 +194,9 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
           for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const double v = V[k][d][e];
+              const double v = (double)V[k][d][e];
               U[k][d][e] = (float)(fma(dq, v, (double)U[k][d][e]) * sc);
-              V[k][d][e] = v * sc;
+              V[k][d][e] = (VT)(v * sc);
             }
       }
       float Rt[9];
@@ -205,7 +215,7 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
             for (int d = 0; d < 3; ++d) {
               const float r = fmaf(Rt[d * 3 + 0], b0, fmaf(Rt[d * 3 + 1], b1, Rt[d * 3 + 2] * b2));
               U[k][d][e] = fmaf(alf, r, U[k][d][e]);
-              V[k][d][e] = fma(be, (double)r, V[k][d][e]);
+              V[k][d][e] = (VT)fma((VT)be, (VT)r, V[k][d][e]);
             }
           }
         }
@@ -237,10 +247,10 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
           d2v v01, v23;
 #pragma unroll
           for (int e = 0; e < 4; ++e) u4[e] = (float)((double)U[k][d][e] - mu[d]);
-          v01[0] = V[k][d][0] - mv[d];
-          v01[1] = V[k][d][1] - mv[d];
-          v23[0] = V[k][d][2] - mv[d];
-          v23[1] = V[k][d][3] - mv[d];
+          v01[0] = (double)V[k][d][0] - mv[d];
+          v01[1] = (double)V[k][d][1] - mv[d];
+          v23[0] = (double)V[k][d][2] - mv[d];
+          v23[1] = (double)V[k][d][3] - mv[d];
           stg(reinterpret_cast<f4v*>(pu + (size_t)d * n_pad + j0), u4);
           stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0), v01);
           stg(reinterpret_cast<d2v*>(pv + (size_t)d * n_pad + j0 + 2), v23);
@@ -429,6 +439,8 @@ hipError_t launch_engine3<float>(int bpw, int grid, const Problem* probs, const 
     case 2: hipLaunchKernelGGL(engine3_kernel<2>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
                                run_if, dout); break;
     case 3: hipLaunchKernelGGL(engine3_kernel<3>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
+                               run_if, dout); break;
+    case 4: hipLaunchKernelGGL(engine3_kernel<4>, dim3(grid), dim3(kWG3), 0, st, probs, items, wg_off, mode, flag,
                                run_if, dout); break;
     default: return hipErrorInvalidValue;
   }

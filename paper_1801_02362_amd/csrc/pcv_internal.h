@@ -196,7 +196,7 @@ hipError_t engine2_init_attributes();
 size_t engine2_lds_bytes(size_t lbuf, int bmax);
 
 // Large-structure engine (FP32 only): bpw = 256-atom blocks per worker wave
-// (1, 2 or 3; a structure may have up to 7 * bpw blocks).
+// (1 to 4; a structure may have up to 7 * bpw blocks).
 template <typename T>
 hipError_t launch_engine3(int bpw, int grid, const Problem* probs, const Item* items, const int* wg_off, int mode,
                           const int* flag, int run_if, double* dout, hipStream_t st);

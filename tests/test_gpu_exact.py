@@ -132,8 +132,9 @@ def test_every_tiling_matches(torch, plan):
 # Large-structure engine: each compiled block count, structures that end
 # inside a 256-atom block or a 64-atom tile, and item counts from one item
 # (the whole landmark range streamed by one workgroup) to one landmark each.
-_E3_CASES = [(n, bpw, items) for n, bpws in ((100, (1, 2, 3)), (700, (1, 2, 3)), (1800, (2, 3)), (1793, (2, 3)),
-                                            (3000, (2, 3)), (3584, (2, 3)), (5000, (3,)), (5376, (3,)))
+_E3_CASES = [(n, bpw, items) for n, bpws in ((100, (1, 2, 3)), (700, (1, 2, 3, 4)), (1800, (2, 3)), (1793, (2, 3)),
+                                            (3000, (2, 3)), (3584, (2, 3, 4)), (5000, (3, 4)), (5376, (3, 4)),
+                                            (5377, (4,)), (6000, (4,)), (7168, (4,)))
              for bpw in bpws for items in (0, 1, 7)]
 
 
@@ -159,6 +160,33 @@ def test_engine3_rejects_structures_it_cannot_hold(torch):
         cv.set_plan(engine=3, wg=512, apt=4, team=0, aptg=0, batch=0)
     with pytest.raises(pcv.PcvError):
         cv.set_plan(engine=3, wg=512, apt=6, team=0, aptg=0, batch=0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=3, wg=512, apt=20, team=0, aptg=0, batch=0)
+    cv.close()
+
+
+def test_engine3_four_blocks_per_wave_default_grid(torch):
+    # 7,000 atoms (28 blocks, four per worker, V in FP32 over an item) and
+    # 600 landmarks: the default plan with one work item per CU.
+    from gpu_util import TOL32
+    s = wl.small_path(7000, 600, 77, dtype=np.float32)
+    rng = np.random.default_rng(78)
+    frames = (s.waypoints[1] + rng.normal(0, 0.02, (2, 7000, 3))).astype(np.float32)
+    lam = landmark_lambda(s.landmarks)
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name="e3_7000x600")
+
+
+@pytest.mark.parametrize("n,engine,apt", [(2049, 3, 8), (3585, 3, 12), (5377, 3, 16), (7168, 3, 16), (7169, 1, None)])
+def test_default_plan_by_structure_size(torch, n, engine, apt):
+    # Engine 3 takes every FP32 structure from 2,049 to 7,168 atoms with the
+    # fewest blocks per worker that hold it; larger ones go to engine 1.
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev
+    s = wl.small_path(n, 3, 7, dtype=np.float32)
+    cv = pcv.PathCV(dev(s.landmarks, torch.float32), 10.0)
+    assert cv.plan["engine"] == engine
+    if apt is not None:
+        assert cv.plan["apt"] == apt
     cv.close()
 
 
