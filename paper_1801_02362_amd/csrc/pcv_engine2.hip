@@ -96,7 +96,8 @@ __device__ __forceinline__ void e2_issue(const E2Item<T>& c, int b, int cw, int 
   char* dst = c.lbase + (size_t)(b & 1) * c.lbuf_bytes;
   for (int ch = cw; ch < chunks; ch += NCW)
     __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)ch * 1024 + lane * 16),
-                                     (__attribute__((address_space(3))) void*)(dst + (size_t)ch * 1024), 16, 0, kStreamPolicy);
+                                     (__attribute__((address_space(3))) void*)(dst + (size_t)ch * 1024), 16, 0,
+                                     kStreamPolicy);
   for (int tc = cw; tc < tails; tc += NCW) {
     const size_t off = (size_t)chunks * 1024 + (size_t)tc * 256;
     __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 4),

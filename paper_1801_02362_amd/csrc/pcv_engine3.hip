@@ -2,9 +2,10 @@
 //
 // One 512-thread workgroup per CU: seven worker waves and one solver wave.
 // The atoms are cut into blocks of 256 (64 lanes x 4 atoms); worker wave w
-// owns blocks w, w + 7, w + 14, w + 21 (at most BPW of them) for every landmark of
-// its work item, so each worker keeps its atoms' share of the centred,
-// weighted structure in registers and streams only its own coordinates:
+// owns blocks w, w + 7, w + 14, w + 21 (at most BPW of them) for every
+// landmark of its work item, so each worker keeps its atoms' share of the
+// centred, weighted structure in registers and streams only its own
+// coordinates:
 //
 //   * a private ring of block slots in LDS is filled by asynchronous
 //     HBM -> LDS copies (global_load_lds_dwordx4, 16 B per lane); a wave
@@ -18,9 +19,10 @@
 //     quaternion eigenproblem of t (Section 3) and folds it into the running
 //     log-sum-exp (Eq. 2) while the workers add the gradient terms of t - 1,
 //     U += e (q - q0) R (a - c) in FP32 and V += e R (a - c) in FP64 (FP32
-//     over the item at four blocks per wave), and go on to contract t + 1.  The solve is thus hidden behind a whole
-//     gradient-plus-correlation step; correlation and result slots are
-//     double-buffered by landmark parity.
+//     over the item at four blocks per wave), and go on to contract t + 1.
+//     The solve is thus hidden behind a whole gradient-plus-correlation
+//     step; correlation and result slots are double-buffered by landmark
+//     parity.
 //
 // Workers reduce their 9 correlation sums over the wave by transposed
 // halving (lane swaps, then DPP row sums); the solver adds the 7 worker sums
@@ -105,7 +107,8 @@ __device__ __forceinline__ void e3_worker(const E3Item& c, int w, int lane, floa
 #pragma unroll
     for (int d = 0; d < 3; ++d)
       __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)d * n_pad),
-                                       (__attribute__((address_space(3))) void*)(dst + d * kBlk3), 16, 0, kStreamPolicy);
+                                       (__attribute__((address_space(3))) void*)(dst + d * kBlk3), 16, 0,
+                                       kStreamPolicy);
     if (++it_k == nbw) { it_k = 0; ++it_t; }
     if (++it_slot == RS) it_slot = 0;
     ++issued;

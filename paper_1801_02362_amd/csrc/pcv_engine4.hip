@@ -129,7 +129,8 @@ __device__ __forceinline__ void e4_worker(const E4Item& c, int w, int lane, floa
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)d * n_pad),
-                                         (__attribute__((address_space(3))) void*)(dst + d * kBlk4), 16, 0, kStreamPolicy);
+                                         (__attribute__((address_space(3))) void*)(dst + d * kBlk4), 16, 0,
+                                         kStreamPolicy);
     }
     if (++it_s == it_na) {
       it_s = 0;
