@@ -32,7 +32,7 @@ struct Plan {
   int ts = 16;
   Engine2Cfg c2{0, 0};      // engine 2
   int g = 0, B = 1, lbuf = 0;
-  int bpw = 0;              // engine 3: 256-atom blocks per worker wave
+  int bpw = 0;              // engines 3 and 5: 256-atom blocks per worker wave
   int spw = 0;              // engine 4: units per worker wave (B = landmark lanes K)
   int grid = 0;
   int n_items = 0;
@@ -211,11 +211,18 @@ static pcv_status build_nl_plan(pcv_handle* h, const Problem& full);
 static pcv_status build_plan(pcv_handle* h) {
   Plan& p = h->plan;
   // Work-item granularity: a team's landmark (engine 1) or a batch (engine 2).
-  const int unit = (p.engine == 2 || p.engine == 4) ? p.B : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
+  const int unit = (p.engine == 2 || p.engine == 4) ? p.B : ((p.engine == 3 || p.engine == 5) ? 1 : p.cfg.wg / p.ts);
   const int units = (h->L + unit - 1) / unit;
   if (!h->user_plan || p.n_items <= 0) {
     const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
     p.n_items = std::max(1, std::min(units, cap));
+  }
+  if (p.engine == 5) {
+    // Engine 5 addresses an item through one range-checked buffer
+    // descriptor, whose offsets must stay below 2 GiB.
+    const long long lm_bytes = 12LL * h->n_pad;
+    const long long per_item = (1LL << 30) / lm_bytes;
+    p.n_items = std::max(p.n_items, (int)((h->L + per_item - 1) / per_item));
   }
   p.n_items = std::min(p.n_items, units);
   p.n_items = std::min(p.n_items, kMaxCloseSlots);
@@ -223,7 +230,7 @@ static pcv_status build_plan(pcv_handle* h) {
   if (p.engine == 2) {
     p.lbuf = p.B * 3 * h->n_pad * (h->fp64 ? 8 : 4);
     p.lds = engine2_lds_bytes((size_t)p.lbuf, p.B);
-  } else if (p.engine == 3 || p.engine == 4) {
+  } else if (p.engine == 3 || p.engine == 4 || p.engine == 5) {
     p.lds = 0;   // static LDS
   } else {
     p.lds = engine_lds_bytes(p.cfg, p.ts, h->fp64);
@@ -306,7 +313,7 @@ static pcv_status build_nl_plan(pcv_handle* h, const Problem& full) {
   // up to 64 workgroups share the M members (the lanes per step are a
   // per-problem value; the launch's units per worker stay the plan's).
   const int K_nl = p.engine == 4 ? std::max(1, std::min(p.B, M / 64)) : p.B;
-  const int unit = (p.engine == 2 || p.engine == 4) ? K_nl : (p.engine == 3 ? 1 : p.cfg.wg / p.ts);
+  const int unit = (p.engine == 2 || p.engine == 4) ? K_nl : ((p.engine == 3 || p.engine == 5) ? 1 : p.cfg.wg / p.ts);
   const int units = (M + unit - 1) / unit;
   const int cap = (p.engine >= 2 || p.cfg.wg >= 512) ? h->cus : 2 * h->cus;
   const int n_items = std::max(1, std::min(units, cap));
@@ -407,11 +414,14 @@ static bool default_plan4(pcv_handle* h) {
   return true;
 }
 
+// Structures above engine 4's range: engine 5 (register-stream workers)
+// while the structure fits three blocks per worker, engine 3 (LDS copy ring)
+// at four.
 static bool default_plan3(pcv_handle* h) {
   if (h->fp64 || h->n_pad <= kEngine4MaxAtoms) return false;
   const int bpw = e3_bpw_for(h->n_pad);
   if (bpw == 0) return false;
-  h->plan.engine = 3;
+  h->plan.engine = bpw <= 3 ? 5 : 3;
   h->plan.bpw = bpw;
   h->plan.cfg = EngineCfg{512, 4 * bpw};
   h->plan.ts = 0;
@@ -592,6 +602,8 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
   hipError_t e;
   if (p.engine == 4)
     e = launch_engine4<T>(p.spw, grid, probs, items, wgoff, mode, flag, run_if, msd, st);
+  else if (p.engine == 5)
+    e = launch_engine5<T>(p.bpw, grid, probs, items, wgoff, mode, flag, run_if, msd, st);
   else if (p.engine == 3)
     e = launch_engine3<T>(p.bpw, grid, probs, items, wgoff, mode, flag, run_if, msd, st);
   else if (p.engine == 2)
@@ -1181,7 +1193,8 @@ extern "C" pcv_status pcv_get_plan(pcv_handle* h, pcv_plan* out) {
   const Plan& p = h->plan;
   out->engine = p.engine;
   out->wg = p.engine >= 2 ? 512 : p.cfg.wg;
-  out->apt = p.engine == 2 ? p.c2.aptc : (p.engine == 3 ? 4 * p.bpw : (p.engine == 4 ? 4 * p.spw : p.cfg.apt));
+  out->apt = p.engine == 2 ? p.c2.aptc
+             : ((p.engine == 3 || p.engine == 5) ? 4 * p.bpw : (p.engine == 4 ? 4 * p.spw : p.cfg.apt));
   out->team = p.engine == 2 ? p.g : (p.engine >= 3 ? 0 : p.ts);
   out->aptg = p.engine == 2 ? p.c2.aptg : 0;
   out->batch = (p.engine == 2 || p.engine == 4) ? p.B : 0;
@@ -1230,6 +1243,16 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
     p.bpw = bpw;
     p.cfg = EngineCfg{512, 4 * bpw};
     p.ts = 0;
+  } else if (q->engine == 5) {
+    if (h->fp64) return fail(h, PCV_EUNSUPPORTED, "engine 5 is FP32 only");
+    const int bpw = q->apt / 4;
+    if (q->apt % 4 != 0 || bpw < 1 || bpw > 3) return fail(h, PCV_EUNSUPPORTED, "engine 5 needs apt = 4, 8 or 12");
+    if ((h->n_pad + 255) / 256 > engine5_max_blocks(bpw))
+      return fail(h, PCV_EINVAL, "engine 5 tiling cannot hold the structure");
+    p.engine = 5;
+    p.bpw = bpw;
+    p.cfg = EngineCfg{512, 4 * bpw};
+    p.ts = 0;
   } else if (q->engine == 4) {
     if (h->fp64) return fail(h, PCV_EUNSUPPORTED, "engine 4 is FP32 only");
     const int spw = q->apt / 4;
@@ -1244,7 +1267,7 @@ extern "C" pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* q) {
     p.cfg = EngineCfg{512, 4 * spw};
     p.ts = 0;
   } else {
-    return fail(h, PCV_EINVAL, "engine must be 1, 2, 3 or 4");
+    return fail(h, PCV_EINVAL, "engine must be 1, 2, 3, 4 or 5");
   }
   p.n_items = q->items;
   HIP_TRY(h, hipStreamSynchronize(h->stream));

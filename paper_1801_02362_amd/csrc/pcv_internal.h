@@ -201,6 +201,12 @@ template <typename T>
 hipError_t launch_engine3(int bpw, int grid, const Problem* probs, const Item* items, const int* wg_off, int mode,
                           const int* flag, int run_if, double* dout, hipStream_t st);
 int engine3_max_blocks(int bpw);
+// Register-stream variant of engine 3 (FP32): the same blocks and solver,
+// landmarks streamed HBM -> registers; bpw 1 to 3.
+template <typename T>
+hipError_t launch_engine5(int bpw, int grid, const Problem* probs, const Item* items, const int* wg_off, int mode,
+                          const int* flag, int run_if, double* dout, hipStream_t st);
+int engine5_max_blocks(int bpw);
 
 // Multi-landmark engine (FP32, n_pad <= 2048): spw = units (landmark lane,
 // 256-atom block) per worker wave (2 or 3).  A problem's Problem::bsz is its

@@ -16,6 +16,38 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kStreamPolicy = 2;
 typedef double d2v __attribute__((ext_vector_type(2)));
 
+// Word 3 of a raw buffer descriptor on gfx9-family chips: 32-bit data
+// format, no swizzle (loads of whole dwords, range-checked against the
+// descriptor's byte count).
+constexpr int kRawBufferWord3 = 0x00020000;
+// A buffer offset past any descriptor's range: such a load returns zeros.
+constexpr int kOutOfRange = 0x7ffffff0;
+
+// Lane k's value (k wave-uniform) in scalar registers.
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, k);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), k);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// A pointer that is the same in every lane, as a wave-uniform (scalar) value.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
+// Raw buffer descriptor of `bytes` bytes at p.  The address must be the same
+// in every lane; it is made wave-uniform explicitly (read from the first
+// lane), so the descriptor lives in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr((void*)p), (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           kRawBufferWord3);
+}
+
 // LDS-only workgroup barrier: the asynchronous copies in flight are not
 // waited for (the compiler's workgroup barrier would drain them).
 __device__ __forceinline__ void bar_lds() {

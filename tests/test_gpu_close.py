@@ -116,10 +116,13 @@ def test_forced_reassignment_and_nonfinite_keep_state():
 _CLOSE_PLANS = [dict(engine=1, wg=256, apt=4, team=256), dict(engine=2, wg=512, apt=16, team=64, aptg=8, batch=5),
                 dict(engine=3, wg=512, apt=8, team=0, aptg=0, batch=0, items=9),
                 dict(engine=4, wg=512, apt=12, team=0, aptg=0, batch=0),
-                dict(engine=3, wg=512, apt=16, team=0, aptg=0, batch=0, items=9)]
+                dict(engine=3, wg=512, apt=16, team=0, aptg=0, batch=0, items=9),
+                dict(engine=5, wg=512, apt=8, team=0, aptg=0, batch=0, items=9),
+                dict(engine=5, wg=512, apt=12, team=0, aptg=0, batch=0, items=4)]
 
 
-@pytest.mark.parametrize("plan", _CLOSE_PLANS, ids=["engine1", "engine2", "engine3", "engine4", "engine3_four_blocks"])
+@pytest.mark.parametrize("plan", _CLOSE_PLANS, ids=["engine1", "engine2", "engine3", "engine4", "engine3_four_blocks",
+                                                    "engine5", "engine5_three_blocks"])
 def test_close_walk_every_engine(plan):
     import torch
     from gpu_util import TOL32

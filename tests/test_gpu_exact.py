@@ -43,7 +43,7 @@ def test_path_22x20_fp64(torch):
 
 def test_rigid_5000x10000_full_size_in_the_bench_configuration(torch):
     """5,000 atoms x 10,000 landmarks (600 MB), the plan the bench times
-    (engine 3, one item per CU): every D_i, s, z and both gradients of one
+    (engine 5, one item per CU): every D_i, s, z and both gradients of one
     frame against the oracle."""
     import paper_1801_02362_amd as pcv
     from gpu_util import TOL32, check_cv, dev, host, say
@@ -51,7 +51,7 @@ def test_rigid_5000x10000_full_size_in_the_bench_configuration(torch):
     f = wl.rigid_frames(base, 1)[0]
     cv = pcv.PathCV(dev(sysm.landmarks, torch.float32), None)
     say(f"[exact] rigid_5000x10000 full size: plan={cv.plan} lambda={cv.lam:.4f}")
-    assert cv.plan["engine"] == 3 and cv.plan["items"] == cv.plan["grid"]
+    assert cv.plan["engine"] == 5 and cv.plan["items"] == cv.plan["grid"]
     o = cv.eval(dev(f, torch.float32), msd=True)
     got = host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"])
     cv.check()
@@ -138,17 +138,22 @@ _E3_CASES = [(n, bpw, items) for n, bpws in ((100, (1, 2, 3)), (700, (1, 2, 3, 4
              for bpw in bpws for items in (0, 1, 7)]
 
 
-@pytest.mark.parametrize("n,bpw,items", _E3_CASES)
-def test_engine3_tilings(torch, n, bpw, items):
+# Engine 5 (register-stream workers) takes the same blocks up to three per
+# worker: the same shapes, plus odd and even landmark counts per item.
+_E5_CASES = [(n, bpw, items) for (n, bpw, items) in _E3_CASES if bpw <= 3] + [(5000, 3, 2), (2100, 2, 4)]
+
+
+@pytest.mark.parametrize("engine,n,bpw,items", [(3,) + c for c in _E3_CASES] + [(5,) + c for c in _E5_CASES])
+def test_engine3_tilings(torch, engine, n, bpw, items):
     from gpu_util import TOL32
     L = 23
     s = wl.small_path(n, L, 40 + n % 17, dtype=np.float32)
     rng = np.random.default_rng(n + bpw)
     frames = (s.waypoints[0] + rng.normal(0, 0.02, (2, n, 3))).astype(np.float32)
     lam = landmark_lambda(s.landmarks)
-    plan = dict(engine=3, wg=512, apt=4 * bpw, team=0, aptg=0, batch=0, items=items if items else L)
-    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name=f"e3_{n}_{bpw}_{items}",
-               plan=plan)
+    plan = dict(engine=engine, wg=512, apt=4 * bpw, team=0, aptg=0, batch=0, items=items if items else L)
+    _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32,
+               name=f"e{engine}_{n}_{bpw}_{items}", plan=plan)
 
 
 def test_engine3_rejects_structures_it_cannot_hold(torch):
@@ -162,6 +167,10 @@ def test_engine3_rejects_structures_it_cannot_hold(torch):
         cv.set_plan(engine=3, wg=512, apt=6, team=0, aptg=0, batch=0)
     with pytest.raises(pcv.PcvError):
         cv.set_plan(engine=3, wg=512, apt=20, team=0, aptg=0, batch=0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=5, wg=512, apt=4, team=0, aptg=0, batch=0)
+    with pytest.raises(pcv.PcvError):
+        cv.set_plan(engine=5, wg=512, apt=16, team=0, aptg=0, batch=0)
     cv.close()
 
 
@@ -176,10 +185,12 @@ def test_engine3_four_blocks_per_wave_default_grid(torch):
     _run_exact(torch, s.landmarks, frames, lam, dtype=torch.float32, tol=TOL32, name="e3_7000x600")
 
 
-@pytest.mark.parametrize("n,engine,apt", [(2049, 3, 8), (3585, 3, 12), (5377, 3, 16), (7168, 3, 16), (7169, 1, None)])
+@pytest.mark.parametrize("n,engine,apt", [(2049, 5, 8), (3585, 5, 12), (5376, 5, 12), (5377, 3, 16), (7168, 3, 16),
+                                          (7169, 1, None)])
 def test_default_plan_by_structure_size(torch, n, engine, apt):
-    # Engine 3 takes every FP32 structure from 2,049 to 7,168 atoms with the
-    # fewest blocks per worker that hold it; larger ones go to engine 1.
+    # Engine 5 takes FP32 structures from 2,049 to 5,376 atoms and engine 3
+    # those up to 7,168, each with the fewest blocks per worker that hold
+    # them; larger ones go to engine 1.
     import paper_1801_02362_amd as pcv
     from gpu_util import dev
     s = wl.small_path(n, 3, 7, dtype=np.float32)
@@ -306,6 +317,7 @@ def test_argument_errors(torch):
 
 
 @pytest.mark.parametrize("plan", [None, dict(engine=3, wg=512, apt=4, team=0, aptg=0, batch=0),
+                                  dict(engine=5, wg=512, apt=4, team=0, aptg=0, batch=0),
                                   dict(engine=2, wg=512, apt=4, team=16, aptg=2, batch=64),
                                   dict(engine=1, wg=256, apt=1, team=64)])
 def test_structure_on_a_landmark(torch, plan):
