@@ -200,6 +200,22 @@ pcv_status pcv_get_neighbour_list(pcv_handle* h, int* members, int capacity, int
 pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, const double* q, double* S, void* dS_dx);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and outputs as pcv_eval_properties, with its scratch (the
+ * weights W, L P doubles rounded up to 256 bytes, and the gradient-pass
+ * partials, chunks P 3 n_pad doubles) taken from a fixed 16 MiB device array
+ * that the library holds on every GPU it runs on until the process ends.
+ * Calls no allocating routine and records no graph; launches eagerly on the
+ * handle's stream.  PCV_EINVAL when the scratch would exceed 16 MiB.  Every
+ * call on one GPU shares that GPU's array (each call overwrites it before
+ * reading it): calls that overlap in time on one GPU (other streams, other
+ * threads, other handles) race and must be serialised by the caller.
+ */
+pcv_status pcv_eval_properties_noalloc(pcv_handle* h, const void* x, int P, const double* q, double* S,
+                                       void* dS_dx);
+
+/*
  * Separate displacement weights w (Section 3.1, Eq. 4 with w != w'): the
  * weights given to pcv_load_landmarks stay the alignment weights w' (centre
  * of mass and rotation); w_disp sets the per-atom weights of the distance,

@@ -118,6 +118,7 @@ def load_library():
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
         "pcv_set_neighbour_list": (st, [vp, i, i]),
         "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
+        "pcv_eval_properties_noalloc": (st, [vp, vp, i, vp, vp, vp]),
         "pcv_set_displacement_weights": (st, [vp, vp]),
         "pcv_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "pcv_load_state": (st, [vp, vp, ctypes.c_size_t]),
@@ -280,6 +281,26 @@ class PathCV:
             dS = o.get("dS_dx") if o.get("dS_dx") is not None else torch.empty(P, x.shape[0], 3, dtype=x.dtype,
                                                                                 device=x.device)
         self._check(self._L.pcv_eval_properties(self._h, _ptr(x), P, _ptr(q), _ptr(S), _ptr(dS)))
+        return {"S": S, "dS_dx": dS}
+
+    def eval_properties_noalloc(self, x, q, *, out: dict) -> dict:
+        """As ``eval_properties`` with caller-provided outputs (``out["S"]``
+        [P] float64 and ``out["dS_dx"]`` [P][n][3] or None) and the library's
+        fixed device scratch: the call allocates nothing
+        (``pcv_eval_properties_noalloc``)."""
+        import torch
+        self._check_x(x)
+        if not (q.is_cuda and q.dtype == torch.float64 and q.dim() == 2 and q.shape[0] == self.n_landmarks
+                and q.is_contiguous()):
+            raise ValueError("q must be a contiguous CUDA float64 tensor [L][P]")
+        P = int(q.shape[1])
+        S, dS = out["S"], out.get("dS_dx")
+        if not (S.is_cuda and S.dtype == torch.float64 and S.numel() == P and S.is_contiguous()):
+            raise ValueError("out['S'] must be a contiguous CUDA float64 tensor [P]")
+        if dS is not None and not (dS.is_cuda and dS.dtype == x.dtype and tuple(dS.shape) == (P, x.shape[0], 3)
+                                   and dS.is_contiguous()):
+            raise ValueError("out['dS_dx'] must be a contiguous CUDA tensor [P][n][3] of the coordinate type")
+        self._check(self._L.pcv_eval_properties_noalloc(self._h, _ptr(x), P, _ptr(q), _ptr(S), _ptr(dS)))
         return {"S": S, "dS_dx": dS}
 
     def set_displacement_weights(self, w_disp=None):

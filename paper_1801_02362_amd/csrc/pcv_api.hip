@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,35 @@ struct Plan {
 // Serial numbers of handles: with the plan version they name the handle's
 // current device buffers (a host address can be reused after destruction).
 static std::atomic<unsigned long long> g_handle_serial{0};
+
+// Fixed device scratch for pcv_eval_properties_noalloc: one array per GPU
+// (the module's own copy on every device it is loaded on), held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name stands for a host-side placeholder); it uses the device
+// address from hipGetSymbolAddress, taken once per device.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: record the address of this device's scratch array.
+static hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 struct pcv_handle {
   unsigned long long serial = 0;
@@ -179,7 +209,8 @@ extern "C" pcv_status pcv_create(pcv_handle** out, const pcv_options* opt) {
     delete h;
     return PCV_EHIP;
   }
-  if (engine_init_attributes() != hipSuccess || engine2_init_attributes() != hipSuccess) {
+  if (engine_init_attributes() != hipSuccess || engine2_init_attributes() != hipSuccess ||
+      scratch_init(o.device) != hipSuccess) {
     (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return PCV_EHIP;
@@ -586,14 +617,8 @@ extern "C" pcv_status pcv_path_lambda(pcv_handle* h, double factor, double* lamb
 // ---------------------------------------------------------------- Algorithm 1
 // Engine launch bracketed by events when kernel timing is on.
 template <typename T>
-static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd,
-                               bool nl = false, int prob_slot = -1) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->timing) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, st);
-  }
+static hipError_t engine_launch(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd,
+                                bool nl = false, int prob_slot = -1) {
   const Plan& p = h->plan;
   const Problem* probs = (nl ? h->d_prob_nl : h->d_prob) + (prob_slot >= 0 ? prob_slot : mode);
   const Item* items = nl ? h->d_items_nl : h->d_items;
@@ -611,6 +636,19 @@ static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const in
                           run_if, msd, st);
   else
     e = launch_engine<T>(p.cfg, grid, p.lds, probs, items, wgoff, mode, flag, run_if, msd, st);
+  return e;
+}
+
+template <typename T>
+static hipError_t engine_timed(pcv_handle* h, hipStream_t st, int mode, const int* flag, int run_if, double* msd,
+                               bool nl = false, int prob_slot = -1) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, st);
+  }
+  const hipError_t e = engine_launch<T>(h, st, mode, flag, run_if, msd, nl, prob_slot);
   if (h->timing) {
     (void)hipEventRecord(e1, st);
     h->ev_pending.emplace_back(e0, e1);
@@ -922,6 +960,46 @@ extern "C" pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, c
     return h->fp64 ? enqueue_props<double>(h, st, x, P, q, S, dS_dx)
                    : enqueue_props<float>(h, st, x, P, q, S, dS_dx);
   });
+}
+
+// pcv_eval_properties with its weights W [L][P] and gradient-pass partials
+// [chunks][P][3][n_pad] in the GPU's fixed scratch array: no allocation, no
+// graph, eager launches on the handle's stream.  Both buffers are written
+// in full before they are read, so nothing needs clearing between calls.
+extern "C" pcv_status pcv_eval_properties_noalloc(pcv_handle* h, const void* x, int P, const double* q, double* S,
+                                                  void* dS_dx) {
+  if (!h) return PCV_EINVAL;
+  if (h->L == 0) return fail(h, PCV_ESTATE, "no landmarks loaded");
+  if (!x || !q || !S) return fail(h, PCV_EINVAL, "x, q and S are required");
+  if (P < 1 || P > kPropsMax) return fail(h, PCV_EINVAL, "need 1 <= P <= " + std::to_string(kPropsMax));
+  if (h->wd) return fail(h, PCV_EUNSUPPORTED, "property maps with displacement weights");
+  const size_t chunks = props_chunks(h->n_pad, h->L);
+  const size_t w_bytes = ((size_t)h->L * P * sizeof(double) + 255) / 256 * 256;
+  const size_t part_bytes = chunks * P * 3 * (size_t)h->n_pad * sizeof(double);
+  if (w_bytes + part_bytes > kScratchBytes)
+    return fail(h, PCV_EINVAL,
+                "property maps need " + std::to_string(w_bytes + part_bytes) + " bytes of scratch; the fixed array holds " +
+                    std::to_string(kScratchBytes));
+  unsigned char* base = (unsigned char*)scratch_ptr(h->opt.device);
+  if (!base) return fail(h, PCV_ESTATE, "no scratch address for this device");
+  double* W = (double*)base;
+  double* part = (double*)(base + w_bytes);
+  HIP_TRY(h, hipSetDevice(h->opt.device));
+  const hipStream_t st = h->stream;
+  hipError_t e;
+  if (h->fp64) {
+    e = launch_prep<double>(h->d_prep, x, 1, h->n, st);
+    if (e == hipSuccess) e = engine_launch<double>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
+    PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+    if (e == hipSuccess) e = launch_props<double>(a, q, h->lam, S, W, part, dS_dx, st);
+  } else {
+    e = launch_prep<float>(h->d_prep, x, 1, h->n, st);
+    if (e == hipSuccess) e = engine_launch<float>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
+    PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+    if (e == hipSuccess) e = launch_props<float>(a, q, h->lam, S, W, part, dS_dx, st);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "property maps (fixed scratch)");
+  return PCV_OK;
 }
 
 extern "C" pcv_status pcv_set_neighbour_list(pcv_handle* h, int M, int stride) {
