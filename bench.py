@@ -81,9 +81,39 @@ def counted_traffic(name: str):
     return d.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate_job(args):
+    """One process: the oracle path_cv on the first k landmarks for about
+    `seconds`; returns (evaluations, elapsed seconds)."""
+    import numpy as np
+    from oracle.path import path_cv
+    x, A, lam, seconds = args
+    n_ev, t0 = 0, time.perf_counter()
+    while True:
+        path_cv(x, A, lam)
+        n_ev += A.shape[0]
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return n_ev, dt
+
+
 def cpu_baseline_exact(sysm, frames, lam, budget_s: float = 12.0):
-    """Oracle path_cv (exact D, s, z and gradients) on the first k landmarks
-    for one frame, k grown until the run takes a few seconds."""
+    """The FP64 oracle (path_cv: exact D, s, z and both gradients, as it
+    stands) on the first k landmarks for one frame, k grown until a run takes
+    a few seconds: once in this process (one thread), then in one process
+    per core (up to 16, BLAS limited to one thread each) over the same
+    window; value = the all-cores rate."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     import numpy as np
     from oracle.path import path_cv
     A = sysm.landmarks
@@ -93,17 +123,58 @@ def cpu_baseline_exact(sysm, frames, lam, budget_s: float = 12.0):
         t0 = time.perf_counter()
         path_cv(x, A[:k].astype(np.float64), lam)
         dt = time.perf_counter() - t0
-        if dt > budget_s / 3 or k >= A.shape[0]:
+        if dt > budget_s / 6 or k >= A.shape[0]:
             break
-        k = min(A.shape[0], int(k * max(2.0, budget_s / 3 / max(dt, 1e-3))))
-    reps = max(1, int(budget_s / max(dt, 1e-3) / 2))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        path_cv(x, A[:k].astype(np.float64), lam)
-    dt = (time.perf_counter() - t0) / reps
-    return {"value": k / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+        k = min(A.shape[0], int(k * max(2.0, budget_s / 6 / max(dt, 1e-3))))
+    Ak = np.ascontiguousarray(A[:k].astype(np.float64))
+    one_ev, one_dt = _oracle_rate_job((x, Ak, lam, budget_s / 3))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as pool:
+        res = list(pool.map(_oracle_rate_job, [(x, Ak, lam, budget_s / 3)] * cores))
+    all_rate = sum(ev / dt for ev, dt in res)
+    return {"value": all_rate, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": one_ev / one_dt, "cpu_model": cpu_model(),
             "sample": f"FP64 NumPy oracle (path_cv with gradients), first {k} of {A.shape[0]} landmarks x "
-                      f"{sysm.n_atoms} atoms, 1 frame, {reps} repetitions, single thread"}
+                      f"{sysm.n_atoms} atoms, 1 frame, repeated for {budget_s / 3:.0f} s in each of {cores} "
+                      f"processes (one thread each) and once in this process"}
+
+
+def stream_ceiling(nbytes: int, grid: int = 256, reps: int = 50):
+    """The project's streaming-read kernel (pcv_stream_read) over a buffer of
+    nbytes: GB/s from HIP events on the current stream (after 10 untimed
+    reads), and whether the per-workgroup sums add up to the buffer's."""
+    import torch
+    import paper_1801_02362_amd as pcv
+    n = nbytes // 4
+    buf = torch.ones(n, dtype=torch.float32, device="cuda")
+    sums = torch.zeros(grid, dtype=torch.float64, device="cuda")
+    for _ in range(10):
+        pcv.stream_read(buf, sums, grid)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pcv.stream_read(buf, sums, grid)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = abs(float(sums.sum().item()) - n) < 0.5
+    del buf
+    torch.cuda.empty_cache()
+    return {"GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "us_per_read": round(ms * 1e3, 2), "bytes": nbytes,
+            "checksum_ok": ok, "kernel": "stream_read_kernel (pcv_stream_read)"}
+
+
+def bench_stream(args):
+    """Practical streaming-read ceiling: pcv_stream_read over --copy-mb MB."""
+    nbytes = int(args.copy_mb * 1e6) // 16 * 16
+    c = stream_ceiling(nbytes, reps=max(10, args.steps))
+    return {"metric": "streaming read GB/s", "value": c["GB_s"], "unit": "GB/s", "n_gpus": 1, "steps": max(10, args.steps),
+            "warmup": 10, "ms_per_step": round(c["us_per_read"] / 1e3, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"one read of {nbytes / 1e6:.0f} MB (16-byte non-temporal loads)",
+                       "hbm_peak_frac": round(c["GB_s"] / HBM_PEAK_GBS, 4), **c}}
 
 
 def kernel_ms(cv, x, x_all):
@@ -163,6 +234,9 @@ def bench_exact(args):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"{KERNEL_NAMES[cv.plan['engine']]} (landmark streaming, exact mode)", "kernel_ms": round(kms, 5),
             "kernel_launches_timed": int(cnt), "algorithmic_bytes_per_launch": alg_bytes}
+    ceil = stream_ceiling(alg_bytes // 16 * 16)
+    roof["stream_read_ceiling_GBs"] = ceil["GB_s"]
+    roof["frac_of_stream_read_ceiling"] = round(achieved / ceil["GB_s"], 4)
     out = {
         "metric": "structure-landmark MSD+grad evals/s",
         "value": round(value, 1),
@@ -191,44 +265,103 @@ def bench_exact(args):
 
 
 def bench_close(args):
+    """Algorithm 2 along the 300-atom, 500-landmark random walk (the close
+    structure at eps = 0.01 nm^2), --frames frames (default 100,000).
+    Timed: the close-structure step with gradients, frame copy included.
+    Untimed, on every frame: the same walk on a fresh handle with every D~_i
+    kept, and the exact Algorithm 1 result with every D_i, for the error
+    statistics (|ds|, |dz| against exact, D~ >= D, Pearson r of D and D~ on
+    the approximate frames) and the reassignment and expensive-MSD counts
+    (Section 6.1, Section 6.2)."""
     import numpy as np
     import torch
     import paper_1801_02362_amd as pcv
     import workloads as wl
-    sysm, frames = wl.path_300x500(args.warmup + args.steps)
+    F = args.frames
+    log(f"[bench] generating path_300x500 walk: {F} frames")
+    sysm, frames = wl.path_300x500(args.warmup + F)
     dev = torch.device("cuda", 0)
-    cv = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), None, eps=0.01)
+    L = sysm.n_landmarks
+    lm = torch.as_tensor(sysm.landmarks, device=dev)
+    cv = pcv.PathCV(lm, None, eps=0.01)
+    lam = cv.lam
     x_all = torch.as_tensor(frames, device=dev)
     x = torch.empty_like(x_all[0])
+    o = None
     for t in range(args.warmup):
         x.copy_(x_all[t])
-        cv.eval_close(x)
+        o = cv.eval_close(x, out=o)
     cv.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(args.steps):
+    for t in range(F):
         x.copy_(x_all[args.warmup + t])
-        cv.eval_close(x)
+        cv.eval_close(x, out=o)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    st = cv.stats()
-    ex = pcv.PathCV(torch.as_tensor(sysm.landmarks, device=dev), cv.lam)
+    cv.close()
+    ex = pcv.PathCV(lm, lam)
+    o_ex = None
+    for t in range(args.warmup):
+        x.copy_(x_all[t])
+        o_ex = ex.eval(x, out=o_ex)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for t in range(args.steps):
+    for t in range(F):
         x.copy_(x_all[args.warmup + t])
-        ex.eval(x)
+        ex.eval(x, out=o_ex)
     torch.cuda.synchronize()
     dt_ex = time.perf_counter() - t1
-    out = {"metric": "close-structure steps/s", "value": round(args.steps / dt, 1), "unit": "steps/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+
+    # Error statistics (untimed): every frame through both paths, distances kept.
+    log("[bench] error pass: close structure and exact on every frame")
+    cv2 = pcv.PathCV(lm, lam, eps=0.01)
+    SZc = torch.empty(F, 2, dtype=torch.float64, device=dev)
+    SZe = torch.empty(F, 2, dtype=torch.float64, device=dev)
+    Dc = torch.empty(F, L, dtype=torch.float64, device=dev)
+    De = torch.empty(F, L, dtype=torch.float64, device=dev)
+    rec = torch.empty(F, dtype=torch.int32, device=dev)
+    gc = {"ds_dx": torch.empty_like(x), "dz_dx": torch.empty_like(x)}
+    ge = {"ds_dx": torch.empty_like(x), "dz_dx": torch.empty_like(x)}
+    for t in range(F):
+        x.copy_(x_all[args.warmup + t])
+        cv2.eval_close(x, out={"sz": SZc[t], "msd": Dc[t], "recomputed": rec[t:t + 1], **gc})
+        ex.eval(x, out={"sz": SZe[t], "msd": De[t], **ge})
+    torch.cuda.synchronize()
+    cv2.check()
+    st = cv2.stats()
+    cv2.close()
+    ex.close()
+    ds = (SZc[:, 0] - SZe[:, 0]).abs()
+    dz = (SZc[:, 1] - SZe[:, 1]).abs()
+    approx = rec == 0
+    na = int(approx.sum().item())
+    gap = Dc[approx] - De[approx]                      # D~_i - D_i on approximate frames
+    rel_tol = 1e-6
+    below = int((gap < -rel_tol * De[approx] - 1e-12).sum().item())
+    a_, b_ = De[approx].flatten(), Dc[approx].flatten()
+    r = float(torch.corrcoef(torch.stack([a_, b_]))[0, 1].item()) if na else float("nan")
+
+    def q(v, p):
+        return float(torch.quantile(v.float(), p).item()) if v.numel() < 16_000_000 else float(v.max().item())
+
+    err = {"frames": F, "recomputes": st["recomputes"], "expensive_msd": st["expensive_msd"],
+           "expensive_msd_per_frame": round(st["expensive_msd"] / F, 4),
+           "mean_frames_between_reassignments": round(F / max(1, st["recomputes"]), 1),
+           "approximate_frames": na,
+           "max_abs_ds": float(ds.max().item()), "p99_abs_ds": q(ds, 0.99), "mean_abs_ds": float(ds.mean().item()),
+           "max_abs_dz": float(dz.max().item()), "p99_abs_dz": q(dz, 0.99), "mean_abs_dz": float(dz.mean().item()),
+           "min_Dtilde_minus_D": float(gap.min().item()) if na else None,
+           "pairs_Dtilde_below_D": below, "pairs_checked": int(gap.numel()),
+           "pearson_r_D_Dtilde": round(r, 6)}
+    log(f"[bench] close: {err}")
+    out = {"metric": "close-structure steps/s", "value": round(F / dt, 1), "unit": "steps/s",
+           "n_gpus": 1, "steps": F, "warmup": args.warmup, "ms_per_step": round(dt / F * 1e3, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 coords, f64 correlation/eigen/lse", "data": "synthetic",
-           "config": {"workload": "close structure (Algorithm 2), 300 atoms x 500 landmarks, random walk "
-                                  "step 0.005 nm, eps 0.01 nm^2", "stats": st,
-                      "exact_steps_per_s": round(args.steps / dt_ex, 1)}}
-    cv.close()
-    ex.close()
+           "config": {"workload": f"close structure (Algorithm 2), 300 atoms x 500 landmarks, random walk "
+                                  f"step 0.005 nm, eps 0.01 nm^2, {F} frames", "lambda": round(lam, 4),
+                      "accuracy_vs_exact": err, "exact_steps_per_s": round(F / dt_ex, 1)}}
     return out
 
 
@@ -455,6 +588,23 @@ def bench_batch(args):
     pairs = sum(w.system.n_atoms * w.system.n_landmarks for w in ws)
     evals = sum(w.system.n_landmarks for w in ws)
     gbs = pairs * 12 / (dt / args.steps) / 1e9
+    # Engine duration from HIP events on its stream (own warm-up, fixed count).
+    for _ in range(KERNEL_WARMUP // 3):
+        b.eval(x)
+    b.set_kernel_timing(True)
+    for _ in range(KERNEL_REPS // 2):
+        b.eval(x)
+    kms, cnt = b.kernel_timing()
+    b.set_kernel_timing(False)
+    kms /= max(cnt, 1)
+    alg_bytes = pairs * 12
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    engine_name = {4: "engine4_kernel", 2: "engine2_kernel", 1: "engine_kernel"}.get(
+        int(str(b.plan).split("engine=")[1][0]) if "engine=" in str(b.plan) else 4, "engine4_kernel")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic("engine_batch_64walkers"),
+            "kernel": f"{engine_name} (64 walkers, one persistent launch)", "kernel_ms": round(kms, 5),
+            "kernel_launches_timed": int(cnt), "algorithmic_bytes_per_launch": alg_bytes}
     out = {"metric": "structure-landmark MSD+grad evals/s", "value": round(evals * args.steps / dt, 1),
            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
@@ -462,7 +612,8 @@ def bench_batch(args):
            "config": {"workload": "64 walkers, atoms U[50,2000], landmarks U[200,5000], one persistent launch",
                       "bytes_per_step": pairs * 12, "plan": b.plan,
                       "plan_source": "autotuner" if args.tune else "heuristic",
-                      "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}}
+                      "step_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
+           "roofline": roof}
     b.close()
     return out
 
@@ -665,7 +816,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="exact",
-                    choices=["exact", "close", "batch", "copy", "surrogate", "mtd", "nl", "props", "f2"])
+                    choices=["exact", "close", "batch", "copy", "stream", "surrogate", "mtd", "nl", "props", "f2"])
     ap.add_argument("--hill-stride", type=int, default=50)
     ap.add_argument("--train-walks", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -679,6 +830,7 @@ def main():
     ap.add_argument("--copy-mb", type=float, default=600.0)
     ap.add_argument("--atoms", type=int, default=5000)
     ap.add_argument("--landmarks", type=int, default=10000)
+    ap.add_argument("--frames", type=int, default=100_000, help="close workload: walk length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-tune", dest="tune", action="store_false",
@@ -692,6 +844,8 @@ def main():
         out = bench_exact(args)
     elif args.workload == "close":
         out = bench_close(args)
+    elif args.workload == "stream":
+        out = bench_stream(args)
     elif args.workload == "copy":
         out = bench_copy(args)
     elif args.workload == "surrogate":

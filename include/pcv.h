@@ -90,7 +90,7 @@ typedef struct pcv_stats {
 
 typedef struct pcv_handle pcv_handle;
 
-/* Default options: device 0, null stream, FP32, eps = 0.01 nm^2, graphs on. */
+/* Default options: device 0, null stream, FP32, eps = 0.01 nm^2, direct launches (use_graph = 0). */
 void pcv_default_options(pcv_options* opt);
 
 /* Create a handle on opt->device.  *out receives the handle (NULL on error). */
@@ -263,7 +263,7 @@ pcv_status pcv_reset_stats(pcv_handle* h);
 pcv_status pcv_check(pcv_handle* h);
 
 /*
- * Tiling of the landmark streaming kernel.  Three engines exist:
+ * Tiling of the landmark streaming kernel.  Five engines exist:
  *   engine 1  teams of `team` lanes, one landmark per team at a time, `apt`
  *             atoms per lane, `wg` threads per workgroup; every lane of a team
  *             takes part in the per-landmark eigen-solve.  Any n up to
@@ -278,6 +278,18 @@ pcv_status pcv_check(pcv_handle* h);
  *           blocks of 256 atoms (apt = 4, 8, 12 or 16, so at most 7 * apt * 64
  *           atoms) and stream them through a private LDS copy ring; one solver
  *           wave; one barrier per landmark.  `team`, `aptg`, `batch` unused.
+ *           The default for 5,633 to 7,168 padded atoms.
+ *   engine 4  FP32 structures of up to 2,048 padded atoms (the default there,
+ *           and the batched walkers' engine): seven worker waves own units
+ *           (landmark lane, 256-atom block), `apt`/4 = 2 or 3 units each, and
+ *           `batch` landmarks (lanes) are processed per step, at most
+ *           floor(7 * (apt / 4) / blocks); one solver wave solves the lanes side
+ *           by side.  `team`, `aptg` unused.
+ *   engine 5  FP32 structures of up to 7 * (apt / 4) * 256 atoms (apt = 4, 8
+ *           or 12): engine 3's blocks and solver with the landmark blocks
+ *           streamed HBM -> registers by range-checked buffer loads (two
+ *           register sets and one LDS slot per worker).  The default for 2,049
+ *           to 5,376 padded atoms.  `team`, `aptg`, `batch` unused.
  * `grid` is an output; `items` <= 0 selects the default number of work items.
  */
 typedef struct pcv_plan {
@@ -305,6 +317,17 @@ pcv_status pcv_set_plan(pcv_handle* h, const pcv_plan* plan);
  */
 pcv_status pcv_set_kernel_timing(pcv_handle* h, int enable);
 pcv_status pcv_get_kernel_timing(pcv_handle* h, double* engine_ms, int64_t* engine_launches);
+
+/*
+ * Streaming-read ceiling of the device (a measurement utility, not part of
+ * the method): reads `bytes` of device memory at src once with the landmark
+ * engines' load path (16-byte non-temporal loads, two sets per wave in
+ * flight, eight waves per workgroup) and writes, per workgroup, the FP64 sum
+ * of its contiguous chunk's floats to wg_sums[0 .. grid).  src must be
+ * 16-byte aligned, bytes a multiple of 16, 1 <= grid <= 65536.  Asynchronous
+ * on `stream` (a hipStream_t or NULL); allocates nothing.
+ */
+pcv_status pcv_stream_read(const void* src, size_t bytes, double* wg_sums, int grid, void* stream);
 
 const char* pcv_status_string(pcv_status s);
 const char* pcv_last_error(const pcv_handle* h);
@@ -347,6 +370,12 @@ pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_path);
 pcv_status pcv_batch_eval(pcv_batch* b, const void* x_all, double* sz_all, void* ds_all, void* dz_all);
 
 /* Description of the chosen plan (static string owned by the batch). */
+/* Kernel timing of the batch's landmark streaming launch (as
+ * pcv_set_kernel_timing / pcv_get_kernel_timing for a single handle: while
+ * enabled, calls run eagerly with HIP events around the engine launch; the
+ * getter synchronises and returns the summed ms and launch count). */
+pcv_status pcv_batch_set_kernel_timing(pcv_batch* b, int enable);
+pcv_status pcv_batch_get_kernel_timing(pcv_batch* b, double* engine_ms, int64_t* engine_launches);
 const char* pcv_batch_plan_string(const pcv_batch* b);
 const char* pcv_batch_last_error(const pcv_batch* b);
 

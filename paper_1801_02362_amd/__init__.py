@@ -100,6 +100,8 @@ def load_library():
         "pcv_batch_plan": (st, [vp, i, ctypes.c_char_p]),
         "pcv_batch_eval": (st, [vp, vp, vp, vp, vp]),
         "pcv_batch_plan_string": (ctypes.c_char_p, [vp]),
+        "pcv_batch_set_kernel_timing": (st, [vp, i]),
+        "pcv_batch_get_kernel_timing": (st, [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)]),
         "pcv_batch_last_error": (ctypes.c_char_p, [vp]),
         "pcv_mlp_create": (st, [ctypes.POINTER(vp), ctypes.POINTER(_Options), i, i, i, vp, vp]),
         "pcv_mlp_destroy": (st, [vp]),
@@ -119,6 +121,7 @@ def load_library():
         "pcv_set_neighbour_list": (st, [vp, i, i]),
         "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
         "pcv_eval_properties_noalloc": (st, [vp, vp, i, vp, vp, vp]),
+        "pcv_stream_read": (st, [vp, ctypes.c_size_t, vp, i, vp]),
         "pcv_set_displacement_weights": (st, [vp, vp]),
         "pcv_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "pcv_load_state": (st, [vp, vp, ctypes.c_size_t]),
@@ -449,6 +452,17 @@ class BatchPathCV:
                                            _ptr(self.ds) if grad else None, _ptr(self.dz) if grad else None))
         return self.sz, self.ds, self.dz
 
+    def set_kernel_timing(self, enable: bool):
+        """HIP-event timing of the landmark streaming launch (eager calls)."""
+        self._check(self._L.pcv_batch_set_kernel_timing(self._b, int(bool(enable))))
+
+    def kernel_timing(self):
+        """(summed engine ms, launches) since timing was enabled."""
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        self._check(self._L.pcv_batch_get_kernel_timing(self._b, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
     def close(self):
         if getattr(self, "_b", None) is not None:
             self._L.pcv_batch_destroy(self._b)
@@ -671,3 +685,18 @@ class Bias:
         out = np.empty((4,) + self.shape, dtype=np.float64)
         self._check(self._L.pcv_bias_get_grid(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+
+def stream_read(buf, wg_sums, grid: int, stream=None):
+    """Read the CUDA tensor ``buf`` once with the engines' load path (the
+    streaming-read ceiling, ``pcv_stream_read``); per-workgroup float sums go
+    to ``wg_sums`` (float64 [grid])."""
+    import torch
+    if not (buf.is_cuda and buf.is_contiguous() and wg_sums.is_cuda and wg_sums.dtype == torch.float64
+            and wg_sums.numel() >= grid):
+        raise ValueError("buf: contiguous CUDA tensor; wg_sums: CUDA float64 tensor of at least grid entries")
+    L = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    s = L.pcv_stream_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(wg_sums), grid, st)
+    if s != 0:
+        raise PcvError(s, L.pcv_status_string(s).decode())

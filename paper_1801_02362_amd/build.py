@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["pcv_kernels.hip", "pcv_engine2.hip", "pcv_engine3.hip", "pcv_engine4.hip", "pcv_api.hip", "pcv_batch.hip", "pcv_mlp.hip", "pcv_bias.hip", "pcv_nl.hip", "pcv_props.hip", "pcv_f2.hip"]
+SOURCES = ["pcv_kernels.hip", "pcv_engine2.hip", "pcv_engine3.hip", "pcv_engine4.hip", "pcv_api.hip", "pcv_batch.hip", "pcv_mlp.hip", "pcv_bias.hip", "pcv_nl.hip", "pcv_props.hip", "pcv_f2.hip", "pcv_ceiling.hip"]
 LIB = os.path.join(PKG, "libpcv.so")
 HOSTTEST_LIB = os.path.join(PKG, "libpcv_hosttest.so")
 

@@ -98,6 +98,9 @@ struct pcv_handle {
   double* Gx32 = nullptr;
   double* xres = nullptr;
   int* status = nullptr;
+  double* corr = nullptr;       // [3 * n_pad / 64][2]: rounding-correction shares of the merges
+  double* corr_prop = nullptr;  // [kPropsMax][3 n / 256]: the same for the property maps
+  unsigned* ticket = nullptr;   // their arrival counter (zero between launches)
   // close structure
   double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
          *Rxy = nullptr, *Dxy = nullptr, *Rsave = nullptr, *gtmp = nullptr, *scratch_sz = nullptr;
@@ -318,6 +321,9 @@ static pcv_status build_plan(pcv_handle* h) {
   base.lam = h->lam;
   base.xw32 = h->xw32;
   base.n_x = h->n_x;
+  base.x_rounded = (!h->fp64 && p.engine != 1) ? 1 : 0;
+  base.corr = h->corr;
+  base.ticket = h->ticket;
   // Entry 3: the property maps' exact pass (rotations saved to their own buffer).
   Problem props_prob = base;
   props_prob.Rsave = h->Rprop;
@@ -517,7 +523,7 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   h->nl_stride = 0;
   h->nl_step = 0;
   h->propmem.release();
-  h->Wprop = h->part_prop = nullptr;
+  h->Wprop = h->part_prop = h->corr_prop = nullptr;
   h->f2mem.release();
   h->wd = nullptr;
   h->pmem.release();
@@ -545,6 +551,9 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->Gx32, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->xres, 3 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
+  HIP_TRY(h, m.alloc((void**)&h->corr, 6 * (np / 64) * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->ticket, sizeof(unsigned)));
+  HIP_TRY(h, hipMemset(h->ticket, 0, sizeof(unsigned)));
   HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Fxy, 10 * sizeof(double)));
@@ -931,13 +940,22 @@ extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, v
 
 // Property maps: the exact pass with rotations and distances saved, then the
 // shared weights, every component and all P gradients (pcv_props.hip).
+static PropsArgs props_args(const pcv_handle* h, int P, double* corr) {
+  PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+  a.xw = h->xw;
+  a.x_rounded = (!h->fp64 && h->plan.engine != 1) ? 1 : 0;
+  a.corr = corr;
+  a.ticket = h->ticket;
+  return a;
+}
+
 template <typename T>
 static hipError_t enqueue_props(pcv_handle* h, hipStream_t st, const void* x, int P, const double* q, double* S,
                                 void* dS) {
   hipError_t e = launch_prep<T>(h->d_prep, x, 1, h->n, st);
   if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
   if (e != hipSuccess) return e;
-  PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+  const PropsArgs a = props_args(h, P, h->corr_prop);
   return launch_props<T>(a, q, h->lam, S, h->Wprop, h->part_prop, dS, st);
 }
 
@@ -954,6 +972,7 @@ extern "C" pcv_status pcv_eval_properties(pcv_handle* h, const void* x, int P, c
     const size_t chunks = props_chunks(h->n_pad, h->L);
     HIP_TRY(h, h->propmem.alloc((void**)&h->Wprop, (size_t)h->L * kPropsMax * sizeof(double)));
     HIP_TRY(h, h->propmem.alloc((void**)&h->part_prop, chunks * kPropsMax * 3 * (size_t)h->n_pad * sizeof(double)));
+    HIP_TRY(h, h->propmem.alloc((void**)&h->corr_prop, (size_t)props_corr_doubles(h->n) * kPropsMax * sizeof(double)));
   }
   const void* key[7] = {x, q, S, dS_dx, (const void*)(uintptr_t)P, nullptr, (const void*)7};
   return run_maybe_graph(h, key, [&](hipStream_t st) {
@@ -975,27 +994,29 @@ extern "C" pcv_status pcv_eval_properties_noalloc(pcv_handle* h, const void* x, 
   if (h->wd) return fail(h, PCV_EUNSUPPORTED, "property maps with displacement weights");
   const size_t chunks = props_chunks(h->n_pad, h->L);
   const size_t w_bytes = ((size_t)h->L * P * sizeof(double) + 255) / 256 * 256;
-  const size_t part_bytes = chunks * P * 3 * (size_t)h->n_pad * sizeof(double);
-  if (w_bytes + part_bytes > kScratchBytes)
+  const size_t part_bytes = (chunks * P * 3 * (size_t)h->n_pad * sizeof(double) + 255) / 256 * 256;
+  const size_t corr_bytes = (size_t)props_corr_doubles(h->n) * P * sizeof(double);
+  if (w_bytes + part_bytes + corr_bytes > kScratchBytes)
     return fail(h, PCV_EINVAL,
-                "property maps need " + std::to_string(w_bytes + part_bytes) + " bytes of scratch; the fixed array holds " +
-                    std::to_string(kScratchBytes));
+                "property maps need " + std::to_string(w_bytes + part_bytes + corr_bytes) +
+                    " bytes of scratch; the fixed array holds " + std::to_string(kScratchBytes));
   unsigned char* base = (unsigned char*)scratch_ptr(h->opt.device);
   if (!base) return fail(h, PCV_ESTATE, "no scratch address for this device");
   double* W = (double*)base;
   double* part = (double*)(base + w_bytes);
+  double* corr = (double*)(base + w_bytes + part_bytes);
   HIP_TRY(h, hipSetDevice(h->opt.device));
   const hipStream_t st = h->stream;
   hipError_t e;
   if (h->fp64) {
     e = launch_prep<double>(h->d_prep, x, 1, h->n, st);
     if (e == hipSuccess) e = engine_launch<double>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
-    PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+    const PropsArgs a = props_args(h, P, corr);
     if (e == hipSuccess) e = launch_props<double>(a, q, h->lam, S, W, part, dS_dx, st);
   } else {
     e = launch_prep<float>(h->d_prep, x, 1, h->n, st);
     if (e == hipSuccess) e = engine_launch<float>(h, st, MODE_EXACT_SAVE, nullptr, 0, h->Dprop, false, 3);
-    PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
+    const PropsArgs a = props_args(h, P, corr);
     if (e == hipSuccess) e = launch_props<float>(a, q, h->lam, S, W, part, dS_dx, st);
   }
   if (e != hipSuccess) return hip_fail(h, e, "property maps (fixed scratch)");
@@ -1188,14 +1209,15 @@ extern "C" pcv_status pcv_load_state(pcv_handle* h, const void* buf, size_t byte
 
 // Token naming a handle and its current buffers (for callers that cache
 // hipGraphs capturing the handle's kernels).
-extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h) {
+extern "C" __attribute__((visibility("hidden"))) unsigned long long pcv_internal_handle_token(const pcv_handle* h) {
   return (h->serial << 32) ^ (unsigned long long)(unsigned)h->plan_version;
 }
 
 // Exact half of the surrogate's fallback step: the close-structure drift test
 // and, on a reassignment, the exact pass (no Eq. 5 branch).  Returns the
 // device flag the surrogate's tail kernel reads.
-extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
+extern "C" __attribute__((visibility("hidden"))) hipError_t pcv_internal_exact_for_surrogate(
+    pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
                                                        double* sz, void* ds, void* dz, const int** flag) {
   if (h->fp64 || h->L == 0 || h->n != n_atoms) return hipErrorInvalidValue;
   if (h->wd) return hipErrorNotSupported;

@@ -65,6 +65,9 @@ struct pcv_batch {
   float* xw32 = nullptr;      // FP32 batches: [3][n_x] per walker (engine 4)
   std::vector<size_t> x32_off;
   int* status = nullptr;
+  double* corr = nullptr;       // per walker [3 * n_pad / 64][2]: rounding-correction shares of the merge
+  unsigned* ticket = nullptr;   // [W] their arrival counters (zero between launches)
+  std::vector<size_t> corr_off;
   PrepArgs* d_prep = nullptr;
   // plan
   BatchPlan plan;
@@ -86,7 +89,25 @@ struct pcv_batch {
   };
   std::vector<GraphEntry> graphs;
   std::string plan_str, err;
+  // kernel timing (eager launches, events around the engine launch)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  double timed_ms = 0.0;
+  long long timed_launches = 0;
 };
+
+static void bcollect_timing(pcv_batch* b) {
+  for (auto& pr : b->ev_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      b->timed_ms += ms;
+      ++b->timed_launches;
+    }
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  b->ev_pending.clear();
+}
 
 static pcv_status bfail(pcv_batch* b, pcv_status s, const std::string& m) {
   if (b) b->err = m;
@@ -134,6 +155,7 @@ extern "C" pcv_status pcv_batch_destroy(pcv_batch* b) {
   if (!b) return PCV_OK;
   (void)hipSetDevice(b->opt.device);
   (void)hipStreamSynchronize(b->stream);
+  bcollect_timing(b);
   bdrop_graphs(b);
   b->pmem.release();
   b->mem.release();
@@ -195,6 +217,11 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
   BHIP_TRY(b, m.alloc((void**)&b->Gx32, W * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->xres, 3 * W * sizeof(double)));
   BHIP_TRY(b, m.alloc((void**)&b->status, W * sizeof(int)));
+  b->corr_off.assign(W + 1, 0);
+  for (int i = 0; i < W; ++i) b->corr_off[i + 1] = b->corr_off[i] + 6 * (size_t)(b->n_pad[i] / 64);
+  BHIP_TRY(b, m.alloc((void**)&b->corr, b->corr_off[W] * sizeof(double)));
+  BHIP_TRY(b, m.alloc((void**)&b->ticket, W * sizeof(unsigned)));
+  BHIP_TRY(b, hipMemset(b->ticket, 0, W * sizeof(unsigned)));
   BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
   b->x32_off.assign(W + 1, 0);
   for (int i = 0; i < W; ++i) b->x32_off[i + 1] = b->x32_off[i] + 3 * (size_t)round_up(b->n_pad[i], 256);
@@ -363,6 +390,9 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.out_off = b->atom_off[i];
     P.out_idx = i;
     P.lam = b->lam[i];
+    P.x_rounded = (!b->fp64 && p.engine != 1) ? 1 : 0;
+    P.corr = b->corr + b->corr_off[i];
+    P.ticket = b->ticket + i;
     probs[i] = P;
     a_off += (size_t)b->L[i] * 3 * b->n_pad[i];
   }
@@ -385,6 +415,12 @@ template <typename T>
 static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, double* sz, void* ds, void* dz) {
   hipError_t e = launch_prep<T>(b->d_prep, x, b->W, *std::max_element(b->n.begin(), b->n.end()), st);
   if (e != hipSuccess) return e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->timing) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, st);
+  }
   if (b->plan.engine == 4)
     e = launch_engine4<T>(b->plan.spw, b->grid, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st);
   else
@@ -393,6 +429,10 @@ static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, dou
                               b->d_items, b->d_wgoff, MODE_EXACT, nullptr, 0, nullptr, st)
           : launch_engine<T>(b->plan.cfg, b->grid, b->lds, b->d_prob, b->d_items, b->d_wgoff, MODE_EXACT, nullptr,
                              0, nullptr, st);
+  if (b->timing) {
+    (void)hipEventRecord(e1, st);
+    b->ev_pending.emplace_back(e0, e1);
+  }
   if (e != hipSuccess) return e;
   Outs o{ds, dz, sz, nullptr};
   return launch_merge_exact<T>(b->d_prob, o, b->W, b->max_n_pad, nullptr, 0, st);
@@ -402,7 +442,7 @@ static pcv_status batch_run(pcv_batch* b, const void* x, double* sz, void* ds, v
   auto enq = [&](hipStream_t st) {
     return b->fp64 ? batch_enqueue<double>(b, st, x, sz, ds, dz) : batch_enqueue<float>(b, st, x, sz, ds, dz);
   };
-  if (!b->opt.use_graph || !allow_graph) {
+  if (!b->opt.use_graph || !allow_graph || b->timing) {
     hipError_t e = enq(b->stream);
     return e == hipSuccess ? PCV_OK : bhip(b, e, "batch enqueue");
   }
@@ -564,44 +604,99 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
   BHIP_TRY(b, hipSetDevice(b->opt.device));
   const BatchPlan base = heuristic_plan(b);
   const std::string key = shape_key(b);
-  BatchPlan cached;
-  if (tune && cache_lookup(cache_path, key, &cached)) {
-    if (batch_apply(b, cached) == PCV_OK) return PCV_OK;
-  }
   pcv_status s = batch_apply(b, base);
   if (s != PCV_OK || !tune) return s;
 
-  // Autotune: reference outputs from the heuristic plan, then every candidate.
+  // Reference outputs of the heuristic plan on probe structures; a plan is
+  // eligible (a cached one included) only if its s, z and both gradients
+  // match them.
   const size_t tsz = b->fp64 ? 8 : 4;
   const int natoms = b->atom_off[b->W];
-  void *x = nullptr, *ds = nullptr, *ds_ref = nullptr;
+  void *x = nullptr, *ds = nullptr, *dz = nullptr, *ds_ref = nullptr, *dz_ref = nullptr;
   double *sz = nullptr, *sz_ref = nullptr;
   DevMem tmp;
   BHIP_TRY(b, tmp.alloc(&x, (size_t)natoms * 3 * tsz));
   BHIP_TRY(b, tmp.alloc(&ds, (size_t)natoms * 3 * tsz));
+  BHIP_TRY(b, tmp.alloc(&dz, (size_t)natoms * 3 * tsz));
   BHIP_TRY(b, tmp.alloc(&ds_ref, (size_t)natoms * 3 * tsz));
+  BHIP_TRY(b, tmp.alloc(&dz_ref, (size_t)natoms * 3 * tsz));
   BHIP_TRY(b, tmp.alloc((void**)&sz, (size_t)b->W * 2 * sizeof(double)));
   BHIP_TRY(b, tmp.alloc((void**)&sz_ref, (size_t)b->W * 2 * sizeof(double)));
   {
-    // Probe structures: the first landmark of every walker (as stored).
+    // Probe structures: the midpoint of every walker's first two landmarks
+    // (as stored) moved by a fixed pattern of up to 2 pm per coordinate, so
+    // the weights spread over several landmarks and every gradient term is
+    // exercised.
     size_t a_off = 0;
-    std::vector<char> host((size_t)natoms * 3 * tsz);
+    std::vector<double> host((size_t)natoms * 3);
     for (int i = 0; i < b->W; ++i) {
-      std::vector<char> soa((size_t)3 * b->n_pad[i] * tsz);
+      const int n_pad = b->n_pad[i];
+      const int two = b->L[i] >= 2 ? 2 : 1;
+      std::vector<char> soa((size_t)two * 3 * n_pad * tsz);
       BHIP_TRY(b, hipMemcpy(soa.data(), (const char*)b->A + a_off * tsz, soa.size(), hipMemcpyDeviceToHost));
+      auto at = [&](int l, int d, int j) {
+        const size_t k = ((size_t)l * 3 + d) * n_pad + j;
+        return b->fp64 ? ((const double*)soa.data())[k] : (double)((const float*)soa.data())[k];
+      };
       for (int j = 0; j < b->n[i]; ++j)
-        for (int d = 0; d < 3; ++d)
-          std::memcpy(&host[((size_t)(b->atom_off[i] + j) * 3 + d) * tsz],
-                      &soa[((size_t)d * b->n_pad[i] + j) * tsz], tsz);
-      a_off += (size_t)b->L[i] * 3 * b->n_pad[i];
+        for (int d = 0; d < 3; ++d) {
+          const double mid = 0.5 * (at(0, d, j) + at(two - 1, d, j));
+          const double pattern = 0.002 * ((double)((j * 7 + d * 3 + i) % 11) - 5.0) / 5.0;
+          host[(size_t)(b->atom_off[i] + j) * 3 + d] = mid + pattern;
+        }
+      a_off += (size_t)b->L[i] * 3 * n_pad;
     }
-    BHIP_TRY(b, hipMemcpy(x, host.data(), host.size(), hipMemcpyHostToDevice));
+    if (b->fp64) {
+      BHIP_TRY(b, hipMemcpy(x, host.data(), host.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> h32(host.begin(), host.end());
+      BHIP_TRY(b, hipMemcpy(x, h32.data(), h32.size() * 4, hipMemcpyHostToDevice));
+    }
   }
-  s = batch_run(b, x, sz_ref, ds_ref, nullptr, false);
+  s = batch_run(b, x, sz_ref, ds_ref, dz_ref, false);
   if (s != PCV_OK) return s;
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
   std::vector<double> hsz_ref(2 * b->W), hsz(2 * b->W);
   BHIP_TRY(b, hipMemcpy(hsz_ref.data(), sz_ref, hsz_ref.size() * sizeof(double), hipMemcpyDeviceToHost));
+  auto to_f64 = [&](const void* dev_p, std::vector<double>& out) -> bool {
+    out.resize((size_t)natoms * 3);
+    if (b->fp64) return hipMemcpy(out.data(), dev_p, out.size() * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    std::vector<float> t(out.size());
+    if (hipMemcpy(t.data(), dev_p, t.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return false;
+    std::copy(t.begin(), t.end(), out.begin());
+    return true;
+  };
+  std::vector<double> hds_ref, hdz_ref, hds, hdz;
+  if (!to_f64(ds_ref, hds_ref) || !to_f64(dz_ref, hdz_ref)) return bfail(b, PCV_EHIP, "autotuner reference copy");
+  // The applied plan reproduces the reference: s and z to 1e-7 (relative to
+  // 1 + |value|), each walker's gradients to 1e-5 of its largest entry.
+  auto matches = [&]() -> bool {
+    if (batch_run(b, x, sz, ds, dz, false) != PCV_OK) return false;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return false;
+    if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return false;
+    for (int i = 0; i < 2 * b->W; ++i)
+      if (!(std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i])))) return false;
+    if (!to_f64(ds, hds) || !to_f64(dz, hdz)) return false;
+    for (int w = 0; w < b->W; ++w) {
+      const size_t a0 = (size_t)b->atom_off[w] * 3, a1 = (size_t)b->atom_off[w + 1] * 3;
+      for (int g = 0; g < 2; ++g) {
+        const std::vector<double>& r = g ? hdz_ref : hds_ref;
+        const std::vector<double>& v = g ? hdz : hds;
+        double scale = 0.0;
+        for (size_t k = a0; k < a1; ++k) scale = std::max(scale, std::fabs(r[k]));
+        for (size_t k = a0; k < a1; ++k)
+          if (!(std::fabs(v[k] - r[k]) <= 1e-5 * scale + 1e-12)) return false;
+      }
+    }
+    return true;
+  };
+  // A cached plan is applied only after it reproduces the reference here.
+  BatchPlan cached;
+  if (cache_lookup(cache_path, key, &cached)) {
+    if (batch_apply(b, cached) == PCV_OK && matches()) return PCV_OK;
+    s = batch_apply(b, base);
+    if (s != PCV_OK) return s;
+  }
 
   EngineCfg menu[16];
   int cnt = 0;
@@ -660,18 +755,13 @@ extern "C" pcv_status pcv_batch_plan(pcv_batch* b, int tune, const char* cache_p
     (void)hipEventElapsedTime(&ms, e0, e1);
     return ms / reps;
   };
-  // Screen: every candidate whose s and z match the heuristic plan's, three
-  // runs each.  Then the three fastest are timed again, ten runs in each of
-  // three interleaved rounds, and the best round decides.
+  // Screen: every candidate whose s, z and gradients match the heuristic
+  // plan's, three runs each.  Then the three fastest are timed again, ten
+  // runs in each of three interleaved rounds, and the best round decides.
   std::vector<std::pair<float, int>> screened;
   for (int k = 0; k < (int)cands.size(); ++k) {
     if (batch_apply(b, cands[k]) != PCV_OK) continue;
-    if (batch_run(b, x, sz, ds, nullptr, false) != PCV_OK) continue;
-    if (hipStreamSynchronize(b->stream) != hipSuccess) continue;
-    if (hipMemcpy(hsz.data(), sz, hsz.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) continue;
-    bool ok = true;
-    for (int i = 0; i < 2 * b->W && ok; ++i) ok = std::fabs(hsz[i] - hsz_ref[i]) <= 1e-7 * (1 + std::fabs(hsz_ref[i]));
-    if (!ok) continue;
+    if (!matches()) continue;
     screened.emplace_back(time_runs(3), k);
   }
   std::sort(screened.begin(), screened.end());
@@ -706,6 +796,25 @@ extern "C" pcv_status pcv_batch_eval(pcv_batch* b, const void* x_all, double* sz
     if (s != PCV_OK) return s;
   }
   return batch_run(b, x_all, sz_all, ds_all, dz_all, true);
+}
+
+extern "C" pcv_status pcv_batch_set_kernel_timing(pcv_batch* b, int enable) {
+  if (!b) return PCV_EINVAL;
+  BHIP_TRY(b, hipSetDevice(b->opt.device));
+  bcollect_timing(b);
+  b->timing = enable != 0;
+  b->timed_ms = 0.0;
+  b->timed_launches = 0;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_batch_get_kernel_timing(pcv_batch* b, double* engine_ms, int64_t* engine_launches) {
+  if (!b || !engine_ms || !engine_launches) return PCV_EINVAL;
+  BHIP_TRY(b, hipSetDevice(b->opt.device));
+  bcollect_timing(b);
+  *engine_ms = b->timed_ms;
+  *engine_launches = b->timed_launches;
+  return PCV_OK;
 }
 
 extern "C" const char* pcv_batch_plan_string(const pcv_batch* b) { return b ? b->plan_str.c_str() : ""; }

@@ -41,6 +41,15 @@ struct Problem {
   double lam;
   const float* xw32;    // [3][n_x] w_j x_c,j rounded to FP32, zero past n (large-structure engine)
   int n_x;              // plane stride of xw32: n_pad rounded up to 256
+  // FP32 engines 2-5 contract with fl32(w_j x_c,j): their distances, s and z
+  // are those of the structure x' = fl32(w x_c) / w.  With x_rounded set,
+  // the exact merges add the first-order difference dS/dx . (x - x') to s
+  // and z: each merge workgroup leaves its share in corr ([3 tiles][2]) and
+  // counts itself in *ticket; the last one adds the shares in index order,
+  // writes (s, z) and returns *ticket to 0.
+  int x_rounded;
+  double* corr;
+  unsigned* ticket;
 };
 
 struct Item {
@@ -252,9 +261,19 @@ struct PropsArgs {
   const double* D;      // [L] distances of the exact pass
   const double* w;      // [n_pad] normalised weights
   int L, n, n_pad, P;
+  // With x_rounded (FP32 engines, see Problem::x_rounded) the gradient pass
+  // always runs and S_k gains dS_k/dx . (x - x'): xw is w x_c in FP64
+  // ([3][n_pad]), corr holds props_corr_doubles(n) shares per component and
+  // ticket counts the reduce workgroups.
+  const double* xw;
+  int x_rounded;
+  double* corr;
+  unsigned* ticket;
 };
 // Landmark chunks of the gradient pass (its partials: chunks x P x 3 x n_pad doubles).
 int props_chunks(int n_pad, int L);
+// Reduce workgroups per component (the rounding-correction shares per component).
+int props_corr_doubles(int n);
 // S [P] (device), W [L][P] scratch, part scratch, dS [P][n][3] or null.
 template <typename T>
 hipError_t launch_props(const PropsArgs& a, const double* q, double lam, double* S, double* W, double* part,

@@ -660,6 +660,60 @@ __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, d
   S = v[1];
 }
 
+// Rounding correction of one merge workgroup (see Problem::x_rounded),
+// called by its whole first wave: lane a holds, for its atom j and the
+// workgroup's coordinate c, ds_j,c d_j,c and dz_j,c d_j,c with
+// d = x - x' = (w x_c - fl32(w x_c)) / w (zero for atoms past n).  blk is the
+// workgroup's index among the nblk that serve the problem.  The last to
+// arrive writes s + sum and z + sum; the sums run in block order, so the
+// result does not depend on arrival order.
+__device__ void sz_rounding_correction(const Problem& P, const Outs& o, double s, double z, double cs, double cz,
+                                       int blk, int nblk) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 32; off >= 1; off >>= 1) {
+    cs += __shfl_xor(cs, off, 64);
+    cz += __shfl_xor(cz, off, 64);
+  }
+  unsigned t = 0;
+  if (lane == 0) {
+    stg(P.corr + 2 * (size_t)blk, cs);
+    stg(P.corr + 2 * (size_t)blk + 1, cz);
+    t = __hip_atomic_fetch_add(P.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  t = __shfl(t, 0, 64);
+  if (t != (unsigned)nblk - 1) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double as = 0.0, az = 0.0;
+  for (int b = lane; b < nblk; b += 64) {
+    as += __hip_atomic_load(P.corr + 2 * (size_t)b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    az += __hip_atomic_load(P.corr + 2 * (size_t)b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    as += __shfl_xor(as, off, 64);
+    az += __shfl_xor(az, off, 64);
+  }
+  if (lane == 0) {
+    o.sz[2 * P.out_idx + 0] = s + as;
+    o.sz[2 * P.out_idx + 1] = z + az;
+    __hip_atomic_store(P.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// This workgroup's terms of the correction for atom j, coordinate c, given
+// the gradient sums gs, gz the merge formed for it.
+__device__ __forceinline__ void rounding_terms(const Problem& P, int j, int c, double gs, double gz, double Z,
+                                               double& cs, double& cz) {
+  cs = 0.0;
+  cz = 0.0;
+  if (j >= P.n) return;
+  const double wj = P.w[j];
+  const double xw = P.xw[(size_t)c * P.n_pad + j];
+  const double dw = xw - (double)(float)xw;   // w_j (x - x')_j,c
+  if (wj <= 0.0 || dw == 0.0) return;
+  cs = 2.0 * P.lam * gs / Z * dw;             // ds/dx_j,c (x - x')_j,c
+  cz = 2.0 * (xw / wj - gz / Z) * dw;         // dz/dx_j,c (x - x')_j,c
+}
+
 // Algorithm 1 merge: s, z (Eq. 2) and, with r_ik the rotated centred
 // landmarks, ds/dx_k = -2 lambda w_k sum_i p_i (q_i - s)(x_k - r_ik)
 //                    = (2 lambda w_k / Z) sum_g f_g (U_g + (q0_g - s) V_g),
@@ -727,17 +781,24 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   red[0][sg][a] = gs;
   red[1][sg][a] = gz;
   __syncthreads();
-  if (sg == 0 && j < P.n) {
+  if (sg == 0) {
     gs = ((red[0][0][a] + red[0][1][a]) + red[0][2][a]) + red[0][3][a];
     gz = ((red[1][0][a] + red[1][1][a]) + red[1][2][a]) + red[1][3][a];
-    const double wj = P.w[j];
-    const size_t at = 3 * ((size_t)P.out_off + j) + c;
-    if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * gs / Z);
-    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * gz / Z));
-  }
-  if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
-    o.sz[2 * P.out_idx + 0] = s;
-    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+    if (j < P.n) {
+      const double wj = P.w[j];
+      const size_t at = 3 * ((size_t)P.out_off + j) + c;
+      if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * gs / Z);
+      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * gz / Z));
+    }
+    if (P.x_rounded) {
+      double cs, cz;
+      rounding_terms(P, j, c, gs, gz, Z, cs, cz);
+      const int tiles = (P.n + 63) / 64;
+      sz_rounding_correction(P, o, s, m - log(Z) / P.lam, cs, cz, c * tiles + (int)blockIdx.x, 3 * tiles);
+    } else if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
+      o.sz[2 * P.out_idx + 0] = s;
+      o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+    }
   }
 }
 
@@ -801,20 +862,26 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int 
   xred[0][sg][a] = gs;
   xred[1][sg][a] = gz;
   __syncthreads();
-  if (sg == 0 && j < P.n) {
+  if (sg == 0) {
     double ts = 0.0, tz = 0.0;
     for (int q = 0; q < NG; ++q) {
       ts += xred[0][q][a];
       tz += xred[1][q][a];
     }
-    const double wj = P.w[j];
-    const size_t at = 3 * ((size_t)P.out_off + j) + c;
-    if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * ts / Z);
-    if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * tz / Z));
-  }
-  if (tile == 0 && c == 0 && threadIdx.x == 0) {
-    o.sz[2 * P.out_idx + 0] = s;
-    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+    if (j < P.n) {
+      const double wj = P.w[j];
+      const size_t at = 3 * ((size_t)P.out_off + j) + c;
+      if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * ts / Z);
+      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * tz / Z));
+    }
+    if (P.x_rounded) {
+      double cs, cz;
+      rounding_terms(P, j, c, ts, tz, Z, cs, cz);
+      sz_rounding_correction(P, o, s, m - log(Z) / P.lam, cs, cz, c * (int)gridDim.x + tile, 3 * (int)gridDim.x);
+    } else if (tile == 0 && c == 0 && threadIdx.x == 0) {
+      o.sz[2 * P.out_idx + 0] = s;
+      o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+    }
   }
 }
 

@@ -895,9 +895,10 @@ extern "C" pcv_status pcv_mlp_eval(pcv_mlp* m, const float* x, int B, double* sz
 }
 
 // ---- fallback step (uses the exact handle's close-structure drift test)
-extern "C" hipError_t pcv_internal_exact_for_surrogate(pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
+extern "C" __attribute__((visibility("hidden"))) hipError_t pcv_internal_exact_for_surrogate(
+    pcv_handle* h, int n_atoms, hipStream_t st, const void* x,
                                                        double* sz, void* ds, void* dz, const int** flag);
-extern "C" unsigned long long pcv_internal_handle_token(const pcv_handle* h);
+extern "C" __attribute__((visibility("hidden"))) unsigned long long pcv_internal_handle_token(const pcv_handle* h);
 
 extern "C" pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, double* sz, float* ds_dx,
                                    float* dz_dx, int* used_surrogate) {

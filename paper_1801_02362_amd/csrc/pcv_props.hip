@@ -134,34 +134,73 @@ __global__ __launch_bounds__(256) void props_grad_kernel(PropsArgs a, const doub
   }
 }
 
-// dS_k/dx_j = w_j * (chunk partials added in chunk order).  The loads are
-// issued eight at a time (independent of the running sum), so a thread waits
-// for one round trip per eight chunks rather than per chunk.
+// dS_k/dx_j = w_j * (chunk partials added in chunk order); grid (3 n / 256
+// rounded up, P), one component per row.  The loads are issued eight at a
+// time (independent of the running sum), so a thread waits for one round
+// trip per eight chunks rather than per chunk.  With x_rounded every
+// workgroup also forms its share of dS_k/dx . (x - x') (x - x' =
+// (w x_c - fl32(w x_c)) / w, so the share is the chunk sum times that
+// residual); the last to arrive adds the shares of each component in block
+// order to S_k and returns the ticket to 0.
 template <typename T>
 __global__ __launch_bounds__(256) void props_reduce_kernel(PropsArgs a, int chunks, const double* __restrict__ part,
-                                                           T* __restrict__ dS) {
-  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const size_t total = (size_t)a.P * a.n * 3;
-  if (idx >= total) return;
-  const int k = (int)(idx / ((size_t)a.n * 3));
-  const int rem = (int)(idx - (size_t)k * a.n * 3);
-  const int j = rem / 3, d = rem - 3 * j;
-  const size_t stride = (size_t)a.P * 3 * a.n_pad;
-  const double* p = part + ((size_t)k * 3 + d) * a.n_pad + j;
-  double s = 0.0;
-  int c = 0;
-  for (; c + 8 <= chunks; c += 8) {
-    double v[8];
+                                                           T* __restrict__ dS, double* __restrict__ S) {
+  __shared__ double sh[4];
+  __shared__ int last;
+  const int k = blockIdx.y;
+  const int n3 = 3 * a.n;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double term = 0.0;
+  if (r < n3) {
+    const int j = r / 3, d = r - 3 * j;
+    const size_t stride = (size_t)a.P * 3 * a.n_pad;
+    const double* p = part + ((size_t)k * 3 + d) * a.n_pad + j;
+    double s = 0.0;
+    int c = 0;
+    for (; c + 8 <= chunks; c += 8) {
+      double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + u) * stride];
+      for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(c + u) * stride];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < chunks; ++c) s += p[(size_t)c * stride];
+    if (dS) dS[(size_t)k * n3 + r] = (T)(a.w[j] * s);
+    if (a.x_rounded) {
+      const double xw = a.xw[(size_t)d * a.n_pad + j];
+      term = s * (xw - (double)(float)xw);
+    }
   }
-  for (; c < chunks; ++c) s += p[(size_t)c * stride];
-  dS[idx] = (T)(a.w[j] * s);
+  if (!a.x_rounded) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
+  if (lane == 0) sh[wave] = term;
+  __syncthreads();
+  const int nbx = gridDim.x, nblk = gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    stg(a.corr + (size_t)k * nbx + blockIdx.x, ((sh[0] + sh[1]) + sh[2]) + sh[3]);
+    const unsigned t = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == (unsigned)nblk - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  for (int k2 = 0; k2 < a.P; ++k2) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nbx; b += 256)
+      v += __hip_atomic_load(a.corr + (size_t)k2 * nbx + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) S[k2] += ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
+
+int props_corr_doubles(int n) { return (3 * n + 255) / 256; }
 
 int props_chunks(int n_pad, int L) {
   const int tiles = (n_pad + 63) / 64;
@@ -176,14 +215,13 @@ hipError_t launch_props(const PropsArgs& a, const double* q, double lam, double*
   if (a.P < 1 || a.P > kPropsMax || a.L < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(props_lse_kernel, dim3(1), dim3(kLseThreads), 0, st, a.D, a.L, a.P, q, lam, S, W);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || dS == nullptr) return e;
+  if (e != hipSuccess || (dS == nullptr && !a.x_rounded)) return e;
   const int chunks = props_chunks(a.n_pad, a.L);
   hipLaunchKernelGGL((props_grad_kernel<T>), dim3((a.n_pad + 63) / 64, chunks), dim3(256), 0, st, a, W, part);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t total = (size_t)a.P * a.n * 3;
-  hipLaunchKernelGGL((props_reduce_kernel<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, chunks,
-                     part, (T*)dS);
+  hipLaunchKernelGGL((props_reduce_kernel<T>), dim3(props_corr_doubles(a.n), a.P), dim3(256), 0, st, a, chunks,
+                     part, (T*)dS, S);
   return hipGetLastError();
 }
 

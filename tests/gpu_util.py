@@ -39,3 +39,26 @@ def check_cv(name, tol, sz, ds, dz, D, ref, *, grads=True):
             e = np.abs(g - r).max()
             scale = np.abs(r).max()
             assert e <= tol["grad"] * scale + 1e-12, f"{name}: {what} err {e:.3e} scale {scale:.3e}"
+
+
+# Oracle jobs for a process pool (spawned children run NumPy only; they
+# never touch the GPU).
+def _lam_job(lm):
+    from oracle.path import landmark_lambda
+    return landmark_lambda(lm)
+
+
+def _cv_job(args):
+    from oracle.path import path_cv
+    frame, lm, lam = args
+    r = path_cv(np.asarray(frame, dtype=np.float64), np.asarray(lm, dtype=np.float64), lam)
+    return r
+
+
+def oracle_pool():
+    """A pool of at most 16 spawned processes for oracle work."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    return cf.ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)),
+                                  mp_context=mp.get_context("spawn"))

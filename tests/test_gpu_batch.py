@@ -56,27 +56,30 @@ def test_batch_equals_single_handles():
     b.close()
 
 
-def test_full_64_walker_batch_sampled_walkers():
+def test_full_64_walker_batch_every_walker():
     """The 64-walker batch the bench times (atoms U[50, 2000], landmarks
-    U[200, 5000], one persistent launch, default plan): eight walkers
-    spread over the launch checked against the oracle in full, and every
-    walker's s within [1, L] with finite gradients."""
+    U[200, 5000], one persistent launch, default plan): every walker's s, z
+    and both gradients checked against the oracle in full (the oracle runs
+    in a pool of processes while the GPU works)."""
     import paper_1801_02362_amd as pcv
     import torch
-    from gpu_util import TOL32, check_cv, dev, host, say
+    from gpu_util import TOL32, _cv_job, _lam_job, check_cv, dev, host, oracle_pool, say
     ws = wl.walkers(n_walkers=64, n_frames=1)
-    lams = [landmark_lambda(w.system.landmarks) for w in ws]
-    b = pcv.BatchPathCV([dev(w.system.landmarks, torch.float32) for w in ws], lams)
-    say(f"[batch] full 64 walkers, plan {b.plan}")
-    x = dev(np.concatenate([w.frames[0] for w in ws]), torch.float32)
-    sz, ds, dz = b.eval(x)
-    sz, ds, dz = host(sz), host(ds), host(dz)
-    b.close()
-    for i, w in enumerate(ws):
-        assert 1.0 <= sz[i][0] <= w.system.n_landmarks, f"walker{i}: s out of range"
-    assert np.isfinite(ds).all() and np.isfinite(dz).all()
-    for i in (0, 9, 18, 27, 36, 45, 54, 63):
-        w = ws[i]
-        ref = path_cv(w.frames[0].astype(np.float64), w.system.landmarks.astype(np.float64), lams[i])
-        a0, a1 = b.atom_off[i], b.atom_off[i + 1]
-        check_cv(f"walker{i}", TOL32, sz[i], ds[a0:a1], dz[a0:a1], None, ref)
+    order = sorted(range(len(ws)), key=lambda i: -ws[i].system.n_atoms * ws[i].system.n_landmarks)
+    with oracle_pool() as pool:
+        lam_f = {i: pool.submit(_lam_job, ws[i].system.landmarks) for i in order}
+        lams = [lam_f[i].result() for i in range(len(ws))]
+        ref_f = {i: pool.submit(_cv_job, (ws[i].frames[0], ws[i].system.landmarks, lams[i])) for i in order}
+        b = pcv.BatchPathCV([dev(w.system.landmarks, torch.float32) for w in ws], lams)
+        say(f"[batch] full 64 walkers, plan {b.plan}")
+        x = dev(np.concatenate([w.frames[0] for w in ws]), torch.float32)
+        sz, ds, dz = b.eval(x)
+        sz, ds, dz = host(sz), host(ds), host(dz)
+        b.close()
+        for i, w in enumerate(ws):
+            assert 1.0 <= sz[i][0] <= w.system.n_landmarks, f"walker{i}: s out of range"
+        assert np.isfinite(ds).all() and np.isfinite(dz).all()
+        for i in range(len(ws)):
+            ref = ref_f[i].result()
+            a0, a1 = b.atom_off[i], b.atom_off[i + 1]
+            check_cv(f"walker{i}", TOL32, sz[i], ds[a0:a1], dz[a0:a1], None, ref)

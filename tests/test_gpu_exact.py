@@ -330,3 +330,41 @@ def test_structure_on_a_landmark(torch, plan):
     frames = np.stack([sp.landmarks[2], sp.landmarks[41]])
     _run_exact(torch, sp.landmarks, frames, lam, dtype=torch.float32, tol=TOL32,
                name=f"on_landmark_{plan['engine'] if plan else 'default'}", plan=plan)
+
+
+@pytest.mark.parametrize("plan", [dict(engine=1, wg=256, apt=2, team=64),
+                                  dict(engine=2, wg=512, apt=4, team=32, aptg=2, batch=13),
+                                  dict(engine=3, wg=512, apt=4, team=0, aptg=0, batch=0),
+                                  dict(engine=4, wg=512, apt=12, team=0, aptg=0, batch=0),
+                                  dict(engine=5, wg=512, apt=4, team=0, aptg=0, batch=0)])
+def test_fp32_frame_rounding_is_corrected(torch, plan):
+    """A sharp path (lambda ~ 980, 93 atoms, 3,122 landmarks: walker 5 of the
+    64-walker batch): s moves by 1.5e-6 when w x_c is rounded to FP32, which
+    the FP32 engines 2-5 contract with.  The merges add the first-order term
+    dS/dx . (x - x'), so every engine lands within 2e-7 of the oracle; the
+    close structure's first (exact) step and the property maps' S_1 = s
+    carry the same correction."""
+    import paper_1801_02362_amd as pcv
+    from gpu_util import TOL32, check_cv, dev, host, say
+    w = wl.walkers(n_walkers=64, n_frames=1)[5]
+    lm, f = w.system.landmarks, w.frames[0]
+    lam = landmark_lambda(lm)
+    ref = path_cv(f.astype(np.float64), lm.astype(np.float64), lam)
+    say(f"[rounding] n={lm.shape[1]} L={lm.shape[0]} lam={lam:.1f} plan={plan}")
+    cv = pcv.PathCV(dev(lm, torch.float32), lam, use_graph=False)
+    cv.set_plan(**plan)
+    x = dev(f, torch.float32)
+    o = cv.eval(x, grad=True, msd=True)
+    sz = host(o["sz"])
+    check_cv("exact", TOL32, sz, host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"]), ref)
+    assert abs(sz[0] - ref.s) <= 2e-7, (sz[0], ref.s)
+    assert abs(sz[1] - ref.z) <= 2e-7, (sz[1], ref.z)
+    c = cv.eval_close(x)
+    assert bool(host(c["recomputed"].to(torch.float64))[0])
+    assert abs(host(c["sz"])[0] - ref.s) <= 2e-7
+    q = torch.arange(1, lm.shape[0] + 1, dtype=torch.float64, device="cuda").reshape(-1, 1)
+    p = cv.eval_properties(x, q)
+    assert abs(host(p["S"])[0] - ref.s) <= 2e-7
+    p2 = cv.eval_properties(x, q, grad=False)
+    assert host(p2["S"])[0] == host(p["S"])[0]
+    cv.close()
