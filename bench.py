@@ -69,14 +69,14 @@ def kernel_source_hash(kernel: str = "engine3_kernel") -> str:
     return h.hexdigest()[:16]
 
 
-def counted_traffic(name: str):
+def counted_traffic(name: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different kernel source."""
+    None when absent, taken on another kernel or on a different source."""
     p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_sha") != kernel_source_hash(d.get("kernel", "engine3_kernel")):
+    if d.get("kernel") != kernel or d.get("kernel_source_sha") != kernel_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -229,7 +229,7 @@ def bench_exact(args):
     log(f"[bench] timed {args.steps} steps in {dt:.4f} s; engine {kms * 1e3:.1f} us per launch")
     alg_bytes = L * n * 12
     achieved = alg_bytes / (kms * 1e-3) / 1e9
-    traffic = counted_traffic(f"engine_exact_{n}x{L}")
+    traffic = counted_traffic(f"engine_exact_{n}x{L}", KERNEL_NAMES[cv.plan["engine"]])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"{KERNEL_NAMES[cv.plan['engine']]} (landmark streaming, exact mode)", "kernel_ms": round(kms, 5),
@@ -602,7 +602,7 @@ def bench_batch(args):
     engine_name = {4: "engine4_kernel", 2: "engine2_kernel", 1: "engine_kernel"}.get(
         int(str(b.plan).split("engine=")[1][0]) if "engine=" in str(b.plan) else 4, "engine4_kernel")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic("engine_batch_64walkers"),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic("engine_batch_64walkers", engine_name),
             "kernel": f"{engine_name} (64 walkers, one persistent launch)", "kernel_ms": round(kms, 5),
             "kernel_launches_timed": int(cnt), "algorithmic_bytes_per_launch": alg_bytes}
     out = {"metric": "structure-landmark MSD+grad evals/s", "value": round(evals * args.steps / dt, 1),

@@ -100,7 +100,6 @@ struct pcv_handle {
   int* status = nullptr;
   double* corr = nullptr;       // [3 * n_pad / 64][2]: rounding-correction shares of the merges
   double* corr_prop = nullptr;  // [kPropsMax][3 n / 256]: the same for the property maps
-  unsigned* ticket = nullptr;   // their arrival counter (zero between launches)
   // close structure
   double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
          *Rxy = nullptr, *Dxy = nullptr, *Rsave = nullptr, *gtmp = nullptr, *scratch_sz = nullptr;
@@ -172,6 +171,9 @@ static pcv_status hip_fail(pcv_handle* h, hipError_t e, const char* where) {
   } while (0)
 
 static void collect_timing(pcv_handle* h);
+
+// FP32 engines 2-5 contract with w x_c rounded to FP32 (see Problem::x_rounded).
+static bool x_rounded(const pcv_handle* h) { return !h->fp64 && h->plan.engine != 1; }
 
 static void drop_graphs(pcv_handle* h) {
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -321,9 +323,8 @@ static pcv_status build_plan(pcv_handle* h) {
   base.lam = h->lam;
   base.xw32 = h->xw32;
   base.n_x = h->n_x;
-  base.x_rounded = (!h->fp64 && p.engine != 1) ? 1 : 0;
+  base.x_rounded = x_rounded(h) ? 1 : 0;
   base.corr = h->corr;
-  base.ticket = h->ticket;
   // Entry 3: the property maps' exact pass (rotations saved to their own buffer).
   Problem props_prob = base;
   props_prob.Rsave = h->Rprop;
@@ -552,8 +553,6 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->xres, 3 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
   HIP_TRY(h, m.alloc((void**)&h->corr, 6 * (np / 64) * sizeof(double)));
-  HIP_TRY(h, m.alloc((void**)&h->ticket, sizeof(unsigned)));
-  HIP_TRY(h, hipMemset(h->ticket, 0, sizeof(unsigned)));
   HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Fxy, 10 * sizeof(double)));
@@ -673,7 +672,7 @@ static hipError_t enqueue_exact(pcv_handle* h, hipStream_t st, const void* x, do
   e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, msd);
   if (e != hipSuccess) return e;
   Outs o{ds, dz, sz, nullptr};
-  return launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+  return launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st, x_rounded(h));
 }
 
 template <typename T>
@@ -711,14 +710,16 @@ static hipError_t enqueue_exact_nl(pcv_handle* h, hipStream_t st, const void* x,
   if (update) {
     hipError_t e = launch_prep<T>(h->d_prep, x, 1, h->n, st);
     if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, h->dfull);
-    if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+    if (e == hipSuccess)
+      e = launch_merge_exact<T>(h->d_prob + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st, x_rounded(h));
     if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
     if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
     return e;
   }
   hipError_t e = launch_prep<T>(h->d_prep_nl, x, 1, h->n, st);
   if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_EXACT, nullptr, 0, nullptr, true);
-  if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob_nl + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st);
+  if (e == hipSuccess)
+    e = launch_merge_exact<T>(h->d_prob_nl + MODE_EXACT, o, 1, h->n_pad, nullptr, 0, st, x_rounded(h));
   return e;
 }
 
@@ -747,7 +748,8 @@ static hipError_t enqueue_close_nl(pcv_handle* h, hipStream_t st, const void* x,
     return e;
   }
   e = engine_timed<T>(h, st, MODE_EXACT_SAVE, h->flag, 1, nullptr);
-  if (e == hipSuccess) e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+  if (e == hipSuccess)
+    e = launch_merge_exact<T>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st, x_rounded(h));
   if (e == hipSuccess) e = nl_gather<T>(h, st, h->flag, 1);
   if (e == hipSuccess) e = engine_timed<T>(h, st, MODE_APPROX, h->flag, 0, nullptr, true);
   if (e == hipSuccess) e = launch_merge_close<T>(h->d_prob_nl + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st);
@@ -943,9 +945,8 @@ extern "C" pcv_status pcv_eval_close(pcv_handle* h, const void* x, double* sz, v
 static PropsArgs props_args(const pcv_handle* h, int P, double* corr) {
   PropsArgs a{h->A, h->ca, h->Rprop, h->Dprop, h->w, h->L, h->n, h->n_pad, P};
   a.xw = h->xw;
-  a.x_rounded = (!h->fp64 && h->plan.engine != 1) ? 1 : 0;
+  a.x_rounded = x_rounded(h) ? 1 : 0;
   a.corr = corr;
-  a.ticket = h->ticket;
   return a;
 }
 
@@ -1231,7 +1232,7 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t pcv_internal_exact_f
   if (e != hipSuccess) return e;
   e = engine_timed<float>(h, st, MODE_EXACT_SAVE, h->flag, 1, nullptr);
   if (e != hipSuccess) return e;
-  e = launch_merge_exact<float>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st);
+  e = launch_merge_exact<float>(h->d_prob + MODE_EXACT_SAVE, o, 1, h->n_pad, h->flag, 1, st, x_rounded(h));
   *flag = h->flag;
   return e;
 }

@@ -66,7 +66,6 @@ struct pcv_batch {
   std::vector<size_t> x32_off;
   int* status = nullptr;
   double* corr = nullptr;       // per walker [3 * n_pad / 64][2]: rounding-correction shares of the merge
-  unsigned* ticket = nullptr;   // [W] their arrival counters (zero between launches)
   std::vector<size_t> corr_off;
   PrepArgs* d_prep = nullptr;
   // plan
@@ -220,8 +219,6 @@ extern "C" pcv_status pcv_batch_load(pcv_batch* b, int W, const int* n_atoms, co
   b->corr_off.assign(W + 1, 0);
   for (int i = 0; i < W; ++i) b->corr_off[i + 1] = b->corr_off[i] + 6 * (size_t)(b->n_pad[i] / 64);
   BHIP_TRY(b, m.alloc((void**)&b->corr, b->corr_off[W] * sizeof(double)));
-  BHIP_TRY(b, m.alloc((void**)&b->ticket, W * sizeof(unsigned)));
-  BHIP_TRY(b, hipMemset(b->ticket, 0, W * sizeof(unsigned)));
   BHIP_TRY(b, m.alloc((void**)&b->d_prep, W * sizeof(PrepArgs)));
   b->x32_off.assign(W + 1, 0);
   for (int i = 0; i < W; ++i) b->x32_off[i + 1] = b->x32_off[i] + 3 * (size_t)round_up(b->n_pad[i], 256);
@@ -392,7 +389,6 @@ static pcv_status batch_apply(pcv_batch* b, const BatchPlan& p) {
     P.lam = b->lam[i];
     P.x_rounded = (!b->fp64 && p.engine != 1) ? 1 : 0;
     P.corr = b->corr + b->corr_off[i];
-    P.ticket = b->ticket + i;
     probs[i] = P;
     a_off += (size_t)b->L[i] * 3 * b->n_pad[i];
   }
@@ -435,7 +431,7 @@ static hipError_t batch_enqueue(pcv_batch* b, hipStream_t st, const void* x, dou
   }
   if (e != hipSuccess) return e;
   Outs o{ds, dz, sz, nullptr};
-  return launch_merge_exact<T>(b->d_prob, o, b->W, b->max_n_pad, nullptr, 0, st);
+  return launch_merge_exact<T>(b->d_prob, o, b->W, b->max_n_pad, nullptr, 0, st, !b->fp64 && b->plan.engine != 1);
 }
 
 static pcv_status batch_run(pcv_batch* b, const void* x, double* sz, void* ds, void* dz, bool allow_graph) {

@@ -43,13 +43,11 @@ struct Problem {
   int n_x;              // plane stride of xw32: n_pad rounded up to 256
   // FP32 engines 2-5 contract with fl32(w_j x_c,j): their distances, s and z
   // are those of the structure x' = fl32(w x_c) / w.  With x_rounded set,
-  // the exact merges add the first-order difference dS/dx . (x - x') to s
-  // and z: each merge workgroup leaves its share in corr ([3 tiles][2]) and
-  // counts itself in *ticket; the last one adds the shares in index order,
-  // writes (s, z) and returns *ticket to 0.
+  // (s, z) gain the first-order difference dS/dx . (x - x'): each exact
+  // merge workgroup leaves its share in corr ([3 ceil(n / 64)][2]) and the
+  // kernel after the merge adds the shares in workgroup order.
   int x_rounded;
   double* corr;
-  unsigned* ticket;
 };
 
 struct Item {
@@ -186,7 +184,7 @@ hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds_bytes, const Proble
                          int run_if, double* dout, hipStream_t st);
 template <typename T>
 hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
-                              const int* flag, int run_if, hipStream_t st);
+                              const int* flag, int run_if, hipStream_t st, bool rounded);
 // prob_exact (may be null): the reassignment's problem; when given, the
 // same launch also performs the exact merge on reassignment steps, so the
 // separate flag-gated launch_merge_exact is not needed.
@@ -263,12 +261,10 @@ struct PropsArgs {
   int L, n, n_pad, P;
   // With x_rounded (FP32 engines, see Problem::x_rounded) the gradient pass
   // always runs and S_k gains dS_k/dx . (x - x'): xw is w x_c in FP64
-  // ([3][n_pad]), corr holds props_corr_doubles(n) shares per component and
-  // ticket counts the reduce workgroups.
+  // ([3][n_pad]), corr holds props_corr_doubles(n) shares per component.
   const double* xw;
   int x_rounded;
   double* corr;
-  unsigned* ticket;
 };
 // Landmark chunks of the gradient pass (its partials: chunks x P x 3 x n_pad doubles).
 int props_chunks(int n_pad, int L);

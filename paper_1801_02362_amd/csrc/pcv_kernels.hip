@@ -660,42 +660,20 @@ __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, d
   S = v[1];
 }
 
-// Rounding correction of one merge workgroup (see Problem::x_rounded),
+// Rounding-correction share of one merge workgroup (see Problem::x_rounded),
 // called by its whole first wave: lane a holds, for its atom j and the
 // workgroup's coordinate c, ds_j,c d_j,c and dz_j,c d_j,c with
 // d = x - x' = (w x_c - fl32(w x_c)) / w (zero for atoms past n).  blk is the
-// workgroup's index among the nblk that serve the problem.  The last to
-// arrive writes s + sum and z + sum; the sums run in block order, so the
-// result does not depend on arrival order.
-__device__ void sz_rounding_correction(const Problem& P, const Outs& o, double s, double z, double cs, double cz,
-                                       int blk, int nblk) {
-  const int lane = threadIdx.x & 63;
+// workgroup's index among the 3 ceil(n / 64) that serve the problem;
+// sz_correct_kernel adds the shares in index order.
+__device__ void rounding_share(const Problem& P, double cs, double cz, int blk) {
   for (int off = 32; off >= 1; off >>= 1) {
     cs += __shfl_xor(cs, off, 64);
     cz += __shfl_xor(cz, off, 64);
   }
-  unsigned t = 0;
-  if (lane == 0) {
+  if ((threadIdx.x & 63) == 0) {
     stg(P.corr + 2 * (size_t)blk, cs);
     stg(P.corr + 2 * (size_t)blk + 1, cz);
-    t = __hip_atomic_fetch_add(P.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  t = __shfl(t, 0, 64);
-  if (t != (unsigned)nblk - 1) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double as = 0.0, az = 0.0;
-  for (int b = lane; b < nblk; b += 64) {
-    as += __hip_atomic_load(P.corr + 2 * (size_t)b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    az += __hip_atomic_load(P.corr + 2 * (size_t)b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  for (int off = 32; off >= 1; off >>= 1) {
-    as += __shfl_xor(as, off, 64);
-    az += __shfl_xor(az, off, 64);
-  }
-  if (lane == 0) {
-    o.sz[2 * P.out_idx + 0] = s + as;
-    o.sz[2 * P.out_idx + 1] = z + az;
-    __hip_atomic_store(P.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -793,12 +771,48 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
     if (P.x_rounded) {
       double cs, cz;
       rounding_terms(P, j, c, gs, gz, Z, cs, cz);
-      const int tiles = (P.n + 63) / 64;
-      sz_rounding_correction(P, o, s, m - log(Z) / P.lam, cs, cz, c * tiles + (int)blockIdx.x, 3 * tiles);
-    } else if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
-      o.sz[2 * P.out_idx + 0] = s;
-      o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+      rounding_share(P, cs, cz, c * ((P.n + 63) / 64) + (int)blockIdx.x);
     }
+  }
+  if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) {
+    o.sz[2 * P.out_idx + 0] = s;
+    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+  }
+}
+
+// (s, z) of each problem with x_rounded plus its merge workgroups' rounding
+// shares, added in workgroup order (one wave per problem; launched after
+// the merge, gated like it).
+__global__ __launch_bounds__(64) void sz_correct_kernel(const Problem* __restrict__ probs, Outs o,
+                                                        const int* __restrict__ flag, int run_if) {
+  if (flag != nullptr && *flag != run_if) return;
+  const Problem& P = probs[blockIdx.x];
+  if (!P.x_rounded) return;
+  const int nblk = 3 * ((P.n + 63) / 64);
+  // Eight shares per lane are loaded before any is added (one round trip
+  // up to 512 shares, i.e. 10,922 atoms); larger structures loop.
+  typedef double pair_t __attribute__((ext_vector_type(2)));
+  double as = 0.0, az = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += 512) {
+    pair_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + threadIdx.x + 64 * u;
+      v[u] = b < nblk ? *reinterpret_cast<const pair_t*>(P.corr + 2 * (size_t)b) : pair_t{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      as += v[u][0];
+      az += v[u][1];
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    as += __shfl_xor(as, off, 64);
+    az += __shfl_xor(az, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    o.sz[2 * P.out_idx + 0] += as;
+    o.sz[2 * P.out_idx + 1] += az;
   }
 }
 
@@ -877,11 +891,12 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int 
     if (P.x_rounded) {
       double cs, cz;
       rounding_terms(P, j, c, ts, tz, Z, cs, cz);
-      sz_rounding_correction(P, o, s, m - log(Z) / P.lam, cs, cz, c * (int)gridDim.x + tile, 3 * (int)gridDim.x);
-    } else if (tile == 0 && c == 0 && threadIdx.x == 0) {
-      o.sz[2 * P.out_idx + 0] = s;
-      o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
+      rounding_share(P, cs, cz, c * (int)gridDim.x + tile);
     }
+  }
+  if (tile == 0 && c == 0 && threadIdx.x == 0) {
+    o.sz[2 * P.out_idx + 0] = s;
+    o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
   }
 }
 
@@ -970,9 +985,31 @@ __global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Pr
 template <typename T>
 __global__ __launch_bounds__(256) void merge_close_final_kernel(const Problem* __restrict__ prob, Outs o,
                                                                 CloseArgs cs, const double* __restrict__ gtmp,
-                                                                int tiles) {
+                                                                int tiles, const Problem* __restrict__ prob_exact) {
   constexpr int BS = 256;
   const int flag = *cs.flag;   // tested once the independent loads below are in flight
+  if (flag == 1 && prob_exact != nullptr) {
+    // Reassignment branch: the exact merge of the first kernel wrote (s, z)
+    // and, with x_rounded, its rounding shares (3 tiles workgroups).
+    if (threadIdx.x < 64) {
+      const Problem& E = *prob_exact;
+      if (!E.x_rounded) return;
+      double as = 0.0, az = 0.0;
+      for (int b = threadIdx.x; b < 3 * tiles; b += 64) {
+        as += E.corr[2 * (size_t)b];
+        az += E.corr[2 * (size_t)b + 1];
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        as += __shfl_xor(as, off, 64);
+        az += __shfl_xor(az, off, 64);
+      }
+      if (threadIdx.x == 0) {
+        o.sz[2 * E.out_idx + 0] += as;
+        o.sz[2 * E.out_idx + 1] += az;
+      }
+    }
+    return;
+  }
   __shared__ double sh[16 * 18];
   __shared__ double gam[18];
   const Problem& P = *prob;
@@ -1135,9 +1172,12 @@ hipError_t launch_engine(EngineCfg cfg, int grid, size_t lds, const Problem* pro
 
 template <typename T>
 hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int max_n_pad,
-                              const int* flag, int run_if, hipStream_t st) {
+                              const int* flag, int run_if, hipStream_t st, bool rounded) {
   dim3 grid((max_n_pad + 63) / 64, 3, n_prob);
   hipLaunchKernelGGL((merge_exact_kernel<T>), grid, dim3(256), 0, st, probs, outs, flag, run_if);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !rounded) return e;
+  hipLaunchKernelGGL(sz_correct_kernel, dim3(n_prob), dim3(64), 0, st, probs, outs, flag, run_if);
   return hipGetLastError();
 }
 
@@ -1149,7 +1189,8 @@ hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseAr
                      prob_exact, outs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(256), 0, st, prob, outs, ca, gtmp, tiles);
+  hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(256), 0, st, prob, outs, ca, gtmp, tiles,
+                     prob_exact);
   return hipGetLastError();
 }
 
@@ -1173,7 +1214,7 @@ hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) 
   template hipError_t launch_engine<T>(EngineCfg, int, size_t, const Problem*, const Item*,        \
                                        const int*, int, const int*, int, double*, hipStream_t);    \
   template hipError_t launch_merge_exact<T>(const Problem*, Outs, int, int, const int*, int,       \
-                                            hipStream_t);                                          \
+                                            hipStream_t, bool);                                    \
   template hipError_t launch_merge_close<T>(const Problem*, int, Outs, CloseArgs, double*, hipStream_t, \
                                             const Problem*);
 PCV_INST(float)

@@ -138,15 +138,13 @@ __global__ __launch_bounds__(256) void props_grad_kernel(PropsArgs a, const doub
 // rounded up, P), one component per row.  The loads are issued eight at a
 // time (independent of the running sum), so a thread waits for one round
 // trip per eight chunks rather than per chunk.  With x_rounded every
-// workgroup also forms its share of dS_k/dx . (x - x') (x - x' =
+// workgroup also leaves its share of dS_k/dx . (x - x') in corr (x - x' =
 // (w x_c - fl32(w x_c)) / w, so the share is the chunk sum times that
-// residual); the last to arrive adds the shares of each component in block
-// order to S_k and returns the ticket to 0.
+// residual); props_correct_kernel adds them to S_k.
 template <typename T>
 __global__ __launch_bounds__(256) void props_reduce_kernel(PropsArgs a, int chunks, const double* __restrict__ part,
-                                                           T* __restrict__ dS, double* __restrict__ S) {
+                                                           T* __restrict__ dS) {
   __shared__ double sh[4];
-  __shared__ int last;
   const int k = blockIdx.y;
   const int n3 = 3 * a.n;
   const int r = blockIdx.x * 256 + threadIdx.x;
@@ -176,26 +174,18 @@ __global__ __launch_bounds__(256) void props_reduce_kernel(PropsArgs a, int chun
   for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
   if (lane == 0) sh[wave] = term;
   __syncthreads();
-  const int nbx = gridDim.x, nblk = gridDim.x * gridDim.y;
-  if (threadIdx.x == 0) {
-    stg(a.corr + (size_t)k * nbx + blockIdx.x, ((sh[0] + sh[1]) + sh[2]) + sh[3]);
-    const unsigned t = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == (unsigned)nblk - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  for (int k2 = 0; k2 < a.P; ++k2) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nbx; b += 256)
-      v += __hip_atomic_load(a.corr + (size_t)k2 * nbx + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) S[k2] += ((sh[0] + sh[1]) + sh[2]) + sh[3];
-  }
-  if (threadIdx.x == 0) __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) a.corr[(size_t)k * gridDim.x + blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// S_k += its nb rounding shares, in block order (wave k of the workgroup).
+__global__ __launch_bounds__(64 * kPropsMax) void props_correct_kernel(const double* __restrict__ corr, int nb, int P,
+                                                                       double* __restrict__ S) {
+  const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (k >= P) return;
+  double v = 0.0;
+  for (int b = lane; b < nb; b += 64) v += corr[(size_t)k * nb + b];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) S[k] += v;
 }
 
 }  // namespace
@@ -220,8 +210,11 @@ hipError_t launch_props(const PropsArgs& a, const double* q, double lam, double*
   hipLaunchKernelGGL((props_grad_kernel<T>), dim3((a.n_pad + 63) / 64, chunks), dim3(256), 0, st, a, W, part);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((props_reduce_kernel<T>), dim3(props_corr_doubles(a.n), a.P), dim3(256), 0, st, a, chunks,
-                     part, (T*)dS, S);
+  const int nb = props_corr_doubles(a.n);
+  hipLaunchKernelGGL((props_reduce_kernel<T>), dim3(nb, a.P), dim3(256), 0, st, a, chunks, part, (T*)dS);
+  e = hipGetLastError();
+  if (e != hipSuccess || !a.x_rounded) return e;
+  hipLaunchKernelGGL(props_correct_kernel, dim3(1), dim3(64 * kPropsMax), 0, st, a.corr, nb, a.P, S);
   return hipGetLastError();
 }
 
