@@ -100,6 +100,7 @@ struct pcv_handle {
   int* status = nullptr;
   double* corr = nullptr;       // [3 * n_pad / 64][2]: rounding-correction shares of the merges
   double* corr_prop = nullptr;  // [kPropsMax][3 n / 256]: the same for the property maps
+  unsigned* close_ticket = nullptr;   // arrival counter of the close merge (zero between launches)
   // close structure
   double *y64 = nullptr, *Gy = nullptr, *Fxy = nullptr, *lamxy = nullptr, *qxy = nullptr,
          *Rxy = nullptr, *Dxy = nullptr, *Rsave = nullptr, *gtmp = nullptr, *scratch_sz = nullptr;
@@ -110,6 +111,7 @@ struct pcv_handle {
   bool user_plan = false;
   double* hdr = nullptr;
   void* vec = nullptr;
+  double* xuv = nullptr;   // engine 4: per-item XU / XV sums of approximate steps
   Problem* d_prob = nullptr;    // [3]: EXACT, EXACT_SAVE, APPROX
   Item* d_items = nullptr;
   int* d_wgoff = nullptr;
@@ -276,6 +278,9 @@ static pcv_status build_plan(pcv_handle* h) {
   HIP_TRY(h, h->pmem.alloc((void**)&h->hdr, n_slots * 4 * sizeof(double)));
   HIP_TRY(h, h->pmem.alloc(&h->vec, n_slots * (h->fp64 ? partial_bytes<double>(h->n_pad)
                                                        : partial_bytes<float>(h->n_pad))));
+  h->xuv = nullptr;
+  if (p.engine == 4 && !h->fp64)
+    HIP_TRY(h, h->pmem.alloc((void**)&h->xuv, n_slots * 18 * sizeof(double)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_prob, 4 * sizeof(Problem)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_items, (size_t)p.n_items * sizeof(Item)));
   HIP_TRY(h, h->pmem.alloc((void**)&h->d_wgoff, (size_t)(p.grid + 1) * sizeof(int)));
@@ -325,6 +330,7 @@ static pcv_status build_plan(pcv_handle* h) {
   base.n_x = h->n_x;
   base.x_rounded = x_rounded(h) ? 1 : 0;
   base.corr = h->corr;
+  base.xuv = h->xuv;
   // Entry 3: the property maps' exact pass (rotations saved to their own buffer).
   Problem props_prob = base;
   props_prob.Rsave = h->Rprop;
@@ -377,6 +383,7 @@ static pcv_status build_nl_plan(pcv_handle* h, const Problem& full) {
   }
   wgoff[n_items] = n_items;
   Problem b = full;
+  b.xuv = nullptr;   // the list set's close merge takes the two-stage path
   b.A = h->A_nl;
   b.ca = h->ca_nl;
   b.Ga = h->Ga_nl;
@@ -528,6 +535,7 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   h->f2mem.release();
   h->wd = nullptr;
   h->pmem.release();
+  h->xuv = nullptr;
   h->mem.release();
   h->n = n_atoms;
   h->n_pad = round_up(n_atoms, 64);
@@ -553,6 +561,8 @@ extern "C" pcv_status pcv_load_landmarks(pcv_handle* h, int n_atoms, int n_landm
   HIP_TRY(h, m.alloc((void**)&h->xres, 3 * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->status, sizeof(int)));
   HIP_TRY(h, m.alloc((void**)&h->corr, 6 * (np / 64) * sizeof(double)));
+  HIP_TRY(h, m.alloc((void**)&h->close_ticket, sizeof(unsigned)));
+  HIP_TRY(h, hipMemset(h->close_ticket, 0, sizeof(unsigned)));
   HIP_TRY(h, m.alloc((void**)&h->y64, 3 * np * sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Gy, sizeof(double)));
   HIP_TRY(h, m.alloc((void**)&h->Fxy, 10 * sizeof(double)));
@@ -682,7 +692,7 @@ static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, do
   pa.xw32 = h->xw32;
   pa.n_x = h->n_x;
   CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
-               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L, h->close_ticket};
   Outs o{ds, dz, sz, rec};
   hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
   if (e != hipSuccess) return e;
@@ -690,7 +700,8 @@ static hipError_t enqueue_close(pcv_handle* h, hipStream_t st, const void* x, do
   // on the device which problem they take).
   e = engine_timed<T>(h, st, MODE_APPROX, h->flag, kRunDual, msd, false, 0);
   if (e != hipSuccess) return e;
-  return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE);
+  return launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE,
+                               h->xuv != nullptr);
 }
 
 template <typename T>
@@ -735,14 +746,15 @@ static hipError_t enqueue_close_nl(pcv_handle* h, hipStream_t st, const void* x,
   pa.xw32 = h->xw32;
   pa.n_x = h->n_x;
   CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
-               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L, h->close_ticket};
   Outs o{ds, dz, sz, rec};
   hipError_t e = launch_prep_close<T>(pa, x, ca, o, st);
   if (e != hipSuccess) return e;
   if (update) {
     e = engine_timed<T>(h, st, MODE_APPROX, h->flag, kRunDual, h->dfull, false, 0);
     if (e == hipSuccess)
-      e = launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE);
+      e = launch_merge_close<T>(h->d_prob + MODE_APPROX, h->n_pad, o, ca, h->gtmp, st, h->d_prob + MODE_EXACT_SAVE,
+                                h->xuv != nullptr);
     if (e == hipSuccess) e = launch_nl_select(h->dfull, h->L, h->nl_M, h->nl_members, st);
     if (e == hipSuccess) e = nl_gather<T>(h, st, nullptr, 0);
     return e;
@@ -1226,7 +1238,7 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t pcv_internal_exact_f
   pa.xw32 = h->xw32;
   pa.n_x = h->n_x;
   CloseArgs ca{h->y64, h->Gy, h->Fxy, h->lamxy, h->qxy, h->Rxy, h->Dxy,
-               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L};
+               h->flag, h->init, h->force, h->counters, h->opt.eps, h->L, h->close_ticket};
   Outs o{ds, dz, sz, nullptr};
   hipError_t e = launch_prep_close<float>(pa, x, ca, o, st);
   if (e != hipSuccess) return e;

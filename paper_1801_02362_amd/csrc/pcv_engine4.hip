@@ -389,6 +389,13 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
   double m = INFINITY;
   // Per-lane sums (landmark lane = lane) against the common running minimum.
   double Z = 0.0, S = 0.0, tU[3] = {0.0, 0.0, 0.0}, tV[3] = {0.0, 0.0, 0.0};
+  // Approximate steps with Problem::xuv: XU = sum e (q - q0) T_i and
+  // XV = sum e T_i with T_i[r][c] = sum_j (w x_c)_j,r (R_i (a_ij - c_i))_c =
+  // (R_i M_i)[c][r], the item's share of Eq. 6's G, kept like tU / tV.
+  const bool want_xuv = mode == MODE_APPROX && P.xuv != nullptr;
+  double XU[9], XV[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) { XU[k] = 0.0; XV[k] = 0.0; }
   // Per-landmark inputs of lane k, fetched one step ahead of use (lanes past
   // the step read landmark i0, in bounds, and stay inactive).
   auto fetch = [&](int t, double cap[3], double& Ga, double& qi, double Rs[9]) {
@@ -415,14 +422,13 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rsv[k] = Rs[k];
       if (t + 1 < T) fetch(t + 1, cap, Ga, qi, Rs);
-      double D = INFINITY, R[9];
+      double D = INFINITY, R[9], Mc[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Mc[q] = 0.0;
       if (act) {
         // Correlation of landmark lane k: its nblk unit sums in block order.
-        double Mc[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) Mc[q] = 0.0;
         for (int b = 0; b < nblk; ++b) {
           const double* pp = e4_part[t & 1][lane * nblk + b];
 #pragma unroll
@@ -486,6 +492,18 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
         tU[d] = fma(dq, tV[d], tU[d]) * sc + al * rc;
         tV[d] = tV[d] * sc + e * rc;
       }
+      if (want_xuv) {
+#pragma unroll
+        for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+          for (int c0 = 0; c0 < 3; ++c0) {
+            const double tv = R[c0 * 3 + 0] * Mc[0 * 3 + r0] + R[c0 * 3 + 1] * Mc[1 * 3 + r0] +
+                              R[c0 * 3 + 2] * Mc[2 * 3 + r0];
+            const int k = r0 * 3 + c0;
+            XU[k] = fma(dq, XV[k], XU[k]) * sc + al * tv;
+            XV[k] = XV[k] * sc + e * tv;
+          }
+      }
       m = mn;
       if (act) {
         double* r = e4_res[t & 1][lane];
@@ -527,6 +545,21 @@ __device__ __forceinline__ void e4_solver(const E4Item& c, int lane, int mode, d
     stg(h + 1, Z);
     stg(h + 2, S);
     stg(h + 3, q0);
+  }
+  if (want_xuv) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      XU[k] = wave_sum_to63(XU[k]);
+      XV[k] = wave_sum_to63(XV[k]);
+    }
+    if (lane == 63) {
+      double* x = P.xuv + (size_t)c.slot * 18;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        stg(x + k, XU[k]);
+        stg(x + 9 + k, XV[k]);
+      }
+    }
   }
   bar_lds();
   if (K > 1) {   // the workers' three barriers of the unit-sum reduction

@@ -48,6 +48,11 @@ struct Problem {
   // kernel after the merge adds the shares in workgroup order.
   int x_rounded;
   double* corr;
+  // Approximate steps of engine 4: per item the 3x3 sums XU and XV of
+  // T_i = sum_j (w x_c)_j (R_i (a_ij - c_i))^T weighted like the partials U
+  // and V ([n_slots][18]); null elsewhere.  With them the close merge is one
+  // kernel (Eq. 6's G comes from the items, not from every atom).
+  double* xuv;
 };
 
 struct Item {
@@ -148,6 +153,7 @@ struct CloseArgs {
   long long* counters;  // [8]: frames, recomputes, expensive_msd, approx_frames
   double eps;
   int L;
+  unsigned* ticket;     // [1] arrival count of the close merge's workgroups (0 between launches)
 };
 
 enum Counter { CNT_FRAMES = 0, CNT_RECOMPUTES = 1, CNT_EXPENSIVE = 2, CNT_APPROX = 3,
@@ -187,10 +193,15 @@ hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int m
                               const int* flag, int run_if, hipStream_t st, bool rounded);
 // prob_exact (may be null): the reassignment's problem; when given, the
 // same launch also performs the exact merge on reassignment steps, so the
-// separate flag-gated launch_merge_exact is not needed.
+// separate flag-gated launch_merge_exact is not needed.  one_pass: the
+// approximate problem carries per-item XU / XV sums (Problem::xuv) and the
+// merge is a single pass.  Otherwise structures of up to kCloseFuseMaxPad
+// padded atoms finish in the last workgroup of the first kernel (one launch
+// per step) and larger ones use a second, single-workgroup kernel.
+constexpr int kCloseFuseMaxPad = 1024;
 template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
-                              hipStream_t st, const Problem* prob_exact = nullptr);
+                              hipStream_t st, const Problem* prob_exact = nullptr, bool one_pass = false);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_count(long long* counters, int which, long long add, hipStream_t st);
 

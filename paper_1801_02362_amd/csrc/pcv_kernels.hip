@@ -173,9 +173,9 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
 }
 
 // ------------------------------------------------------------ frame prep
-// CACHE: atoms per thread whose x and w the first pass keeps in registers
-// for the second (one global round trip fewer); atoms past CACHE * BS are
-// loaded again.  The sums are taken in the same order either way.  With y
+// CACHE: atoms per thread whose x and w (and y) the first pass keeps in
+// registers for the second (one global round trip fewer); atoms past
+// CACHE * BS are loaded again.  The sums are taken in the same order either way.  With y
 // (a centred structure [3][n_pad], FP64) the second pass also forms the
 // correlation My = sum_j y_j (w_j x_c,j)^T (row-major, 9 values).
 template <typename T, int BS, int CACHE = 0>
@@ -183,7 +183,7 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
                              double c[3], double g32[4], const double* y = nullptr, double* My = nullptr) {
   constexpr int KC = CACHE > 0 ? CACHE : 1;
   T xk[KC][3];
-  double wk[KC];
+  double wk[KC], yk[KC][3];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   auto acc1 = [&](double wj, const T* xv) {
 #pragma unroll
@@ -200,6 +200,10 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
       wk[k] = a.w[j];
 #pragma unroll
       for (int d = 0; d < 3; ++d) xk[k][d] = x[3 * j + d];
+      if (y) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) yk[k][d] = y[(size_t)d * a.n_pad + j];
+      }
     }
   }
 #pragma unroll
@@ -212,7 +216,7 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x
   // rounded to T; g[5..13]: the correlation with y.
   double g[14] = {0.0};
-  auto acc2 = [&](int j, double wj, const T* xv) {
+  auto acc2 = [&](int j, double wj, const T* xv, const double* yc) {
     const double iw = wj > 0.0 ? 1.0 / wj : 0.0;
     double xwv[3];
 #pragma unroll
@@ -227,7 +231,8 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
       g[2 + d] += r;
     }
     if (y) {
-      const double yv[3] = {y[j], y[(size_t)a.n_pad + j], y[2 * (size_t)a.n_pad + j]};
+      const double yv[3] = {yc ? yc[0] : y[j], yc ? yc[1] : y[(size_t)a.n_pad + j],
+                            yc ? yc[2] : y[2 * (size_t)a.n_pad + j]};
 #pragma unroll
       for (int r0 = 0; r0 < 3; ++r0)
 #pragma unroll
@@ -244,11 +249,11 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
 #pragma unroll
   for (int k = 0; k < CACHE; ++k) {
     const int j = threadIdx.x + k * BS;
-    if (j < a.n) acc2(j, wk[k], xk[k]);
+    if (j < a.n) acc2(j, wk[k], xk[k], y ? yk[k] : nullptr);
     else if (j < a.n_pad) pad(j);
   }
   for (int j = threadIdx.x + CACHE * BS; j < a.n_pad; j += BS) {
-    if (j < a.n) acc2(j, a.w[j], x + 3 * j);
+    if (j < a.n) acc2(j, a.w[j], x + 3 * j, nullptr);
     else pad(j);
   }
   if (y) {
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(256) void prep_close_kernel(PrepArgs a, const T* __
     cnt[3] = cs.counters[CNT_APPROX];
   }
   double M[9];
-  centre_frame<T, BS>(a, x, sh, Gx, finite, c, g32, init ? cs.y64 : nullptr, M);
+  centre_frame<T, BS, 4>(a, x, sh, Gx, finite, c, g32, init ? cs.y64 : nullptr, M);
   double Dxy = NAN;
   if (init) {
     if (threadIdx.x == 0) {
@@ -836,11 +841,25 @@ __global__ __launch_bounds__(64) void sz_correct_kernel(const Problem* __restric
 // G_z, per tile).
 constexpr int kBetaThreads = 256;
 
+// Last-arrival test of a workgroup's first wave, called by all its lanes
+// after the wave's global writes: true in exactly one of the nblk
+// workgroups of the launch, which then sees every other workgroup's writes
+// and must return *ticket to 0.
+__device__ bool last_arrival(unsigned* ticket, int nblk) {
+  __threadfence();
+  unsigned v = 0;
+  if ((threadIdx.x & 63) == 0) v = atomicAdd(ticket, 1u);
+  v = __shfl(v, 0, 64);
+  const bool last = v == (unsigned)nblk - 1;
+  if (last) __threadfence();
+  return last;
+}
+
 // The exact merge (as merge_exact_kernel) of one tile of 64 atoms and
 // coordinate c: the reassignment branch of a close-structure step served by
 // the same launch.
 template <typename T, int BS>
-__device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int c) {
+__device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int c, unsigned* ticket) {
   using acc = typename AccT<T>::type;
   constexpr int NG = BS / 64;
   __shared__ double xsh[2 * NG];
@@ -892,27 +911,270 @@ __device__ void merge_exact_tile(const Problem& P, const Outs& o, int tile, int 
       double cs, cz;
       rounding_terms(P, j, c, ts, tz, Z, cs, cz);
       rounding_share(P, cs, cz, c * (int)gridDim.x + tile);
+      // With a ticket the last workgroup adds the shares (tiles x 3 of
+      // them, in order) and writes (s, z); otherwise the second kernel does.
+      if (ticket != nullptr && last_arrival(ticket, 3 * (int)gridDim.x)) {
+        const int nblk = 3 * (int)gridDim.x;
+        double as = 0.0, az = 0.0;
+        for (int b = a; b < nblk; b += 64) {
+          as += P.corr[2 * (size_t)b];
+          az += P.corr[2 * (size_t)b + 1];
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+          as += __shfl_xor(as, off, 64);
+          az += __shfl_xor(az, off, 64);
+        }
+        if (a == 0) {
+          o.sz[2 * P.out_idx + 0] = s + as;
+          o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam + az;
+          *ticket = 0u;
+        }
+      }
     }
   }
-  if (tile == 0 && c == 0 && threadIdx.x == 0) {
+  if (tile == 0 && c == 0 && threadIdx.x == 0 && !(ticket != nullptr && P.x_rounded)) {
     o.sz[2 * P.out_idx + 0] = s;
     o.sz[2 * P.out_idx + 1] = m - log(Z) / P.lam;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
-                                                                       double* __restrict__ gtmp,
-                                                                       const Problem* __restrict__ prob_exact, Outs o) {
+// Eq. 6 second stage of the approximate step, run by the first BS threads
+// of a workgroup (BS = 64: one wave, the others may have exited): G of the
+// s and z terms summed over the tiles' shares in gtmp (fixed order), the two
+// rotation adjoints Gamma, then per atom the explicit terms -2 w R_xy beta
+// and 2 (w x - w R_xy betaz) plus the rotation terms, and (s, z).
+template <typename T, int BS>
+__device__ void close_final_stage(const Problem& P, const Outs& o, const CloseArgs& cs,
+                                  const double* __restrict__ gtmp, int tiles, double m, double Z, double S,
+                                  double* sh, double* gam) {
+  const int t = threadIdx.x;
+  const int n = P.n, n_pad = P.n_pad;
+  auto sync = [&]() {
+    if (BS == 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+      __syncthreads();
+    }
+  };
+  if (t < 18) {
+    double g = 0.0;
+    for (int k = 0; k < tiles; ++k) g += gtmp[6 * (size_t)n_pad + (size_t)k * 18 + t];
+    sh[t] = g;
+  }
+  sync();
+  // The two adjoints (for s and for z) are independent: two lanes of one
+  // wave (BS = 64) or the first lanes of two waves.
+  constexpr int tz = BS > 64 ? 64 : 1;
+  if (t == 0 || t == tz) {
+    const int h = t == 0 ? 0 : 9;
+    double F[10], qv[4], G[9], Gm[9];
+    for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
+    for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
+    for (int k = 0; k < 9; ++k) G[k] = sh[h + k];
+    rotation_adjoint(F, *cs.lamxy, qv, G, Gm);
+    for (int k = 0; k < 9; ++k) gam[h + k] = Gm[k];
+  }
+  sync();
+  T* ds = (T*)o.ds;
+  T* dz = (T*)o.dz;
+  const double* Rx = cs.Rxy;
+  for (int j = t; j < n; j += BS) {
+    double y[3], be[3], bz[3], xw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      y[d] = cs.y64[(size_t)d * n_pad + j];
+      be[d] = gtmp[(size_t)d * n_pad + j];
+      bz[d] = gtmp[3 * (size_t)n_pad + (size_t)d * n_pad + j];
+      xw[d] = P.xw[(size_t)d * n_pad + j];
+    }
+    const double wj = P.w[j];
+#pragma unroll
+    for (int c0 = 0; c0 < 3; ++c0) {
+      const double rb = Rx[c0 * 3 + 0] * be[0] + Rx[c0 * 3 + 1] * be[1] + Rx[c0 * 3 + 2] * be[2];
+      const double rzb = Rx[c0 * 3 + 0] * bz[0] + Rx[c0 * 3 + 1] * bz[1] + Rx[c0 * 3 + 2] * bz[2];
+      const double rs = wj * (gam[0 * 3 + c0] * y[0] + gam[1 * 3 + c0] * y[1] + gam[2 * 3 + c0] * y[2]);
+      const double rz = wj * (gam[9 + 0 * 3 + c0] * y[0] + gam[9 + 1 * 3 + c0] * y[1] + gam[9 + 2 * 3 + c0] * y[2]);
+      if (ds) ds[3 * j + c0] = (T)(-2.0 * wj * rb + rs);
+      if (dz) dz[3 * j + c0] = (T)(2.0 * (xw[c0] - wj * rzb) + rz);
+    }
+  }
+  if (t == 0) {
+    o.sz[0] = S / Z;
+    o.sz[1] = m - log(Z) / P.lam;
+  }
+}
+
+// The approximate step's merge in one pass when the engine left per-item
+// XU / XV sums (Problem::xuv): G_s = (2 lambda / Z) sum_g f_g (XU_g +
+// (q0_g - s) XV_g) and G_z = -(2 / Z) sum_g f_g XV_g are formed by every
+// workgroup from the item sums, so each can finish its own atoms (all three
+// coordinates of 64 atoms; the workgroups of coordinates 1 and 2 of the
+// grid have nothing to do).  Wave 0 forms G and the two rotation adjoints
+// while the other waves read the item partials of the tile's atoms.
+template <typename T, int BS>
+__device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Outs& o, int tile) {
+  using acc = typename AccT<T>::type;
+  constexpr int NG = BS / 64;    // wave 0: G and the adjoints; waves 1..NG-1: the partials
+  constexpr int NW = NG - 1;
+  __shared__ double lsh[2 * NG];
+  __shared__ double fq1[2][256];
+  __shared__ double red1[6][NW][64];
+  __shared__ double gam1[18];
+  double m, Z, S;
+  global_lse<BS>(P, lsh, m, Z, S);
+  const double s = S / Z, lam = P.lam;
+  const int n_pad = P.n_pad;
+  const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int j = tile * 64 + a;
+  double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
+  double g18[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) g18[k] = 0.0;
+  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
+    __syncthreads();
+    const int g = g0 + threadIdx.x;
+    if (threadIdx.x < 256 && g < P.n_slots) {
+      fq1[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
+      fq1[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
+    }
+    __syncthreads();
+    const int gn = min(256, P.n_slots - g0);
+    if (sg == 0) {
+      // Item sums, lane t taking items t, t + 64, ...
+      for (int t = a; t < gn; t += 64) {
+        const double f = fq1[0][t], dq = fq1[1][t];
+        const double* xp = P.xuv + (size_t)(g0 + t) * 18;
+        double xu[9], xv[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          xu[k] = xp[k];
+          xv[k] = xp[9 + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          g18[k] = fma(f, fma(dq, xv[k], xu[k]), g18[k]);
+          g18[9 + k] = fma(f, xv[k], g18[9 + k]);
+        }
+      }
+    } else if (j < n_pad) {
+      // Items t = sg - 1, sg - 1 + NW, ...; four of them (24 loads) are in
+      // flight before any is added.
+      int t = sg - 1;
+      for (; t + 3 * NW < gn; t += 4 * NW) {
+        acc u[4][3];
+        double v[4][3];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            u[b][d] = ldg_nt(partial_u<acc>(P.vec, g0 + t + NW * b, n_pad) + (size_t)d * n_pad + j);
+            v[b][d] = ldg_nt(partial_v<acc>(P.vec, g0 + t + NW * b, n_pad) + (size_t)d * n_pad + j);
+          }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double f = fq1[0][t + NW * b], dq = fq1[1][t + NW * b];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            su[d] = fma(f, fma(dq, v[b][d], (double)u[b][d]), su[d]);
+            sv[d] = fma(f, v[b][d], sv[d]);
+          }
+        }
+      }
+      for (; t < gn; t += NW) {
+        const double f = fq1[0][t], dq = fq1[1][t];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)d * n_pad + j);
+          const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)d * n_pad + j);
+          su[d] = fma(f, fma(dq, v, u), su[d]);
+          sv[d] = fma(f, v, sv[d]);
+        }
+      }
+    }
+  }
+  if (sg == 0) {
+    // G over the items (fixed-order wave sum), then the two adjoints in
+    // lanes 0 (s) and 1 (z), while the other waves finish their partials.
+#pragma unroll
+    for (int k = 0; k < 18; ++k)
+      for (int off = 32; off > 0; off >>= 1) g18[k] += __shfl_xor(g18[k], off, 64);
+    if (a < 2) {
+      const int h = a == 0 ? 0 : 9;
+      const double sc = a == 0 ? 2.0 * lam / Z : -2.0 / Z;
+      double F[10], qv[4], G[9], Gm[9];
+      for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
+      for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
+      for (int k = 0; k < 9; ++k) G[k] = sc * (a == 0 ? g18[k] : g18[9 + k]);
+      rotation_adjoint(F, *cs.lamxy, qv, G, Gm);
+      for (int k = 0; k < 9; ++k) gam1[h + k] = Gm[k];
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red1[d][sg - 1][a] = su[d];
+      red1[3 + d][sg - 1][a] = sv[d];
+    }
+  }
+  __syncthreads();
+  if (sg != 0 || j >= P.n) return;
+  double be[3], bz[3], y[3], xw[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < NW; ++q) {
+      t0 += red1[d][q][a];
+      t1 += red1[3 + d][q][a];
+    }
+    be[d] = -lam / Z * t0;
+    bz[d] = t1 / Z;
+    y[d] = cs.y64[(size_t)d * n_pad + j];
+    xw[d] = P.xw[(size_t)d * n_pad + j];
+  }
+  const double wj = P.w[j];
+  const double* Rx = cs.Rxy;
+  T* ds = (T*)o.ds;
+  T* dz = (T*)o.dz;
+#pragma unroll
+  for (int c0 = 0; c0 < 3; ++c0) {
+    const double rb = Rx[c0 * 3 + 0] * be[0] + Rx[c0 * 3 + 1] * be[1] + Rx[c0 * 3 + 2] * be[2];
+    const double rzb = Rx[c0 * 3 + 0] * bz[0] + Rx[c0 * 3 + 1] * bz[1] + Rx[c0 * 3 + 2] * bz[2];
+    const double rs = wj * (gam1[0 * 3 + c0] * y[0] + gam1[1 * 3 + c0] * y[1] + gam1[2 * 3 + c0] * y[2]);
+    const double rz = wj * (gam1[9 + 0 * 3 + c0] * y[0] + gam1[9 + 1 * 3 + c0] * y[1] + gam1[9 + 2 * 3 + c0] * y[2]);
+    if (ds) ds[3 * j + c0] = (T)(-2.0 * wj * rb + rs);
+    if (dz) dz[3 * j + c0] = (T)(2.0 * (xw[c0] - wj * rzb) + rz);
+  }
+  if (tile == 0 && a == 0) {
+    o.sz[0] = s;
+    o.sz[1] = m - log(Z) / lam;
+  }
+}
+
+// fuse 1: the close-merge ticket is used, so the last workgroup runs the
+// second stage (and, on reassignment steps, the rounding correction);
+// fuse 2 (launched with kOnePassThreads): as 1 on reassignment steps, and
+// the approximate step in one pass (close_merge_one).
+constexpr int kOnePassThreads = 512;
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void merge_close_beta_kernel(const Problem* __restrict__ prob, CloseArgs cs,
+                                                              double* __restrict__ gtmp,
+                                                              const Problem* __restrict__ prob_exact, Outs o,
+                                                              int fuse) {
   using acc = typename AccT<T>::type;  // partial storage type
   constexpr int NG = kBetaThreads / 64;   // slot groups
   const int c = blockIdx.y;
   const int flag = __builtin_amdgcn_readfirstlane(*cs.flag);
   if (flag == 1 && prob_exact != nullptr) {
-    merge_exact_tile<T, kBetaThreads>(*prob_exact, o, blockIdx.x, c);
+    merge_exact_tile<T, BS>(*prob_exact, o, blockIdx.x, c, fuse ? cs.ticket : nullptr);
     return;
   }
   if (flag != 0) return;
+  if constexpr (BS == kOnePassThreads) {
+    if (c == 0) close_merge_one<T, BS>(*prob, cs, o, blockIdx.x);
+    return;
+  } else {
+  if (fuse == 2) return;   // launched with kOnePassThreads only
   __shared__ double sh[2 * NG];
   __shared__ double fq[2][256];
   __shared__ double red[2][NG][64];
@@ -980,6 +1242,12 @@ __global__ __launch_bounds__(kBetaThreads) void merge_close_beta_kernel(const Pr
       gs[9 + r0 * 3 + c] = G[3 + r0];
     }
   }
+  if (fuse == 1 && last_arrival(cs.ticket, (int)(gridDim.x * gridDim.y))) {
+    __shared__ double fsh[18], fgam[18];
+    close_final_stage<T, 64>(P, o, cs, gtmp, (int)gridDim.x, m, Z, S, fsh, fgam);
+    if (a == 0) *cs.ticket = 0u;
+  }
+  }
 }
 
 template <typename T>
@@ -1010,61 +1278,13 @@ __global__ __launch_bounds__(256) void merge_close_final_kernel(const Problem* _
     }
     return;
   }
-  __shared__ double sh[16 * 18];
-  __shared__ double gam[18];
-  const Problem& P = *prob;
-  const int n = P.n, n_pad = P.n_pad;
-  double F[10], qv[4], lv = 0.0;
-  if (threadIdx.x == 0 || threadIdx.x == 64) {
-    for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
-    for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
-    lv = *cs.lamxy;
-  }
-  if (threadIdx.x < 18) {
-    double g = 0.0;
-    for (int t = 0; t < tiles; ++t) g += gtmp[6 * (size_t)n_pad + (size_t)t * 18 + threadIdx.x];
-    sh[threadIdx.x] = g;
-  }
-  __syncthreads();
   if (flag != 0) return;
-  // The two adjoints (for s and for z) are independent: one wave each.
-  if (threadIdx.x == 0 || threadIdx.x == 64) {
-    const int h = threadIdx.x == 0 ? 0 : 9;
-    double G[9], Gm[9];
-    for (int k = 0; k < 9; ++k) G[k] = sh[h + k];
-    rotation_adjoint(F, lv, qv, G, Gm);
-    for (int k = 0; k < 9; ++k) gam[h + k] = Gm[k];
-  }
+  __shared__ double lsh[2 * (BS / 64)];
+  __shared__ double fsh[18], gam[18];
+  const Problem& P = *prob;
   double m, Z, S;
-  global_lse<BS>(P, sh + 32, m, Z, S);   // also orders gam[] before its use below
-  T* ds = (T*)o.ds;
-  T* dz = (T*)o.dz;
-  const double* Rx = cs.Rxy;
-  for (int j = threadIdx.x; j < n; j += BS) {
-    double y[3], be[3], bz[3], xw[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      y[d] = cs.y64[(size_t)d * n_pad + j];
-      be[d] = gtmp[(size_t)d * n_pad + j];
-      bz[d] = gtmp[3 * (size_t)n_pad + (size_t)d * n_pad + j];
-      xw[d] = P.xw[(size_t)d * n_pad + j];
-    }
-    const double wj = P.w[j];
-#pragma unroll
-    for (int c0 = 0; c0 < 3; ++c0) {
-      // explicit Eq. 6 terms -2 w R_xy beta and 2 (w x - w R_xy betaz)
-      const double rb = Rx[c0 * 3 + 0] * be[0] + Rx[c0 * 3 + 1] * be[1] + Rx[c0 * 3 + 2] * be[2];
-      const double rzb = Rx[c0 * 3 + 0] * bz[0] + Rx[c0 * 3 + 1] * bz[1] + Rx[c0 * 3 + 2] * bz[2];
-      const double rs = wj * (gam[0 * 3 + c0] * y[0] + gam[1 * 3 + c0] * y[1] + gam[2 * 3 + c0] * y[2]);
-      const double rz = wj * (gam[9 + 0 * 3 + c0] * y[0] + gam[9 + 1 * 3 + c0] * y[1] + gam[9 + 2 * 3 + c0] * y[2]);
-      if (ds) ds[3 * j + c0] = (T)(-2.0 * wj * rb + rs);
-      if (dz) dz[3 * j + c0] = (T)(2.0 * (xw[c0] - wj * rzb) + rz);
-    }
-  }
-  if (threadIdx.x == 0) {
-    o.sz[0] = S / Z;
-    o.sz[1] = m - log(Z) / P.lam;
-  }
+  global_lse<BS>(P, lsh, m, Z, S);
+  close_final_stage<T, BS>(P, o, cs, gtmp, tiles, m, Z, S, fsh, gam);
 }
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
@@ -1183,12 +1403,17 @@ hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int m
 
 template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
-                              hipStream_t st, const Problem* prob_exact) {
+                              hipStream_t st, const Problem* prob_exact, bool one_pass) {
   const int tiles = (n_pad + 63) / 64;
-  hipLaunchKernelGGL((merge_close_beta_kernel<T>), dim3(tiles, 3), dim3(kBetaThreads), 0, st, prob, ca, gtmp,
-                     prob_exact, outs);
+  const int fuse = one_pass ? 2 : (n_pad <= kCloseFuseMaxPad ? 1 : 0);
+  if (one_pass)
+    hipLaunchKernelGGL((merge_close_beta_kernel<T, kOnePassThreads>), dim3(tiles, 3), dim3(kOnePassThreads), 0, st,
+                       prob, ca, gtmp, prob_exact, outs, fuse);
+  else
+    hipLaunchKernelGGL((merge_close_beta_kernel<T, kBetaThreads>), dim3(tiles, 3), dim3(kBetaThreads), 0, st, prob,
+                       ca, gtmp, prob_exact, outs, fuse);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || fuse) return e;
   hipLaunchKernelGGL((merge_close_final_kernel<T>), dim3(1), dim3(256), 0, st, prob, outs, ca, gtmp, tiles,
                      prob_exact);
   return hipGetLastError();
@@ -1216,7 +1441,7 @@ hipError_t launch_count(long long* c, int which, long long add, hipStream_t st) 
   template hipError_t launch_merge_exact<T>(const Problem*, Outs, int, int, const int*, int,       \
                                             hipStream_t, bool);                                    \
   template hipError_t launch_merge_close<T>(const Problem*, int, Outs, CloseArgs, double*, hipStream_t, \
-                                            const Problem*);
+                                            const Problem*, bool);
 PCV_INST(float)
 PCV_INST(double)
 
