@@ -17,7 +17,8 @@ along a random walk, steps/s), ``--workload batch`` (64 uneven walkers in one
 persistent launch), ``--workload mtd`` (close-structure CVs plus the Eq. 1
 grid bias and its atom gradient every step), ``--workload nl`` (neighbour
 lists, 304 atoms x 2120 references, with and without the close structure),
-``--workload props`` (8 properties per reference with gradients), ``--workload f2``
+``--workload props`` (8 properties per reference with gradients), ``--workload mlp`` (training
+throughput of the surrogate network), ``--workload f2``
 (separate displacement and alignment weights), ``--workload surrogate`` (train the MLP surrogate on
 exact-labelled walks, then compare exact, close-structure and surrogate
 steps/s and |ds| on the test walk) and ``--workload copy`` (a plain device
@@ -789,6 +790,49 @@ def bench_surrogate(args):
     return out
 
 
+def bench_mlp(args):
+    """Training throughput of the surrogate network (300 atoms: 900 -> H ->
+    H -> H -> 2, BF16 matrix-core GEMMs): --steps Adam steps on a batch of
+    --batch seeded BF16 inputs and targets.  FLOPs per step: forward and
+    weight gradients 2 B P_w each, backward signals 2 B (P_w - 900 H) (no
+    input gradient), with P_w the weight count."""
+    import numpy as np
+    import torch
+    import paper_1801_02362_amd as pcv
+    import workloads as wl
+    dev = torch.device("cuda", 0)
+    n, H, B = 300, args.hidden, args.batch
+    sysm, _ = wl.path_300x500(1)
+    sur = pcv.Surrogate(sysm.landmarks[0].astype(np.float64), hidden=H, max_batch=B)
+    sur.set_params(wl.mlp_init(wl.mlp_sizes(n, H), 0))
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.randn(B, 3 * n, generator=g).to(torch.bfloat16).view(torch.int16).to(dev)
+    t = torch.randn(B, 2, generator=g).to(dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        sur.train_step(x, t, 1e-4, loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sur.train_step(x, t, 1e-4, loss)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    pw = 3 * n * H + 2 * H * H + 2 * H
+    flops = 2 * B * pw * 3 - 2 * B * 3 * n * H
+    tf = flops / dt / 1e12
+    sur.close()
+    return {"metric": "surrogate training TFLOP/s", "value": round(tf, 2), "unit": "TFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 x bf16 -> f32",
+            "data": "synthetic",
+            "config": {"workload": f"Adam training step, MLP 900-{H}-{H}-{H}-2 (SiLU), batch {B}",
+                       "flops_per_step": flops},
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(tf / 2500.0, 4), "traffic": None,
+                         "kernel": "whole training step (gemm_mfma_kernel products, split-K reductions, "
+                                   "bias sums, loss, Adam)"}}
+
+
 def bench_copy(args):
     """Plain device-to-device copy of a known size (counter calibration)."""
     import torch
@@ -816,7 +860,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="exact",
-                    choices=["exact", "close", "batch", "copy", "stream", "surrogate", "mtd", "nl", "props", "f2"])
+                    choices=["exact", "close", "batch", "copy", "stream", "surrogate", "mlp", "mtd", "nl", "props",
+                             "f2"])
     ap.add_argument("--hill-stride", type=int, default=50)
     ap.add_argument("--train-walks", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=10000)
@@ -848,6 +893,8 @@ def main():
         out = bench_stream(args)
     elif args.workload == "copy":
         out = bench_copy(args)
+    elif args.workload == "mlp":
+        out = bench_mlp(args)
     elif args.workload == "surrogate":
         out = bench_surrogate(args)
     elif args.workload == "mtd":

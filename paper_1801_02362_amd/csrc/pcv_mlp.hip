@@ -63,7 +63,8 @@ struct GemmArgs {
   const float* pre;  // EPI_SILU_GRAD: pre-activation of row i / pre_div
   int ldpre, pre_div;
   float* part;       // split-K partial sums [splits][M][N] (EPI_PARTIAL)
-  int kc;            // split-K: K range per split (multiple of 16)
+  int kc;            // split-K: K range per split (multiple of the kernel's K step)
+  long long part_cap; // floats the partial buffer holds
 };
 
 // Epilogue of element (i, j) with accumulated value v.
@@ -156,7 +157,172 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int spli
   epilogue<EPI>(g, i, j, v);
 }
 
+// ---------------------------------------------------------------- 128x128
+// Matrix-core GEMM for the batched products (M > 64): 128 x 128 output
+// tile per workgroup of four waves (2 x 2, each 64 x 64 = 4 x 4 MFMA tiles
+// of v_mfma_f32_16x16x32_bf16), K in steps of 64 staged through LDS with two
+// buffers (the next step's global loads are in flight while the current one
+// is multiplied; one barrier per step).  In LDS both operands are K-major
+// rows (A as [m][k], B as [n][k], 64 BF16 + 8 of padding per row), so every
+// MFMA operand is one 16-byte LDS read: lane l takes row l % 16 and the eight
+// k values 8 (l / 16) .. 8 (l / 16) + 7; C lane l holds column l % 16, rows
+// 4 (l / 16) .. + 3.  AKC / BKC: A / B contiguous along k in global memory
+// (else along m / n: then the loads are transposed on their way to LDS).
+// VEC = 4: global loads of 4 BF16 (8 bytes); VEC = 1: single elements.
+// With gridDim.z > 1 each z takes a k range of kc (a multiple of 64) and
+// writes partials (EPI_PARTIAL).
+constexpr int kBM = 128, kBN = 128, kBKm = 64, kLdsRow = kBKm + 8;
+constexpr int kPieces = kBM * kBKm / 4 / 256;   // 4-element pieces per thread per operand and stage
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef uint16_t u4s __attribute__((ext_vector_type(4)));
+
+// 128 rows x kBKm k of one operand, kPieces 4-element pieces per thread.
+// KC (contiguous along k): piece q of thread t is row (t + 256 q) / (kBKm / 4),
+// k 4 ((t + 256 q) % (kBKm / 4)) .. + 3.  Otherwise (contiguous along the
+// rows) thread t owns the 4 x 4 blocks b = t + 256 h of rows 4 (b % 32) .. + 3
+// and k 4 (b / 32) .. + 3: piece 4 h + e is column 4 (b / 32) + e of block h,
+// transposed in registers before the store so that LDS is written in
+// k-contiguous 8-byte runs.  Elements past rows or kend read as zero.
+template <bool KC, int VEC>
+__device__ __forceinline__ void mfma_stage_load(const uint16_t* __restrict__ P, long long s_row, long long s_k,
+                                                int rows, int r0, int k0, int kend, u4s (&v)[kPieces]) {
+  constexpr int KQ = kBKm / 4;
+#pragma unroll
+  for (int q = 0; q < kPieces; ++q) {
+    const int c = threadIdx.x + 256 * q;
+    const int b = threadIdx.x + 256 * (q >> 2);
+    const int r = KC ? (c / KQ) : (b & 31) * 4;
+    const int k = KC ? (c % KQ) * 4 : (b >> 5) * 4 + (q & 3);
+    const int gr = r0 + r, gk = k0 + k;
+    if (VEC == 4) {
+      // the contiguous extent is a multiple of 4: a piece is wholly in or out
+      const bool in = gr < rows && gk < kend;
+      v[q] = in ? *reinterpret_cast<const u4s*>(P + (long long)gr * s_row + (long long)gk * s_k) : u4s{0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = KC ? gr : gr + e, kk = KC ? gk + e : gk;
+        v[q][e] = (rr < rows && kk < kend) ? P[(long long)rr * s_row + (long long)kk * s_k] : (uint16_t)0;
+      }
+    }
+  }
+}
+
+template <bool KC>
+__device__ __forceinline__ void mfma_stage_store(uint16_t* __restrict__ L, const u4s (&v)[kPieces]) {
+  constexpr int KQ = kBKm / 4;
+  if (KC) {
+#pragma unroll
+    for (int q = 0; q < kPieces; ++q) {
+      const int c = threadIdx.x + 256 * q;
+      *reinterpret_cast<u4s*>(L + (c / KQ) * kLdsRow + (c % KQ) * 4) = v[q];
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < kPieces / 4; ++h) {
+      const int b = threadIdx.x + 256 * h;
+      const int r = (b & 31) * 4, k = (b >> 5) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const u4s w = {v[4 * h][e], v[4 * h + 1][e], v[4 * h + 2][e], v[4 * h + 3][e]};
+        *reinterpret_cast<u4s*>(L + (r + e) * kLdsRow + k) = w;
+      }
+    }
+  }
+}
+
+template <int EPI, bool AKC, bool BKC, int VEC>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kBM * kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kBN * kLdsRow];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  const int kbeg = (EPI == EPI_PARTIAL) ? (int)blockIdx.z * g.kc : 0;
+  const int kend = (EPI == EPI_PARTIAL) ? min(g.K, kbeg + g.kc) : g.K;
+  // A(i, k) = A[i sAi + k sAk] (rows i); B(k, j) = B[k sBk + j sBj] (rows j).
+  f4v acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  u4s ra[kPieces], rb[kPieces];
+  mfma_stage_load<AKC, VEC>(g.A, g.sAi, g.sAk, g.M, m0, kbeg, kend, ra);
+  mfma_stage_load<BKC, VEC>(g.B, g.sBj, g.sBk, g.N, n0, kbeg, kend, rb);
+  mfma_stage_store<AKC>(As[0], ra);
+  mfma_stage_store<BKC>(Bs[0], rb);
+  __syncthreads();
+  int buf = 0;
+  const int kq = 8 * (lane >> 4);
+  for (int k0 = kbeg; k0 < kend; k0 += kBKm) {
+    const bool more = k0 + kBKm < kend;
+    if (more) {
+      mfma_stage_load<AKC, VEC>(g.A, g.sAi, g.sAk, g.M, m0, k0 + kBKm, kend, ra);
+      mfma_stage_load<BKC, VEC>(g.B, g.sBj, g.sBk, g.N, n0, k0 + kBKm, kend, rb);
+    }
+    const uint16_t* La = As[buf];
+    const uint16_t* Lb = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < kBKm; kk += 32) {
+      bf8v av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        av[a] = *reinterpret_cast<const bf8v*>(La + (wm * 64 + a * 16 + (lane & 15)) * kLdsRow + kk + kq);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bv[b] = *reinterpret_cast<const bf8v*>(Lb + (wn * 64 + b * 16 + (lane & 15)) * kLdsRow + kk + kq);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) {
+      mfma_stage_store<AKC>(As[buf ^ 1], ra);
+      mfma_stage_store<BKC>(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm * 64 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = n0 + wn * 64 + b * 16 + (lane & 15);
+        if (i < g.M && j < g.N) epilogue<EPI>(g, i, j, acc[a][b][r]);
+      }
+}
+
 constexpr int kMaxSplits = 16;
+constexpr int kBigSplits = 16;   // split-K of the 128 x 128 kernel
+
+template <int EPI, bool AKC, bool BKC>
+static void launch_mfma(const GemmArgs& g, dim3 grid, bool vec4, hipStream_t st) {
+  if (vec4)
+    hipLaunchKernelGGL((gemm_mfma_kernel<EPI, AKC, BKC, 4>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_mfma_kernel<EPI, AKC, BKC, 1>), grid, dim3(256), 0, st, g);
+}
+
+// Operand orientation and load width of one product.  8-byte loads need the
+// contiguous extent and the other stride to be multiples of 4 elements and
+// both bases 8-byte aligned.
+template <int EPI>
+static void launch_mfma_any(const GemmArgs& g, dim3 grid, hipStream_t st) {
+  const bool akc = g.sAk == 1, bkc = g.sBk == 1;
+  const long long a_other = akc ? g.sAi : g.sAk, b_other = bkc ? g.sBj : g.sBk;
+  const int a_ext = akc ? g.K : g.M, b_ext = bkc ? g.K : g.N;
+  const bool vec4 = a_other % 4 == 0 && b_other % 4 == 0 && a_ext % 4 == 0 && b_ext % 4 == 0 &&
+                    ((uintptr_t)g.A & 7) == 0 && ((uintptr_t)g.B & 7) == 0;
+  if (akc && bkc) launch_mfma<EPI, true, true>(g, grid, vec4, st);
+  else if (akc) launch_mfma<EPI, true, false>(g, grid, vec4, st);
+  else if (bkc) launch_mfma<EPI, false, true>(g, grid, vec4, st);
+  else launch_mfma<EPI, false, false>(g, grid, vec4, st);
+}
 
 // Batches that fit one 64-row tile split K over up to 16 workgroups per
 // column tile (partials in g.part, then a deterministic reduction), so a
@@ -164,6 +330,31 @@ constexpr int kMaxSplits = 16;
 template <int EPI>
 hipError_t gemm(GemmArgs g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (g.M > kTM) {
+    // Batched products: the 128 x 128 matrix-core kernel, with split-K
+    // (partials, then the fixed-order reduction) when the tiles alone would
+    // leave most of the chip idle.
+    const int tiles = ((g.M + kBM - 1) / kBM) * ((g.N + kBN - 1) / kBN);
+    const int ksteps = (g.K + kBKm - 1) / kBKm;
+    int splits = 1;
+    if (g.part != nullptr && tiles < 128 && ksteps >= 16)
+      splits = std::min(kBigSplits, std::max(1, std::min(256 / tiles, ksteps / 8)));
+    const int kc = ((ksteps + splits - 1) / splits) * kBKm;
+    const int used = (g.K + kc - 1) / kc;
+    if (splits > 1 && (long long)used * g.M * g.N <= g.part_cap) {
+      g.kc = kc;
+      launch_mfma_any<EPI_PARTIAL>(g, dim3((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, used), st);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const long long total = (long long)g.M * g.N;
+      hipLaunchKernelGGL((splitk_reduce_kernel<EPI>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g,
+                         used);
+      return hipGetLastError();
+    }
+    g.kc = g.K;
+    launch_mfma_any<EPI>(g, dim3((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM), st);
+    return hipGetLastError();
+  }
   const int kt = (g.K + kTK - 1) / kTK;
   if (g.M <= kTM && g.part != nullptr && kt >= 8) {
     const int splits = std::min(kMaxSplits, (kt + 3) / 4);
@@ -184,17 +375,31 @@ hipError_t gemm(GemmArgs g, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Column sums of a row-major [M][N] FP32 matrix into out[N] (bias gradients).
-__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ d, int M, int N,
-                                                     float* __restrict__ out) {
+// Column sums of a row-major [M][N] FP32 matrix into out[N] (bias
+// gradients), in two fixed-order stages: colsum_part_kernel sums slice z of
+// the rows (rows z, z + S, ... for S slices) per column into part[z][N],
+// colsum_kernel adds the S slices in order.
+constexpr int kColSlices = 64;
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ d, int M, int N,
+                                                          float* __restrict__ part) {
   __shared__ float red[4][64];
   const int j = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+  const int z = blockIdx.y;
   float s = 0.f;
   if (j < N)
-    for (int i = grp; i < M; i += 4) s += d[(long long)i * N + j];
+    for (int i = z + kColSlices * grp; i < M; i += 4 * kColSlices) s += d[(long long)i * N + j];
   red[grp][threadIdx.x & 63] = s;
   __syncthreads();
-  if (grp == 0 && j < N) out[j] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  if (grp == 0 && j < N)
+    part[(long long)z * N + j] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ part, int N, float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.f;
+  for (int z = 0; z < kColSlices; ++z) s += part[(long long)z * N + j];
+  out[j] = s;
 }
 
 // Mean squared error over the batch (summed over the two outputs) and its
@@ -495,7 +700,8 @@ struct pcv_mlp {
   uint16_t* dbf[3] = {nullptr, nullptr, nullptr};
   float* gx = nullptr;
   double *sz_s = nullptr, *judge = nullptr, *anchor = nullptr;
-  float* part = nullptr;   // split-K partials: kMaxSplits x 64 rows x max width
+  float* part = nullptr;   // split-K partials (part_cap floats)
+  long long part_cap = 0;
   float *ds_s = nullptr, *dz_s = nullptr;
   long long* cnt = nullptr;
   struct GraphEntry {
@@ -606,7 +812,9 @@ extern "C" pcv_status pcv_mlp_create(pcv_mlp** out, const pcv_options* opt, int 
   A((void**)&m->judge, 4 * 8);
   A((void**)&m->cnt, 4 * 8);
   A((void**)&m->anchor, 3 * 8);
-  A((void**)&m->part, (size_t)kMaxSplits * 64 * std::max<size_t>(nin, H) * 4);
+  m->part_cap = (long long)std::max<size_t>((size_t)kMaxSplits * 64 * std::max<size_t>(nin, H),
+                                            (size_t)kBigSplits * std::max<size_t>(nin, H) * H);
+  A((void**)&m->part, (size_t)m->part_cap * 4);
   if (!ok) return fail_create(PCV_ENOMEM);
   double* dref = nullptr;
   if (hipMalloc((void**)&dref, nin * 8) != hipSuccess) return fail_create(PCV_ENOMEM);
@@ -695,6 +903,7 @@ static hipError_t mlp_forward(pcv_mlp* m, const uint16_t* in, int B, hipStream_t
   for (int l = 0; l < 4; ++l) {
     GemmArgs g{};
     g.part = m->part;
+    g.part_cap = m->part_cap;
     g.A = (l == 0) ? in : m->act[l];
     g.sAi = m->dims[l];
     g.sAk = 1;
@@ -732,6 +941,7 @@ static hipError_t mlp_backward(pcv_mlp* m, const uint16_t* dy, int Rr, int pre_d
     // d_{l-1} = (d_l W_l^T) * silu'(pre_{l-1})
     GemmArgs g{};
     g.part = m->part;
+    g.part_cap = m->part_cap;
     g.A = dprev;
     g.sAi = ldprev;
     g.sAk = 1;
@@ -755,6 +965,7 @@ static hipError_t mlp_backward(pcv_mlp* m, const uint16_t* dy, int Rr, int pre_d
   if (want_input) {
     GemmArgs g{};
     g.part = m->part;
+    g.part_cap = m->part_cap;
     g.A = m->dbf[0];
     g.sAi = H;
     g.sAk = 1;
@@ -806,6 +1017,7 @@ extern "C" pcv_status pcv_mlp_train_step(pcv_mlp* m, const uint16_t* inputs, con
   for (int l = 0; l < 4; ++l) {
     GemmArgs g{};
     g.part = m->part;
+    g.part_cap = m->part_cap;
     g.A = (l == 0) ? inputs : m->act[l];
     g.sAi = 1;
     g.sAk = m->dims[l];
@@ -820,7 +1032,9 @@ extern "C" pcv_status pcv_mlp_train_step(pcv_mlp* m, const uint16_t* inputs, con
     MHIP(m, gemm<EPI_STORE>(g, st));
     const float* dsrc = (l == 3) ? m->dy32 : m->d32[l];
     const int N = m->dims[l + 1];
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64), dim3(256), 0, st, dsrc, B, N, m->g32 + m->off_b[l]);
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, kColSlices), dim3(256), 0, st, dsrc, B, N, m->part);
+    MHIP(m, hipGetLastError());
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, st, m->part, N, m->g32 + m->off_b[l]);
     MHIP(m, hipGetLastError());
   }
   m->adam_t += 1;
