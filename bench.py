@@ -654,6 +654,22 @@ def bench_surrogate(args):
     sur.set_params(wl.mlp_init(wl.mlp_sizes(n, args.hidden), 0))
     sur.set_scaling(mean, sd)
     inputs = sg.aligned_inputs(sur, fd)
+    # Coverage of the test walk by the training frames (the surrogate's
+    # reach): for 100 evenly spaced test frames, the smallest MSD to any
+    # training frame, the training frames taken as landmarks of the exact
+    # kernel in chunks.
+    walk_probe = torch.as_tensor(walk[:: max(1, K // 100)][:100], device=dev)
+    min_d = np.full(walk_probe.shape[0], np.inf)
+    for c0 in range(0, int(fd.shape[0]), 100_000):
+        chunk = pcv.PathCV(fd[c0:c0 + 100_000].contiguous(), 1.0)
+        for k in range(walk_probe.shape[0]):
+            o = chunk.eval(walk_probe[k], grad=False, msd=True)
+            min_d[k] = min(min_d[k], float(o["msd"].min().item()))
+        chunk.close()
+    coverage = {"test_frames": int(walk_probe.shape[0]), "min_msd_to_training_median": float(np.median(min_d)),
+                "min_msd_to_training_min": float(min_d.min()), "min_msd_to_training_max": float(min_d.max()),
+                "eps": args.eps}
+    log(f"[surrogate] test-walk coverage: median min MSD to the training frames {coverage['min_msd_to_training_median']:.4f}")
     del fd
     F = int(inputs.shape[0])
     n_val = max(args.batch, F // 50)
@@ -780,6 +796,7 @@ def bench_surrogate(args):
                       "at_ds_1e-3": {"surrogate": operating_point("surrogate"), "close": operating_point("close"),
                                      "exact_steps_per_s": round(sps_exact, 1)},
                       "close_recomputes": st_close["recomputes"], "judge": st_sur,
+                      "train_test_coverage": coverage,
                       "batched": {"frames": B, "surrogate_frames_per_s": round(sur_batched, 1),
                                   "exact_frames_per_s": round(exact_batched, 1)},
                       "training": {"frames": F, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,

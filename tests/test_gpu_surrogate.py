@@ -316,23 +316,43 @@ def test_trained_network_learns_s_on_held_out_frames(torch):
 
 
 def test_batched_surrogate_outpaces_the_exact_batch(torch):
-    """What the network gains in throughput: one batched evaluation of 1,024
-    structures (300 atoms, 500 landmarks, a 900-512-512-512-2 network)
-    against the exact batched-walker launch over the same structures."""
+    """What the trained network gains in throughput, at the accuracy it
+    has: the full-size network (900-512-512-512-2) trained on exact labels of
+    random walks on the 300-atom, 500-landmark path, then one batched
+    evaluation of 1,024 held-out frames of the same walks against the exact
+    batched-walker launch over the same structures.  The surrogate's error
+    on those frames is asserted (in distribution; the test walk of the bench
+    lies outside the training frames' reach, see the bench's overlap
+    report) together with the speed-up."""
     import time
     import paper_1801_02362_amd as pcv
+    from paper_1801_02362_amd import surrogate as sg
     from gpu_util import dev, say
-    sysm, walk = wl.path_300x500(1024)
+    sysm, _ = wl.path_300x500(1)
     lam = landmark_lambda(sysm.landmarks)
+    frames = wl.surrogate_training_walks(40, 1000, system=sysm)
+    frames = frames[wl.minibatch_order(frames.shape[0], 2)]
+    lm = dev(sysm.landmarks, torch.float32)
+    fd = dev(frames, torch.float32)
+    labels = sg.exact_labels(lm, lam, fd)
+    n_tr = frames.shape[0] - 1024
+    mean, sd = sg.standardise(labels[:n_tr])
+    targets = ((labels - torch.as_tensor(mean, device="cuda")) / torch.as_tensor(sd, device="cuda")).float().contiguous()
     sur = pcv.Surrogate(sysm.landmarks[0].astype(np.float64), hidden=512, max_batch=1024)
     sur.set_params(wl.mlp_init(wl.mlp_sizes(300, 512), 3))
-    sur.set_scaling(np.array([250.0, 0.01]), np.array([100.0, 0.01]))
-    xb = dev(walk, torch.float32)
-    lm = dev(sysm.landmarks, torch.float32)
+    sur.set_scaling(mean, sd)
+    inputs = sg.aligned_inputs(sur, fd)
+    sg.train(sur, inputs[:n_tr], targets[:n_tr], epochs=8, batch=1024, lr=2e-3, lr_final=1e-4)
+    xb = fd[n_tr:].contiguous()
     ob = sur.eval(xb)
+    err = (ob["sz"][:, 0] - labels[n_tr:, 0]).abs()
+    rms, spread = float(err.pow(2).mean().sqrt()), float(labels[n_tr:, 0].std())
+    say(f"[surrogate] held-out |ds| rms {rms:.3f} max {float(err.max()):.3f} (s spread {spread:.1f})")
+    assert rms < 0.1 * spread
     bx = pcv.BatchPathCV([lm] * 1024, [lam] * 1024)
     xall = xb.reshape(1024 * 300, 3)
-    bx.eval(xall)
+    sz_ex, _, _ = bx.eval(xall)
+    assert float((sz_ex[:, 0] - labels[n_tr:, 0]).abs().max()) < 1e-6
     torch.cuda.synchronize()
 
     def rate(fn):
@@ -345,6 +365,6 @@ def test_batched_surrogate_outpaces_the_exact_batch(torch):
     r_sur = rate(lambda: sur.eval(xb, out=ob))
     r_ex = rate(lambda: bx.eval(xall))
     say(f"[surrogate] batched frames/s: surrogate {r_sur:,.0f}, exact {r_ex:,.0f}")
-    assert r_sur > 1.5 * r_ex                  # measured 2.5x at this batch, 6.8x at 4,096
+    assert r_sur > 1.5 * r_ex
     bx.close()
     sur.close()
