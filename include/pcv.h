@@ -135,6 +135,10 @@ pcv_status pcv_set_lambda(pcv_handle* h, double lambda);
  *   sz     device double[2]: s, z
  *   ds_dx  device [n][3] or NULL;  dz_dx  device [n][3] or NULL
  *   msd    device double[L] (the exact D_i) or NULL
+ * FP32 handles on engines 2-5 contract the landmarks with w x_c rounded to
+ * FP32; s and z include the first-order correction dS/dx . (x - x') for
+ * that rounding (likewise the property maps), the D_i do not (they are
+ * within the FP32 MSD bound either way).
  */
 pcv_status pcv_eval(pcv_handle* h, const void* x, double* sz, void* ds_dx, void* dz_dx, double* msd);
 
