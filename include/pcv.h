@@ -473,6 +473,23 @@ pcv_status pcv_mlp_step(pcv_mlp* m, pcv_handle* h, const float* x, double* sz, f
                         int* used_surrogate);
 pcv_status pcv_mlp_get_stats(pcv_mlp* m, pcv_mlp_stats* out);
 pcv_status pcv_mlp_reset_stats(pcv_mlp* m);
+
+/*
+ * Checkpoint and resume of the surrogate's training state (a project
+ * addition): the FP32 master parameters, Adam's two moment vectors and step
+ * count, the output scaling and the fallback step's anchor.  The network
+ * shape (atoms, width) and the reference structure are configuration.
+ *   pcv_mlp_save_state: buf = host buffer of *bytes bytes, or NULL to query
+ *     the size (*bytes receives it); PCV_EINVAL (and the size in *bytes)
+ *     when the buffer is too small.
+ *   pcv_mlp_load_state: buf = host bytes written by pcv_mlp_save_state for a
+ *     surrogate of the same shape (PCV_ESHAPE otherwise, PCV_EINVAL for a
+ *     damaged buffer).  Training steps after a load continue exactly as
+ *     they would have on the saved handle.
+ * Both synchronise the stream.
+ */
+pcv_status pcv_mlp_save_state(pcv_mlp* m, void* buf, size_t* bytes);
+pcv_status pcv_mlp_load_state(pcv_mlp* m, const void* buf, size_t bytes);
 const char* pcv_mlp_last_error(const pcv_mlp* m);
 
 /* ------------------------------------------------------------------------

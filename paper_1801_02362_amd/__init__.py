@@ -117,6 +117,8 @@ def load_library():
         "pcv_mlp_step": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "pcv_mlp_get_stats": (st, [vp, ctypes.POINTER(_MlpStats)]),
         "pcv_mlp_reset_stats": (st, [vp]),
+        "pcv_mlp_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "pcv_mlp_load_state": (st, [vp, vp, ctypes.c_size_t]),
         "pcv_mlp_last_error": (ctypes.c_char_p, [vp]),
         "pcv_set_neighbour_list": (st, [vp, i, i]),
         "pcv_eval_properties": (st, [vp, vp, i, vp, vp, vp]),
@@ -600,6 +602,20 @@ class Surrogate:
         used = o.get("used") if o.get("used") is not None else torch.empty(1, dtype=torch.int32, device=x.device)
         self._check(self._L.pcv_mlp_step(self._h, exact._h, _ptr(x), _ptr(sz), _ptr(ds), _ptr(dz), _ptr(used)))
         return {"sz": sz, "ds_dx": ds, "dz_dx": dz, "used": used}
+
+    def save_state(self) -> bytes:
+        """Training state (parameters, Adam moments and step, scaling, the
+        fallback anchor) as bytes (``pcv_mlp_save_state``)."""
+        n = ctypes.c_size_t(0)
+        self._check(self._L.pcv_mlp_save_state(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._L.pcv_mlp_save_state(self._h, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def load_state(self, blob: bytes):
+        """Restore a state written by ``save_state`` (``pcv_mlp_load_state``)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(self._L.pcv_mlp_load_state(self._h, buf, len(blob)))
 
     def stats(self) -> dict:
         st = _MlpStats()

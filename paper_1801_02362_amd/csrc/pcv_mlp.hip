@@ -1157,4 +1157,77 @@ extern "C" pcv_status pcv_mlp_reset_stats(pcv_mlp* m) {
   return PCV_OK;
 }
 
+// State blob: header {magic, version, n, H, P, adam_t} (6 x int64), scaling
+// mean[2], sd[2], anchor[3] (7 doubles), then w32, m32, v32 (3 P floats).
+static constexpr long long kMlpMagic = 0x3174617453706c4dLL;   // "MlpState1" (little-endian, 8 bytes)
+
+static size_t mlp_state_bytes(const pcv_mlp* m) { return 6 * 8 + 7 * 8 + 3 * (size_t)m->P * 4; }
+
+extern "C" pcv_status pcv_mlp_save_state(pcv_mlp* m, void* buf, size_t* bytes) {
+  if (!m || !bytes) return PCV_EINVAL;
+  const size_t need = mlp_state_bytes(m);
+  if (!buf) {
+    *bytes = need;
+    return PCV_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return mfail(m, PCV_EINVAL, "state buffer too small");
+  }
+  MHIP(m, hipSetDevice(m->opt.device));
+  MHIP(m, hipStreamSynchronize(m->stream));
+  char* p = (char*)buf;
+  const long long hdr[6] = {kMlpMagic, 1, m->n, m->H, m->P, m->adam_t};
+  std::memcpy(p, hdr, sizeof(hdr));
+  p += sizeof(hdr);
+  double sc[7] = {m->mean[0], m->mean[1], m->sd[0], m->sd[1], 0.0, 0.0, 0.0};
+  MHIP(m, hipMemcpy(sc + 4, m->anchor, 3 * sizeof(double), hipMemcpyDeviceToHost));
+  std::memcpy(p, sc, sizeof(sc));
+  p += sizeof(sc);
+  MHIP(m, hipMemcpy(p, m->w32, (size_t)m->P * 4, hipMemcpyDeviceToHost));
+  p += (size_t)m->P * 4;
+  MHIP(m, hipMemcpy(p, m->m32, (size_t)m->P * 4, hipMemcpyDeviceToHost));
+  p += (size_t)m->P * 4;
+  MHIP(m, hipMemcpy(p, m->v32, (size_t)m->P * 4, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return PCV_OK;
+}
+
+extern "C" pcv_status pcv_mlp_load_state(pcv_mlp* m, const void* buf, size_t bytes) {
+  if (!m || !buf) return PCV_EINVAL;
+  if (bytes < 6 * 8) return mfail(m, PCV_EINVAL, "state buffer too small");
+  const char* p = (const char*)buf;
+  long long hdr[6];
+  std::memcpy(hdr, p, sizeof(hdr));
+  if (hdr[0] != kMlpMagic || hdr[1] != 1) return mfail(m, PCV_EINVAL, "not a surrogate state");
+  if (hdr[2] != m->n || hdr[3] != m->H || hdr[4] != m->P) return mfail(m, PCV_ESHAPE, "surrogate shape differs");
+  if (bytes != mlp_state_bytes(m) || hdr[5] < 0) return mfail(m, PCV_EINVAL, "damaged surrogate state");
+  p += sizeof(hdr);
+  double sc[7];
+  std::memcpy(sc, p, sizeof(sc));
+  p += sizeof(sc);
+  for (int k = 0; k < 7; ++k)
+    if (!std::isfinite(sc[k])) return mfail(m, PCV_EINVAL, "damaged surrogate state");
+  if (!(sc[2] > 0.0) || !(sc[3] > 0.0)) return mfail(m, PCV_EINVAL, "damaged surrogate state");
+  MHIP(m, hipSetDevice(m->opt.device));
+  MHIP(m, hipStreamSynchronize(m->stream));
+  MHIP(m, hipMemcpy(m->w32, p, (size_t)m->P * 4, hipMemcpyHostToDevice));
+  p += (size_t)m->P * 4;
+  MHIP(m, hipMemcpy(m->m32, p, (size_t)m->P * 4, hipMemcpyHostToDevice));
+  p += (size_t)m->P * 4;
+  MHIP(m, hipMemcpy(m->v32, p, (size_t)m->P * 4, hipMemcpyHostToDevice));
+  MHIP(m, hipMemcpy(m->anchor, sc + 4, 3 * sizeof(double), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((m->P + 255) / 256)), dim3(256), 0, m->stream, m->w32, m->wbf,
+                     m->P);
+  MHIP(m, hipGetLastError());
+  MHIP(m, hipStreamSynchronize(m->stream));
+  m->adam_t = hdr[5];
+  m->mean[0] = sc[0];
+  m->mean[1] = sc[1];
+  m->sd[0] = sc[2];
+  m->sd[1] = sc[3];
+  mlp_drop_graphs(m);
+  return PCV_OK;
+}
+
 extern "C" const char* pcv_mlp_last_error(const pcv_mlp* m) { return m ? m->err.c_str() : "null handle"; }

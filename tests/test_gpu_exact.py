@@ -368,3 +368,29 @@ def test_fp32_frame_rounding_is_corrected(torch, plan):
     p2 = cv.eval_properties(x, q, grad=False)
     assert host(p2["S"])[0] == host(p["S"])[0]
     cv.close()
+
+
+@pytest.mark.parametrize("n,L", [(6000, 8000), (7000, 7000)])
+def test_four_blocks_per_wave_at_full_size(torch, n, L):
+    """The sizes quoted for engine 3 with four blocks per worker (V kept in
+    FP32 over an item, about 31 landmarks per item), path-shaped landmarks
+    and a frame between two of them so that the weights spread over
+    several landmarks and items: the default plan against the oracle."""
+    import paper_1801_02362_amd as pcv
+    from gpu_util import TOL32, check_cv, dev, host, say
+    s = wl.small_path(n, L, 90 + n % 7, dtype=np.float32)
+    lam = landmark_lambda(s.landmarks)
+    rng = np.random.default_rng(n)
+    i = L // 3
+    f = (0.5 * (s.landmarks[i].astype(np.float64) + s.landmarks[i + 1]) + rng.normal(0, 0.002, (n, 3)))
+    f = f.astype(np.float32)
+    cv = pcv.PathCV(dev(s.landmarks, torch.float32), lam)
+    say(f"[exact] four blocks per wave {n} x {L}: plan={cv.plan}")
+    assert cv.plan["engine"] == 3 and cv.plan["apt"] == 16
+    o = cv.eval(dev(f, torch.float32), msd=True)
+    got = host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"])
+    cv.close()
+    ref = path_cv(f.astype(np.float64), s.landmarks.astype(np.float64), lam)
+    w = np.exp(-lam * (ref.D - ref.D.min()))
+    say(f"[exact] effective landmarks {w.sum() ** 2 / (w ** 2).sum():.1f}, s {ref.s:.4f}")
+    check_cv(f"e3_bpw4_{n}x{L}", TOL32, *got, ref)

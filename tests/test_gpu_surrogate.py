@@ -368,3 +368,37 @@ def test_batched_surrogate_outpaces_the_exact_batch(torch):
     assert r_sur > 1.5 * r_ex
     bx.close()
     sur.close()
+
+
+def test_training_state_checkpoint_resumes_bit_for_bit(torch):
+    """pcv_mlp_save_state / pcv_mlp_load_state: train, save, train three
+    more steps; load the saved state into a fresh surrogate and take the
+    same three steps: parameters, Adam moments (through the next steps) and
+    outputs agree bit for bit."""
+    import paper_1801_02362_amd as pcv
+    from gpu_util import dev, host
+    s, ref, sur, net, params, sizes = _setup(n=24, hidden=64, seed=21, max_batch=128)
+    X = _frames(s, 128, 22, sigma=0.05)
+    xb, _ = sur.align(dev(X, torch.float32))
+    rng = np.random.default_rng(23)
+    T = dev(rng.normal(0, 1, (128, 2)).astype(np.float32), torch.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(4):
+        sur.train_step(xb, T, 1e-3, loss)
+    blob = sur.save_state()
+    for _ in range(3):
+        sur.train_step(xb, T, 1e-3, loss)
+    want = sur.params()
+    y_want = host(sur.forward(xb))
+    other = pcv.Surrogate(ref, hidden=64, max_batch=128, use_graph=False)
+    other.load_state(blob)
+    for _ in range(3):
+        other.train_step(xb, T, 1e-3, loss)
+    assert np.array_equal(other.params(), want)
+    assert np.array_equal(host(other.forward(xb)), y_want)
+    with pytest.raises(pcv.PcvError):
+        pcv.Surrogate(ref, hidden=96, max_batch=8, use_graph=False).load_state(blob)
+    with pytest.raises(pcv.PcvError):
+        other.load_state(blob[:-4])
+    other.close()
+    sur.close()

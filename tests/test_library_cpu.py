@@ -4,6 +4,8 @@ same header the kernels inline) agrees with the oracle."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -123,3 +125,34 @@ def test_native_rotation_adjoint_matches_oracle(hm, seed):
     hm.pcvt_rotation_adjoint(_p(F), lam, _p(np.ascontiguousarray(q)), _p(G), _p(Gam))
     ref = rotation_adjoint(sp.evals, sp.evecs, G)
     assert np.abs(Gam.reshape(3, 3) - ref).max() < 1e-9 * max(1.0, np.abs(ref).max())
+
+
+def test_header_compiles_as_c(tmp_path):
+    """include/pcv.h is a C header: a C99 translation unit that includes it
+    and calls into it compiles with warnings as errors."""
+    src = tmp_path / "t.c"
+    src.write_text('#include "pcv.h"\nint main(void) { pcv_options o; pcv_default_options(&o); return o.device; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", f"-I{os.path.join(ROOT, 'include')}",
+                        "-c", str(src), "-o", str(tmp_path / "t.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_host_math_under_address_and_undefined_sanitizers(tmp_path):
+    """The superposition math the kernels inline (pcv_math.h, through
+    pcv_hosttest.cpp), built for the host with AddressSanitizer and
+    UndefinedBehaviorSanitizer and run over random and degenerate inputs."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = tmp_path / "host_sanitize"
+    cmd = [hipcc, "-O1", "-g", "-std=c++17", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+           "-fsanitize=undefined", "-fno-sanitize-recover=all", f"-I{os.path.join(ROOT, 'include')}",
+           f"-I{os.path.join(PKG, 'csrc')}", os.path.join(ROOT, "tests", "host_sanitize_main.cpp"),
+           os.path.join(PKG, "csrc", "pcv_hosttest.cpp"), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-2000:]
+    assert "0 non-finite" in r.stdout
