@@ -715,13 +715,19 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
   __shared__ double red[2][4][64];
   const Problem& P = probs[blockIdx.z];
   if ((int)blockIdx.x * 64 >= P.n) return;
-  double m, Z, S;
-  global_lse<256>(P, sh, m, Z, S);
-  const double s = S / Z;
   const int c = blockIdx.y;
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + a;
   const int n_pad = P.n_pad;
+  // The first wave's per-atom inputs, fetched before the sums.
+  double wj = 0.0, xwj = 0.0;
+  if (sg == 0 && j < P.n) {
+    wj = P.w[j];
+    xwj = P.xw[(size_t)c * n_pad + j];
+  }
+  double m, Z, S;
+  global_lse<256>(P, sh, m, Z, S);
+  const double s = S / Z;
   double gs = 0.0, gz = 0.0;
   for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
     __syncthreads();
@@ -768,10 +774,9 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
     gs = ((red[0][0][a] + red[0][1][a]) + red[0][2][a]) + red[0][3][a];
     gz = ((red[1][0][a] + red[1][1][a]) + red[1][2][a]) + red[1][3][a];
     if (j < P.n) {
-      const double wj = P.w[j];
       const size_t at = 3 * ((size_t)P.out_off + j) + c;
       if (o.ds) ((T*)o.ds)[at] = (T)(2.0 * P.lam * wj * gs / Z);
-      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (P.xw[(size_t)c * n_pad + j] - wj * gz / Z));
+      if (o.dz) ((T*)o.dz)[at] = (T)(2.0 * (xwj - wj * gz / Z));
     }
     if (P.x_rounded) {
       double cs, cz;
@@ -1022,12 +1027,34 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
   __shared__ double fq1[2][256];
   __shared__ double red1[6][NW][64];
   __shared__ double gam1[18];
-  double m, Z, S;
-  global_lse<BS>(P, lsh, m, Z, S);
-  const double s = S / Z, lam = P.lam;
   const int n_pad = P.n_pad;
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = tile * 64 + a;
+  // Wave 0's inputs that depend on nothing computed here are fetched first,
+  // so their latency hides behind the sums: the atom's y, w x_c and w, R_xy,
+  // and (lanes 0, 1) the y -> x eigen-system for the adjoints.
+  double y[3] = {0.0, 0.0, 0.0}, xw[3] = {0.0, 0.0, 0.0}, wj = 0.0, Rx[9];
+  double F[10], qv[4], lxy = 0.0;
+  if (sg == 0) {
+    if (j < P.n) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        y[d] = cs.y64[(size_t)d * n_pad + j];
+        xw[d] = P.xw[(size_t)d * n_pad + j];
+      }
+      wj = P.w[j];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rx[k] = cs.Rxy[k];
+    if (a < 2) {
+      for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
+      for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
+      lxy = *cs.lamxy;
+    }
+  }
+  double m, Z, S;
+  global_lse<BS>(P, lsh, m, Z, S);
+  const double s = S / Z, lam = P.lam;
   double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
   double g18[18];
 #pragma unroll
@@ -1103,11 +1130,9 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
     if (a < 2) {
       const int h = a == 0 ? 0 : 9;
       const double sc = a == 0 ? 2.0 * lam / Z : -2.0 / Z;
-      double F[10], qv[4], G[9], Gm[9];
-      for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
-      for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
+      double G[9], Gm[9];
       for (int k = 0; k < 9; ++k) G[k] = sc * (a == 0 ? g18[k] : g18[9 + k]);
-      rotation_adjoint(F, *cs.lamxy, qv, G, Gm);
+      rotation_adjoint(F, lxy, qv, G, Gm);
       for (int k = 0; k < 9; ++k) gam1[h + k] = Gm[k];
     }
   } else {
@@ -1119,7 +1144,7 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
   }
   __syncthreads();
   if (sg != 0 || j >= P.n) return;
-  double be[3], bz[3], y[3], xw[3];
+  double be[3], bz[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double t0 = 0.0, t1 = 0.0;
@@ -1129,11 +1154,7 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
     }
     be[d] = -lam / Z * t0;
     bz[d] = t1 / Z;
-    y[d] = cs.y64[(size_t)d * n_pad + j];
-    xw[d] = P.xw[(size_t)d * n_pad + j];
   }
-  const double wj = P.w[j];
-  const double* Rx = cs.Rxy;
   T* ds = (T*)o.ds;
   T* dz = (T*)o.dz;
 #pragma unroll
