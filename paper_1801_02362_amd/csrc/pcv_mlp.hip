@@ -300,6 +300,142 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
 constexpr int kMaxSplits = 16;
 constexpr int kBigSplits = 16;   // split-K of the 128 x 128 kernel
 
+// ------------------------------------------------------------------- GEMV
+// Products of at most kGemvRows rows (one structure: the forward pass has
+// one row, the backward passes two, for s and z) in one launch, FP32
+// accumulation of BF16 products on the vector units (such a product is
+// bandwidth-bound on the weights).  BKC (B contiguous along k, the backward
+// products with W^T): a workgroup takes 8 columns, 32 lanes per column each
+// reading 8 consecutive k per load, summed over the 32 lanes with shuffles.
+// Otherwise (B contiguous along n, the forward products): a workgroup takes
+// 32 columns, thread t reads columns 8 (t % 4) .. + 7 of rows k = t / 4,
+// t / 4 + 64, ..., and the 64 slices are added through LDS in slice order.
+// VEC = 8: 16-byte loads of B; VEC = 1: single elements.
+constexpr int kGemvRows = 4;
+typedef uint16_t u8s __attribute__((ext_vector_type(8)));
+
+template <int VEC>
+__device__ __forceinline__ void gemv_load8(const uint16_t* __restrict__ p, long long step, int valid, float (&v)[8]) {
+  if (VEC == 8 && valid == 8) {
+    const u8s b = *reinterpret_cast<const u8s*>(p);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = bf2f(b[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = e < valid ? bf2f(p[(long long)e * step]) : 0.f;
+  }
+}
+
+template <int EPI, bool BKC, int VEC>
+__global__ __launch_bounds__(256) void gemv_kernel(GemmArgs g) {
+  const int t = threadIdx.x;
+  const int M = g.M;
+  if (BKC) {
+    const int j = blockIdx.x * 8 + (t >> 5), q = t & 31;
+    float acc[kGemvRows] = {0.f, 0.f, 0.f, 0.f};
+    if (j < g.N) {
+      // Two chunks of 8 k per lane in flight before either is added.
+      for (int kb = 8 * q; kb < g.K; kb += 512) {
+        float b[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k0 = kb + 256 * h;
+          gemv_load8<VEC>(g.B + (long long)j * g.sBj + k0, g.sBk, max(0, min(8, g.K - k0)), b[h]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k0 = kb + 256 * h;
+          const int valid = max(0, min(8, g.K - k0));
+#pragma unroll
+          for (int i = 0; i < kGemvRows; ++i) {
+            if (i < M) {
+              float a[8];
+              gemv_load8<1>(g.A + (long long)i * g.sAi + (long long)k0 * g.sAk, g.sAk, valid, a);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) acc[i] = fmaf(a[e], b[h][e], acc[i]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGemvRows; ++i)
+      for (int off = 16; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (q == 0 && j < g.N)
+      for (int i = 0; i < M; ++i) epilogue<EPI>(g, i, j, acc[i]);
+  } else {
+    __shared__ float red[64][32][kGemvRows];
+    const int cg = t & 3, q = t >> 2;
+    const int j0 = blockIdx.x * 32 + cg * 8;
+    const int valid = max(0, min(8, g.N - j0));
+    float acc[kGemvRows][8];
+#pragma unroll
+    for (int i = 0; i < kGemvRows; ++i)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[i][e] = 0.f;
+    if (valid > 0) {
+      // Four rows of B per thread in flight before any is added.
+      for (int kb = q; kb < g.K; kb += 256) {
+        float b[4][8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int k = kb + 64 * h;
+          if (k < g.K) gemv_load8<VEC>(g.B + (long long)k * g.sBk + (long long)j0 * g.sBj, g.sBj, valid, b[h]);
+          else
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[h][e] = 0.f;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int k = kb + 64 * h;
+          if (k >= g.K) break;
+#pragma unroll
+          for (int i = 0; i < kGemvRows; ++i) {
+            if (i < M) {
+              const float a = bf2f(g.A[(long long)i * g.sAi + (long long)k * g.sAk]);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) acc[i][e] = fmaf(a, b[h][e], acc[i][e]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGemvRows; ++i)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[q][cg * 8 + e][i] = acc[i][e];
+    __syncthreads();
+    if (t < 32 * kGemvRows) {
+      const int c = t & 31, i = t >> 5;
+      const int j = blockIdx.x * 32 + c;
+      if (i < M && j < g.N) {
+        float v = 0.f;
+        for (int qq = 0; qq < 64; ++qq) v += red[qq][c][i];
+        epilogue<EPI>(g, i, j, v);
+      }
+    }
+  }
+}
+
+template <int EPI>
+static hipError_t gemv(const GemmArgs& g, hipStream_t st) {
+  const bool bkc = g.sBk == 1;
+  // 16-byte loads of B: 8 contiguous elements at 16-byte aligned addresses.
+  const long long other = bkc ? g.sBj : g.sBk;
+  const int ext = bkc ? g.K : g.N;
+  const bool vec = other % 8 == 0 && ext % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+  if (bkc) {
+    const dim3 grid((g.N + 7) / 8);
+    if (vec) hipLaunchKernelGGL((gemv_kernel<EPI, true, 8>), grid, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((gemv_kernel<EPI, true, 1>), grid, dim3(256), 0, st, g);
+  } else {
+    const dim3 grid((g.N + 31) / 32);
+    if (vec) hipLaunchKernelGGL((gemv_kernel<EPI, false, 8>), grid, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((gemv_kernel<EPI, false, 1>), grid, dim3(256), 0, st, g);
+  }
+  return hipGetLastError();
+}
+
 template <int EPI, bool AKC, bool BKC>
 static void launch_mfma(const GemmArgs& g, dim3 grid, bool vec4, hipStream_t st) {
   if (vec4)
@@ -355,6 +491,7 @@ hipError_t gemm(GemmArgs g, hipStream_t st) {
     launch_mfma_any<EPI>(g, dim3((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM), st);
     return hipGetLastError();
   }
+  if (g.M <= kGemvRows) return gemv<EPI>(g, st);
   const int kt = (g.K + kTK - 1) / kTK;
   if (g.M <= kTM && g.part != nullptr && kt >= 8) {
     const int splits = std::min(kMaxSplits, (kt + 3) / 4);
