@@ -22,7 +22,6 @@ namespace {
 
 constexpr int kMaxAtomsF32 = 512 * 16;
 constexpr int kMaxAtomsF64 = 256 * 8;
-constexpr int kMaxCloseSlots = 2048;
 // Largest structure (padded atoms) engine 4 holds; engine 3 takes larger
 // FP32 structures.
 constexpr int kEngine4MaxAtoms = 2048;

@@ -199,6 +199,9 @@ hipError_t launch_merge_exact(const Problem* probs, Outs outs, int n_prob, int m
 // padded atoms finish in the last workgroup of the first kernel (one launch
 // per step) and larger ones use a second, single-workgroup kernel.
 constexpr int kCloseFuseMaxPad = 1024;
+// Most work items (slots) of one problem; the one-pass close merge keeps
+// their log-sum-exp weights in LDS.
+constexpr int kMaxCloseSlots = 2048;
 template <typename T>
 hipError_t launch_merge_close(const Problem* prob, int n_pad, Outs outs, CloseArgs ca, double* gtmp,
                               hipStream_t st, const Problem* prob_exact = nullptr, bool one_pass = false);

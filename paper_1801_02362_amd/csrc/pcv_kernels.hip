@@ -16,6 +16,7 @@
 //               derivative of R_xy.
 #include "pcv_internal.h"
 #include "pcv_math.h"
+#include "pcv_stream.h"
 
 namespace pcv {
 
@@ -665,6 +666,54 @@ __device__ void global_lse(const Problem& P, double* sh, double& m, double& Z, d
   S = v[1];
 }
 
+// Header (m, Z, S, q0) of slot threadIdx.x, fetched before the merge's other
+// loads so that its round trip overlaps theirs.
+struct HdrSlot {
+  double m, z, s, q;
+};
+// Loads are unconditional (clamped to the last slot) so that none of them
+// waits for another; the values of threads past the slots are then replaced.
+__device__ __forceinline__ HdrSlot hdr_first(const Problem& P) {
+  const bool in = (int)threadIdx.x < P.n_slots;
+  const double* h = P.hdr + (size_t)min((int)threadIdx.x, P.n_slots - 1) * 4;
+  const double m = ldg(h + 0), z = ldg(h + 1), s = ldg(h + 2), q = ldg(h + 3);
+  // Keep the scheduler from moving later loads ahead of these.
+  __builtin_amdgcn_sched_barrier(0);
+  return {in ? m : INFINITY, in ? z : 0.0, in ? s : 0.0, in ? q : 0.0};
+}
+
+// The log-sum-exp of global_lse from the first pass's headers in h (slots
+// threadIdx.x + k BS for k >= 1 are read here), with every slot's weight
+// f_g = exp(-lambda (m_g - m)) and q0_g - s staged in fw[g], fdq[g]
+// (kMaxCloseSlots entries each).  Ends with a workgroup barrier.
+template <int BS>
+__device__ void lse_stage(const Problem& P, const HdrSlot& h, double* lsh, double* fw, double* fdq, double& m,
+                          double& Z, double& S) {
+  const int ns = P.n_slots;
+  const double lam = P.lam;
+  double ml = h.m;
+  for (int g = threadIdx.x + BS; g < ns; g += BS) ml = fmin(ml, ldg(P.hdr + (size_t)g * 4));
+  m = block_min<BS>(ml, lsh);
+  const double f0 = scale_to(h.m, m, lam);
+  double v[2] = {f0 * h.z, f0 * h.s};
+  for (int g = threadIdx.x + BS; g < ns; g += BS) {
+    const double f = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
+    v[0] = fma(f, ldg(P.hdr + (size_t)g * 4 + 1), v[0]);
+    v[1] = fma(f, ldg(P.hdr + (size_t)g * 4 + 2), v[1]);
+    fw[g] = f;
+  }
+  block_sum<2, BS>(v, lsh);
+  Z = v[0];
+  S = v[1];
+  const double s = S / Z;
+  if ((int)threadIdx.x < ns) {
+    fw[threadIdx.x] = f0;
+    fdq[threadIdx.x] = h.q - s;
+  }
+  for (int g = threadIdx.x + BS; g < ns; g += BS) fdq[g] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
+  __syncthreads();
+}
+
 // Rounding-correction share of one merge workgroup (see Problem::x_rounded),
 // called by its whole first wave: lane a holds, for its atom j and the
 // workgroup's coordinate c, ds_j,c d_j,c and dz_j,c d_j,c with
@@ -709,62 +758,79 @@ template <typename T>
 __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restrict__ probs, Outs o,
                                                           const int* __restrict__ flag, int run_if) {
   using acc = typename AccT<T>::type;
-  if (flag != nullptr && *flag != run_if) return;
   __shared__ double sh[8];
-  __shared__ double fq[2][256];
+  __shared__ double fq[2][kMaxCloseSlots];
   __shared__ double red[2][4][64];
   const Problem& P = probs[blockIdx.z];
+  // The gate flag and the problem's fields are read together: the empty
+  // statement takes them all, so their loads are issued before the first
+  // branch instead of one round trip after another.
+  const int fl = flag != nullptr ? *flag : run_if;
+  asm volatile("" ::"s"(fl), "s"(P.n), "s"(P.n_pad), "s"(P.n_slots), "s"(P.hdr), "s"(P.vec), "s"(P.w), "s"(P.xw),
+               "s"(P.lam));
+  if (fl != run_if) return;
   if ((int)blockIdx.x * 64 >= P.n) return;
   const int c = blockIdx.y;
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + a;
-  const int n_pad = P.n_pad;
-  // The first wave's per-atom inputs, fetched before the sums.
-  double wj = 0.0, xwj = 0.0;
-  if (sg == 0 && j < P.n) {
-    wj = P.w[j];
-    xwj = P.xw[(size_t)c * n_pad + j];
+  const int n_pad = P.n_pad, ns = P.n_slots;
+  const bool jin = j < n_pad;
+  // Loads that do not depend on the log-sum-exp: the first wave's per-atom
+  // inputs, the slot headers and the first 16 partials of each wave (slots
+  // sg, sg + 4, ..., sg + 60).
+  // Every load is issued unconditionally at a clamped index (slot, atom)
+  // and only used when in range, so none waits for another; the headers go
+  // first, since loads complete in issue order and the log-sum-exp needs
+  // them before the partials.
+  const HdrSlot h = hdr_first(P);
+  const int jc = min(j, P.n - 1);
+  const double wj = ldg(P.w + jc), xwj = ldg(P.xw + (size_t)c * n_pad + jc);
+  const int jp = min(j, n_pad - 1);
+  acc u[16];
+  double v[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const int g = min(sg + 4 * b, ns - 1);
+    u[b] = ldg_nt(partial_u<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + jp);
+    v[b] = ldg_nt(partial_v<acc>(P.vec, g, n_pad) + (size_t)c * n_pad + jp);
   }
   double m, Z, S;
-  global_lse<256>(P, sh, m, Z, S);
+  lse_stage<256>(P, h, sh, fq[0], fq[1], m, Z, S);
   const double s = S / Z;
   double gs = 0.0, gz = 0.0;
-  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
-    __syncthreads();
-    const int g = g0 + threadIdx.x;
-    if (g < P.n_slots) {
-      fq[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, P.lam);
-      fq[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
+  if (jin) {
+    // Slots in order; 16 of them are loaded before any is added, so a wave
+    // waits for one round trip per 16 slots.
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const int g = sg + 4 * b;
+      if (g < ns) {
+        const double f = fq[0][g];
+        gs = fma(f, fma(fq[1][g], v[b], (double)u[b]), gs);
+        gz = fma(f, v[b], gz);
+      }
     }
-    __syncthreads();
-    const int gn = min(256, P.n_slots - g0);
-    if (j < n_pad) {
-      // Slots t = sg, sg + 4, ... in order; 16 of them are loaded before
-      // any is added, so a wave waits for one round trip per 16 slots.
-      int t = sg;
-      for (; t + 60 < gn; t += 64) {
-        acc u[16];
-        double v[16];
+    int t = sg + 64;
+    for (; t + 60 < ns; t += 64) {
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          u[b] = ldg_nt(partial_u<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
-          v[b] = ldg_nt(partial_v<acc>(P.vec, g0 + t + 4 * b, n_pad) + (size_t)c * n_pad + j);
-        }
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          const double f = fq[0][t + 4 * b];
-          gs = fma(f, fma(fq[1][t + 4 * b], v[b], (double)u[b]), gs);
-          gz = fma(f, v[b], gz);
-        }
+      for (int b = 0; b < 16; ++b) {
+        u[b] = ldg_nt(partial_u<acc>(P.vec, t + 4 * b, n_pad) + (size_t)c * n_pad + j);
+        v[b] = ldg_nt(partial_v<acc>(P.vec, t + 4 * b, n_pad) + (size_t)c * n_pad + j);
       }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const double f = fq[0][t + 4 * b];
+        gs = fma(f, fma(fq[1][t + 4 * b], v[b], (double)u[b]), gs);
+        gz = fma(f, v[b], gz);
+      }
+    }
 #pragma unroll 4
-      for (; t < gn; t += 4) {
-        const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
-        const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)c * n_pad + j);
-        const double f = fq[0][t];
-        gs = fma(f, fma(fq[1][t], v, u), gs);
-        gz = fma(f, v, gz);
-      }
+    for (; t < ns; t += 4) {
+      const double uu = (double)ldg_nt(partial_u<acc>(P.vec, t, n_pad) + (size_t)c * n_pad + j);
+      const double vv = ldg_nt(partial_v<acc>(P.vec, t, n_pad) + (size_t)c * n_pad + j);
+      const double f = fq[0][t];
+      gs = fma(f, fma(fq[1][t], vv, uu), gs);
+      gz = fma(f, vv, gz);
     }
   }
   red[0][sg][a] = gs;
@@ -795,9 +861,11 @@ __global__ __launch_bounds__(256) void merge_exact_kernel(const Problem* __restr
 // the merge, gated like it).
 __global__ __launch_bounds__(64) void sz_correct_kernel(const Problem* __restrict__ probs, Outs o,
                                                         const int* __restrict__ flag, int run_if) {
-  if (flag != nullptr && *flag != run_if) return;
   const Problem& P = probs[blockIdx.x];
-  if (!P.x_rounded) return;
+  // Gate flag and fields read together (see merge_exact_kernel).
+  const int fl = flag != nullptr ? *flag : run_if;
+  asm volatile("" ::"s"(fl), "s"(P.x_rounded), "s"(P.n), "s"(P.corr), "s"(P.out_idx));
+  if (fl != run_if || !P.x_rounded) return;
   const int nblk = 3 * ((P.n + 63) / 64);
   // Eight shares per lane are loaded before any is added (one round trip
   // up to 512 shares, i.e. 10,922 atoms); larger structures loop.
@@ -1016,126 +1084,240 @@ __device__ void close_final_stage(const Problem& P, const Outs& o, const CloseAr
 // (q0_g - s) XV_g) and G_z = -(2 / Z) sum_g f_g XV_g are formed by every
 // workgroup from the item sums, so each can finish its own atoms (all three
 // coordinates of 64 atoms; the workgroups of coordinates 1 and 2 of the
-// grid have nothing to do).  Wave 0 forms G and the two rotation adjoints
-// while the other waves read the item partials of the tile's atoms.
+// grid have nothing to do).  Wave 0 forms the log-sum-exp, G and the two
+// rotation adjoints while the other waves sum the item partials of the
+// tile's atoms.
+//
+// The step is a chain of dependent round trips, so the problem's fields are
+// read together with the step flag, and every load that does not depend on
+// the log-sum-exp is issued before it: wave 0's item headers (slots a + 64 k,
+// k < 4), the y -> x eigen-system and its first two item sums, and the
+// first kOnePassPrefetch partials of each other wave; the adjoints'
+// Cholesky factor (from the eigen-system only) is formed while they are in
+// flight.  Returns false when the caller has to run the reassignment branch
+// (flag 1 with an exact problem), true otherwise.
+constexpr int kOnePassPrefetch = 12;
 template <typename T, int BS>
-__device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Outs& o, int tile) {
+__device__ bool close_merge_one(const Problem& P, const CloseArgs& cs, const Outs& o, int tile, int c,
+                                bool has_exact) {
   using acc = typename AccT<T>::type;
-  constexpr int NG = BS / 64;    // wave 0: G and the adjoints; waves 1..NG-1: the partials
+  constexpr int NG = BS / 64;    // wave 0: log-sum-exp, G and the adjoints; waves 1..NG-1: the partials
   constexpr int NW = NG - 1;
-  __shared__ double lsh[2 * NG];
-  __shared__ double fq1[2][256];
+  constexpr int PF = kOnePassPrefetch;
+  constexpr int KH = 4;          // header slots per wave-0 lane read ahead
+  static_assert(3 * PF == 36, "wave 0 keeps two item sums (2 x 18 doubles) in the partials' registers");
+  __shared__ double fq1[2][kMaxCloseSlots];
   __shared__ double red1[6][NW][64];
-  __shared__ double gam1[18];
-  const int n_pad = P.n_pad;
+  __shared__ double gsum[18], gam1[18];
+  __shared__ double lse1[4];
+  // The problem's fields, read with the flag (one round trip for all).
+  const int n_pad = P.n_pad, ns = P.n_slots, n = P.n;
+  const double lam = P.lam;
+  const double* __restrict__ hdr = P.hdr;
+  void* vec = P.vec;
+  const double* __restrict__ xuv = P.xuv;
+  const double* __restrict__ xwp = P.xw;
+  const double* __restrict__ wp = P.w;
+  const int flag = __builtin_amdgcn_readfirstlane(ldg(cs.flag));
+  // An empty statement that takes the fields: their loads are issued before
+  // the flag's branch instead of being moved behind it.
+  asm volatile("" ::"s"(n_pad), "s"(ns), "s"(n), "s"(lam), "s"(hdr), "s"(vec), "s"(xuv), "s"(xwp), "s"(wp));
+  if (flag == 1 && has_exact) return false;
+  if (flag != 0 || c != 0) return true;
   const int a = threadIdx.x & 63, sg = threadIdx.x >> 6;
   const int j = tile * 64 + a;
-  // Wave 0's inputs that depend on nothing computed here are fetched first,
-  // so their latency hides behind the sums: the atom's y, w x_c and w, R_xy,
-  // and (lanes 0, 1) the y -> x eigen-system for the adjoints.
-  double y[3] = {0.0, 0.0, 0.0}, xw[3] = {0.0, 0.0, 0.0}, wj = 0.0, Rx[9];
+  const bool jin = j < n_pad;
+  // Wave 0: headers first (loads complete in issue order), then the
+  // eigen-system.
+  double hm[KH], hz[KH], hs[KH], hq[KH];
   double F[10], qv[4], lxy = 0.0;
   if (sg == 0) {
-    if (j < P.n) {
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const double* h = hdr + (size_t)min(a + 64 * k, ns - 1) * 4;
+      hm[k] = ldg(h + 0);
+      hz[k] = ldg(h + 1);
+      hs[k] = ldg(h + 2);
+      hq[k] = ldg(h + 3);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) F[k] = ldg(cs.Fxy + k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qv[k] = ldg(cs.qxy + k);
+    lxy = ldg(cs.lamxy);
+  }
+  // pv: a partial-summing wave's V partials of its first PF items, or wave
+  // 0's item sums of items a and a + 64 (entries 0..17 and 18..35).  One
+  // unconditional load per register at a clamped index, the address chosen
+  // per wave (no branch, so no value has to be complete before the sums;
+  // wave 0's pu loads are not used).
+  double pv[PF][3];
+  acc pu[PF][3];
+  {
+    const int jp = min(j, n_pad - 1);
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+      const int g = max(0, min(sg - 1 + NW * b, ns - 1));
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        y[d] = cs.y64[(size_t)d * n_pad + j];
-        xw[d] = P.xw[(size_t)d * n_pad + j];
-      }
-      wj = P.w[j];
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rx[k] = cs.Rxy[k];
-    if (a < 2) {
-      for (int k = 0; k < 10; ++k) F[k] = cs.Fxy[k];
-      for (int k = 0; k < 4; ++k) qv[k] = cs.qxy[k];
-      lxy = *cs.lamxy;
-    }
-  }
-  double m, Z, S;
-  global_lse<BS>(P, lsh, m, Z, S);
-  const double s = S / Z, lam = P.lam;
-  double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
-  double g18[18];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) g18[k] = 0.0;
-  for (int g0 = 0; g0 < P.n_slots; g0 += 256) {
-    __syncthreads();
-    const int g = g0 + threadIdx.x;
-    if (threadIdx.x < 256 && g < P.n_slots) {
-      fq1[0][threadIdx.x] = scale_to(ldg(P.hdr + (size_t)g * 4), m, lam);
-      fq1[1][threadIdx.x] = ldg(P.hdr + (size_t)g * 4 + 3) - s;
-    }
-    __syncthreads();
-    const int gn = min(256, P.n_slots - g0);
-    if (sg == 0) {
-      // Item sums, lane t taking items t, t + 64, ...
-      for (int t = a; t < gn; t += 64) {
-        const double f = fq1[0][t], dq = fq1[1][t];
-        const double* xp = P.xuv + (size_t)(g0 + t) * 18;
-        double xu[9], xv[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          xu[k] = xp[k];
-          xv[k] = xp[9 + k];
-        }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          g18[k] = fma(f, fma(dq, xv[k], xu[k]), g18[k]);
-          g18[9 + k] = fma(f, xv[k], g18[9 + k]);
-        }
-      }
-    } else if (j < n_pad) {
-      // Items t = sg - 1, sg - 1 + NW, ...; four of them (24 loads) are in
-      // flight before any is added.
-      int t = sg - 1;
-      for (; t + 3 * NW < gn; t += 4 * NW) {
-        acc u[4][3];
-        double v[4][3];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            u[b][d] = ldg_nt(partial_u<acc>(P.vec, g0 + t + NW * b, n_pad) + (size_t)d * n_pad + j);
-            v[b][d] = ldg_nt(partial_v<acc>(P.vec, g0 + t + NW * b, n_pad) + (size_t)d * n_pad + j);
-          }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const double f = fq1[0][t + NW * b], dq = fq1[1][t + NW * b];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            su[d] = fma(f, fma(dq, v[b][d], (double)u[b][d]), su[d]);
-            sv[d] = fma(f, v[b][d], sv[d]);
-          }
-        }
-      }
-      for (; t < gn; t += NW) {
-        const double f = fq1[0][t], dq = fq1[1][t];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const double u = (double)ldg_nt(partial_u<acc>(P.vec, g0 + t, n_pad) + (size_t)d * n_pad + j);
-          const double v = ldg_nt(partial_v<acc>(P.vec, g0 + t, n_pad) + (size_t)d * n_pad + j);
-          su[d] = fma(f, fma(dq, v, u), su[d]);
-          sv[d] = fma(f, v, sv[d]);
-        }
+        const int k = 3 * b + d;
+        const double* x0 = xuv + (size_t)min(a + 64 * (k / 18), ns - 1) * 18 + k % 18;
+        const double* pvp = partial_v<acc>(vec, g, n_pad) + (size_t)d * n_pad + jp;
+        pu[b][d] = ldg_nt(partial_u<acc>(vec, g, n_pad) + (size_t)d * n_pad + jp);
+        pv[b][d] = ldg_nt(sg == 0 ? x0 : pvp);
       }
     }
   }
+  double m = 0.0, Z = 0.0, S = 0.0;
+  AdjointFactor af;
   if (sg == 0) {
-    // G over the items (fixed-order wave sum), then the two adjoints in
-    // lanes 0 (s) and 1 (z), while the other waves finish their partials.
+    if (a < 2) adjoint_factor(F, lxy, qv, af);
+    // Log-sum-exp over the item headers (lane-local in slot order, then a
+    // fixed xor tree): (m, Z, S), and every slot's f_g and q0_g - s into LDS.
+    double ml = INFINITY;
 #pragma unroll
-    for (int k = 0; k < 18; ++k)
-      for (int off = 32; off > 0; off >>= 1) g18[k] += __shfl_xor(g18[k], off, 64);
+    for (int k = 0; k < KH; ++k) ml = (a + 64 * k < ns) ? fmin(ml, hm[k]) : ml;
+    for (int g = a + 64 * KH; g < ns; g += 64) ml = fmin(ml, ldg(hdr + (size_t)g * 4));
+    for (int off = 32; off > 0; off >>= 1) ml = fmin(ml, __shfl_xor(ml, off, 64));
+    m = ml;
+    double fk[KH], zl = 0.0, sl = 0.0;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      fk[k] = (a + 64 * k < ns) ? scale_to(hm[k], m, lam) : 0.0;
+      zl = fma(fk[k], hz[k], zl);
+      sl = fma(fk[k], hs[k], sl);
+    }
+    for (int g = a + 64 * KH; g < ns; g += 64) {
+      const double f = scale_to(ldg(hdr + (size_t)g * 4), m, lam);
+      zl = fma(f, ldg(hdr + (size_t)g * 4 + 1), zl);
+      sl = fma(f, ldg(hdr + (size_t)g * 4 + 2), sl);
+      fq1[0][g] = f;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      zl += __shfl_xor(zl, off, 64);
+      sl += __shfl_xor(sl, off, 64);
+    }
+    Z = zl;
+    S = sl;
+    const double s = S / Z;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int g = a + 64 * k;
+      if (g < ns) {
+        fq1[0][g] = fk[k];
+        fq1[1][g] = hq[k] - s;
+      }
+    }
+    for (int g = a + 64 * KH; g < ns; g += 64) fq1[1][g] = ldg(hdr + (size_t)g * 4 + 3) - s;
+  }
+  __syncthreads();
+  double su[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
+  double y[3], xw[3], wj, Rx[9];
+  if (sg == 0) {
+    // The atom's inputs of the final stage, in flight during the sums
+    // (clamped atom; only atoms below n are written).
+    const int jc = min(j, n - 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      y[d] = ldg(cs.y64 + (size_t)d * n_pad + jc);
+      xw[d] = ldg(xwp + (size_t)d * n_pad + jc);
+    }
+    wj = ldg(wp + jc);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rx[k] = ldg(cs.Rxy + k);
+    // Item sums, lane t taking items t, t + 64, ... (fixed order), then G
+    // as fixed-order wave sums and the two adjoints in lanes 0 (s) and 1 (z).
+    double g18[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) g18[k] = 0.0;
+    auto add_item = [&](int g, const double (&xp)[18]) {
+      const double f = fq1[0][g], dq = fq1[1][g];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        g18[k] = fma(f, fma(dq, xp[9 + k], xp[k]), g18[k]);
+        g18[9 + k] = fma(f, xp[9 + k], g18[9 + k]);
+      }
+    };
+    {
+      double x0[18], x1[18];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) {
+        x0[k] = pv[k / 3][k % 3];
+        x1[k] = pv[(18 + k) / 3][(18 + k) % 3];
+      }
+      if (a < ns) add_item(a, x0);
+      if (a + 64 < ns) add_item(a + 64, x1);
+    }
+    for (int g = a + 128; g < ns; g += 64) {
+      double xp[18];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) xp[k] = ldg(xuv + (size_t)g * 18 + k);
+      add_item(g, xp);
+    }
+    wave_sum9_store(g18, gsum, a);
+    wave_sum9_store(g18 + 9, gsum + 9, a);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (a < 2) {
       const int h = a == 0 ? 0 : 9;
       const double sc = a == 0 ? 2.0 * lam / Z : -2.0 / Z;
       double G[9], Gm[9];
-      for (int k = 0; k < 9; ++k) G[k] = sc * (a == 0 ? g18[k] : g18[9 + k]);
-      rotation_adjoint(F, lxy, qv, G, Gm);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) G[k] = sc * gsum[h + k];
+      adjoint_apply(af, qv, G, Gm);
+#pragma unroll
       for (int k = 0; k < 9; ++k) gam1[h + k] = Gm[k];
     }
-  } else {
+  } else if (jin) {
+    // Items g = sg - 1 + NW b: the prefetched ones, then the rest with four
+    // in flight before any is added.
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+      const int g = sg - 1 + NW * b;
+      if (g < ns) {
+        const double f = fq1[0][g], dq = fq1[1][g];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          su[d] = fma(f, fma(dq, pv[b][d], (double)pu[b][d]), su[d]);
+          sv[d] = fma(f, pv[b][d], sv[d]);
+        }
+      }
+    }
+    int g = sg - 1 + NW * PF;
+    for (; g + 3 * NW < ns; g += 4 * NW) {
+      acc u[4][3];
+      double v[4][3];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          u[b][d] = ldg_nt(partial_u<acc>(vec, g + NW * b, n_pad) + (size_t)d * n_pad + j);
+          v[b][d] = ldg_nt(partial_v<acc>(vec, g + NW * b, n_pad) + (size_t)d * n_pad + j);
+        }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double f = fq1[0][g + NW * b], dq = fq1[1][g + NW * b];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          su[d] = fma(f, fma(dq, v[b][d], (double)u[b][d]), su[d]);
+          sv[d] = fma(f, v[b][d], sv[d]);
+        }
+      }
+    }
+    for (; g < ns; g += NW) {
+      const double f = fq1[0][g], dq = fq1[1][g];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u = (double)ldg_nt(partial_u<acc>(vec, g, n_pad) + (size_t)d * n_pad + j);
+        const double v = ldg_nt(partial_v<acc>(vec, g, n_pad) + (size_t)d * n_pad + j);
+        su[d] = fma(f, fma(dq, v, u), su[d]);
+        sv[d] = fma(f, v, sv[d]);
+      }
+    }
+  }
+  if (sg != 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       red1[d][sg - 1][a] = su[d];
@@ -1143,7 +1325,8 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
     }
   }
   __syncthreads();
-  if (sg != 0 || j >= P.n) return;
+  if (sg != 0 || j >= n) return true;
+  const double iz = 1.0 / Z;
   double be[3], bz[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -1152,8 +1335,8 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
       t0 += red1[d][q][a];
       t1 += red1[3 + d][q][a];
     }
-    be[d] = -lam / Z * t0;
-    bz[d] = t1 / Z;
+    be[d] = -lam * iz * t0;
+    bz[d] = t1 * iz;
   }
   T* ds = (T*)o.ds;
   T* dz = (T*)o.dz;
@@ -1167,9 +1350,10 @@ __device__ void close_merge_one(const Problem& P, const CloseArgs& cs, const Out
     if (dz) dz[3 * j + c0] = (T)(2.0 * (xw[c0] - wj * rzb) + rz);
   }
   if (tile == 0 && a == 0) {
-    o.sz[0] = s;
+    o.sz[0] = S * iz;
     o.sz[1] = m - log(Z) / lam;
   }
+  return true;
 }
 
 // fuse 1: the close-merge ticket is used, so the last workgroup runs the
@@ -1185,16 +1369,18 @@ __global__ __launch_bounds__(BS) void merge_close_beta_kernel(const Problem* __r
   using acc = typename AccT<T>::type;  // partial storage type
   constexpr int NG = kBetaThreads / 64;   // slot groups
   const int c = blockIdx.y;
+  if constexpr (BS == kOnePassThreads) {
+    if (!close_merge_one<T, BS>(*prob, cs, o, blockIdx.x, c, prob_exact != nullptr))
+      merge_exact_tile<T, BS>(*prob_exact, o, blockIdx.x, c, fuse ? cs.ticket : nullptr);
+    return;
+  }
   const int flag = __builtin_amdgcn_readfirstlane(*cs.flag);
   if (flag == 1 && prob_exact != nullptr) {
     merge_exact_tile<T, BS>(*prob_exact, o, blockIdx.x, c, fuse ? cs.ticket : nullptr);
     return;
   }
   if (flag != 0) return;
-  if constexpr (BS == kOnePassThreads) {
-    if (c == 0) close_merge_one<T, BS>(*prob, cs, o, blockIdx.x);
-    return;
-  } else {
+  if constexpr (BS != kOnePassThreads) {
   if (fuse == 2) return;   // launched with kOnePassThreads only
   __shared__ double sh[2 * NG];
   __shared__ double fq[2][256];

@@ -274,45 +274,55 @@ PCV_HD void rot_grad_q(const double q[4], const double G[9], double g[4]) {
   g[3] = 2.0 * (-G[0] * q3 - G[1] * q0 + G[2] * q1 + G[3] * q0 - G[4] * q3 + G[5] * q2 + G[6] * q1 + G[7] * q2 + G[8] * q3);
 }
 
-// Solve the SPD 4x4 system K mu = b by Cholesky (K = lam I - F + q q^T).
-PCV_HD void chol4_solve(double K[4][4], const double b[4], double x[4]) {
-  double Lm[4][4] = {{0}};
+// The part of the rotation adjoint that does not depend on G: the Cholesky
+// factor of K = lam I - F + q q^T (lower triangle) and the reciprocals of its
+// diagonal, so that the solve for any G takes multiplications only.
+struct AdjointFactor {
+  double L[4][4];
+  double inv[4];
+};
+
+PCV_HD void adjoint_factor(const double F[10], double lam, const double q[4], AdjointFactor& af) {
+  double A[4][4], K[4][4];
+  unpack4(F, A);
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) K[r][c] = ((r == c) ? lam : 0.0) - A[r][c] + q[r] * q[c];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) af.L[i][j] = 0.0;
   for (int i = 0; i < 4; ++i) {
     for (int j = 0; j <= i; ++j) {
       double s = K[i][j];
-      for (int k = 0; k < j; ++k) s -= Lm[i][k] * Lm[j][k];
-      if (i == j) Lm[i][i] = sqrt(s > 1e-300 ? s : 1e-300);
-      else Lm[i][j] = s / Lm[j][j];
+      for (int k = 0; k < j; ++k) s -= af.L[i][k] * af.L[j][k];
+      if (i == j) {
+        af.L[i][i] = sqrt(s > 1e-300 ? s : 1e-300);
+        af.inv[i] = 1.0 / af.L[i][i];
+      } else {
+        af.L[i][j] = s * af.inv[j];
+      }
     }
-  }
-  double y[4];
-  for (int i = 0; i < 4; ++i) {
-    double s = b[i];
-    for (int k = 0; k < i; ++k) s -= Lm[i][k] * y[k];
-    y[i] = s / Lm[i][i];
-  }
-  for (int i = 3; i >= 0; --i) {
-    double s = y[i];
-    for (int k = i + 1; k < 4; ++k) s -= Lm[k][i] * x[k];
-    x[i] = s / Lm[i][i];
   }
 }
 
 // Gamma = d(sum_ab G_ab R_ab)/dM through the top eigenvector of F(M):
-// mu = (lam I - F)^+ (g_q projected off q), Gamma_ab = mu^T F(E_ab) q.
-PCV_HD void rotation_adjoint(const double F[10], double lam, const double q[4], const double G[9],
-                             double Gamma[9]) {
+// mu = (lam I - F)^+ (g_q projected off q), Gamma_ab = mu^T F(E_ab) q, with
+// the factor of K from adjoint_factor.
+PCV_HD void adjoint_apply(const AdjointFactor& af, const double q[4], const double G[9], double Gamma[9]) {
   double g[4];
   rot_grad_q(q, G, g);
   const double gq = g[0] * q[0] + g[1] * q[1] + g[2] * q[2] + g[3] * q[3];
   double b[4];
   for (int k = 0; k < 4; ++k) b[k] = g[k] - gq * q[k];
-  double A[4][4], K[4][4];
-  unpack4(F, A);
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) K[r][c] = ((r == c) ? lam : 0.0) - A[r][c] + q[r] * q[c];
-  double mu[4];
-  chol4_solve(K, b, mu);
+  double y[4], mu[4];
+  for (int i = 0; i < 4; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= af.L[i][k] * y[k];
+    y[i] = s * af.inv[i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < 4; ++k) s -= af.L[k][i] * mu[k];
+    mu[i] = s * af.inv[i];
+  }
   double P[4][4];
   for (int r = 0; r < 4; ++r)
     for (int c = 0; c < 4; ++c) P[r][c] = mu[r] * q[c] + mu[c] * q[r];
@@ -327,6 +337,13 @@ PCV_HD void rotation_adjoint(const double F[10], double lam, const double q[4], 
   Gamma[6] = P[0][2] + P[1][3];                       // zx
   Gamma[5] = P[0][1] + P[2][3];                       // yz
   Gamma[7] = -P[0][1] + P[2][3];                      // zy
+}
+
+PCV_HD void rotation_adjoint(const double F[10], double lam, const double q[4], const double G[9],
+                             double Gamma[9]) {
+  AdjointFactor af;
+  adjoint_factor(F, lam, q, af);
+  adjoint_apply(af, q, G, Gamma);
 }
 
 }  // namespace pcv
