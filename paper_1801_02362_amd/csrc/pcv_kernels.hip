@@ -52,6 +52,32 @@ __device__ void block_sum(double v[NV], double* sh) {
   }
 }
 
+// block_sum for the frame preparation's latency-bound reductions: each
+// wave folds its values nine at a time with lane swaps (wave_sum9_store,
+// a few VALU operations per value instead of six cross-lane shuffles),
+// then every thread adds the waves' sums in wave order.  sh must hold
+// (BS/64) * 9 * ceil(NV/9) doubles.
+template <int NV, int BS>
+__device__ void block_sum_swap(double v[NV], double* sh) {
+  constexpr int NC = (NV + 8) / 9;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();   // the previous user of sh is done
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) {
+    double w9[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w9[k] = (ch * 9 + k < NV) ? v[ch * 9 + k] : 0.0;
+    wave_sum9_store(w9, sh + (wave * NC + ch) * 9, lane);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += sh[(w * NC + k / 9) * 9 + k % 9];
+    v[k] = s;
+  }
+}
+
 template <int BS>
 __device__ double block_min(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -178,7 +204,8 @@ __global__ __launch_bounds__(256) void pair_msd_kernel(const T* __restrict__ A, 
 // registers for the second (one global round trip fewer); atoms past
 // CACHE * BS are loaded again.  The sums are taken in the same order either way.  With y
 // (a centred structure [3][n_pad], FP64) the second pass also forms the
-// correlation My = sum_j y_j (w_j x_c,j)^T (row-major, 9 values).
+// correlation My = sum_j y_j (w_j x_c,j)^T (row-major, 9 values).  sh holds
+// (BS / 64) * 18 doubles (block_sum_swap of up to 14 values).
 template <typename T, int BS, int CACHE = 0>
 __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& Gx, bool& finite,
                              double c[3], double g32[4], const double* y = nullptr, double* My = nullptr) {
@@ -211,7 +238,7 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   for (int k = 0; k < CACHE; ++k)
     if (threadIdx.x + k * BS < a.n) acc1(wk[k], xk[k]);
   for (int j = threadIdx.x + CACHE * BS; j < a.n; j += BS) acc1(a.w[j], x + 3 * j);
-  block_sum<4, BS>(v, sh);
+  block_sum_swap<4, BS>(v, sh);
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
   // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x
@@ -258,11 +285,11 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
     else pad(j);
   }
   if (y) {
-    block_sum<14, BS>(g, sh);
+    block_sum_swap<14, BS>(g, sh);
 #pragma unroll
     for (int k = 0; k < 9; ++k) My[k] = g[5 + k];
   } else {
-    block_sum<5, BS>(g, sh);
+    block_sum_swap<5, BS>(g, sh);
   }
   Gx = g[0];
   g32[0] = g[1] - (g[2] * g[2] + g[3] * g[3] + g[4] * g[4]);
@@ -277,7 +304,7 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void prep_kernel(const PrepArgs* __restrict__ args,
                                                   const void* __restrict__ x_base) {
-  __shared__ double sh[(BS / 64) * 5];
+  __shared__ double sh[(BS / 64) * 9];
   const PrepArgs a = args[blockIdx.x];
   const T* x = (const T*)x_base + 3 * a.x_off;
   double Gx, c[3], g32[4];
