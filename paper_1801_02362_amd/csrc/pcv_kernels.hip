@@ -238,7 +238,11 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
   for (int k = 0; k < CACHE; ++k)
     if (threadIdx.x + k * BS < a.n) acc1(wk[k], xk[k]);
   for (int j = threadIdx.x + CACHE * BS; j < a.n; j += BS) acc1(a.w[j], x + 3 * j);
-  block_sum_swap<4, BS>(v, sh);
+  // Lane-swap sums pay off at 256 threads (300 atoms: 4.4 -> 4.0 us for
+  // the exact prep); at 512 threads the shuffle tree was faster (9.2 against
+  // 10.2 us at 5,000 atoms, same box), so the wide launch keeps it.
+  if constexpr (BS == 256) block_sum_swap<4, BS>(v, sh);
+  else block_sum<4, BS>(v, sh);
   finite = (v[3] == 0.0);
   c[0] = v[0]; c[1] = v[1]; c[2] = v[2];
   // g[0]: Gx; g[1]: sum (w x rounded to T)^2 / w; g[2..4]: sum of w x
@@ -289,7 +293,8 @@ __device__ void centre_frame(const PrepArgs& a, const T* x, double* sh, double& 
 #pragma unroll
     for (int k = 0; k < 9; ++k) My[k] = g[5 + k];
   } else {
-    block_sum_swap<5, BS>(g, sh);
+    if constexpr (BS == 256) block_sum_swap<5, BS>(g, sh);
+    else block_sum<5, BS>(g, sh);
   }
   Gx = g[0];
   g32[0] = g[1] - (g[2] * g[2] + g[3] * g[3] + g[4] * g[4]);
