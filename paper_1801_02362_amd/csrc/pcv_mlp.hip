@@ -309,7 +309,8 @@ constexpr int kBigSplits = 16;   // split-K of the 128 x 128 kernel
 // reading 8 consecutive k per load, summed over the 32 lanes with shuffles.
 // Otherwise (B contiguous along n, the forward products): a workgroup takes
 // 32 columns, thread t reads columns 8 (t % 4) .. + 7 of rows k = t / 4,
-// t / 4 + 64, ..., and the 64 slices are added through LDS in slice order.
+// t / 4 + 64, ...; the 64 slices are added by a shuffle tree inside each
+// wave and then across the four waves through LDS.
 // VEC = 8: 16-byte loads of B; VEC = 1: single elements.
 constexpr int kGemvRows = 4;
 typedef uint16_t u8s __attribute__((ext_vector_type(8)));
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(256) void gemv_kernel(GemmArgs g) {
     if (q == 0 && j < g.N)
       for (int i = 0; i < M; ++i) epilogue<EPI>(g, i, j, acc[i]);
   } else {
-    __shared__ float red[64][32][kGemvRows];
+    __shared__ float red[4][32][kGemvRows];
     const int cg = t & 3, q = t >> 2;
     const int j0 = blockIdx.x * 32 + cg * 8;
     const int valid = max(0, min(8, g.N - j0));
@@ -400,17 +401,29 @@ __global__ __launch_bounds__(256) void gemv_kernel(GemmArgs g) {
         }
       }
     }
+    // The 16 slices of a wave (lanes cg + 4 m) are added by an xor tree over
+    // m, then the four waves' sums in wave order.
 #pragma unroll
-    for (int i = 0; i < kGemvRows; ++i)
+    for (int i = 0; i < kGemvRows; ++i) {
+      if (i < M) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) red[q][cg * 8 + e][i] = acc[i][e];
+        for (int e = 0; e < 8; ++e)
+          for (int off = 4; off < 64; off <<= 1) acc[i][e] += __shfl_xor(acc[i][e], off, 64);
+      }
+    }
+    const int wv = t >> 6;
+    if ((t & 63) < 4) {
+#pragma unroll
+      for (int i = 0; i < kGemvRows; ++i)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[wv][cg * 8 + e][i] = acc[i][e];
+    }
     __syncthreads();
     if (t < 32 * kGemvRows) {
       const int c = t & 31, i = t >> 5;
       const int j = blockIdx.x * 32 + c;
       if (i < M && j < g.N) {
-        float v = 0.f;
-        for (int qq = 0; qq < 64; ++qq) v += red[qq][c][i];
+        const float v = ((red[0][c][i] + red[1][c][i]) + red[2][c][i]) + red[3][c][i];
         epilogue<EPI>(g, i, j, v);
       }
     }
