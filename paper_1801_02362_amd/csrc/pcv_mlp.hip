@@ -26,6 +26,7 @@
 #include "pcv_host_util.h"
 #include "pcv_internal.h"
 #include "pcv_math.h"
+#include "pcv_stream.h"
 
 namespace pcv {
 namespace {
@@ -618,6 +619,31 @@ __device__ void bsum(double v[NV], double* sh) {
   }
 }
 
+// bsum for the alignment's latency-bound reductions (256 threads): each
+// wave folds its values nine at a time with lane swaps (wave_sum9_store),
+// then every thread adds the four waves' sums in wave order.  sh holds
+// 4 * 9 * ceil(NV / 9) doubles.
+template <int NV>
+__device__ void bsum_swap(double v[NV], double* sh) {
+  constexpr int NC = (NV + 8) / 9;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) {
+    double w9[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w9[k] = (ch * 9 + k < NV) ? v[ch * 9 + k] : 0.0;
+    wave_sum9_store(w9, sh + (wave * NC + ch) * 9, lane);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += sh[(w * NC + k / 9) * 9 + k % 9];
+    v[k] = s;
+  }
+}
+
 // Reference set-up: weighted centring of the reference (once).
 __global__ __launch_bounds__(256) void ref_centre_kernel(const double* __restrict__ ref, const double* __restrict__ w,
                                                          int n, double* __restrict__ ref_c, double* __restrict__ Ga) {
@@ -647,7 +673,7 @@ __global__ __launch_bounds__(256) void align_kernel(const float* __restrict__ x,
                                                     const double* __restrict__ ref_c, const double* __restrict__ Ga,
                                                     double* __restrict__ st, float* __restrict__ xa32,
                                                     uint16_t* __restrict__ xa_bf) {
-  __shared__ double sh[4 * 10];
+  __shared__ double sh[4 * 18];
   __shared__ double Rs[9];
   const int b = blockIdx.x;
   const float* xb = x + (size_t)b * 3 * n;
@@ -655,7 +681,7 @@ __global__ __launch_bounds__(256) void align_kernel(const float* __restrict__ x,
   for (int j = threadIdx.x; j < n; j += 256)
 #pragma unroll
     for (int d = 0; d < 3; ++d) c[d] = fma(w[j], (double)xb[3 * j + d], c[d]);
-  bsum<3>(c, sh);
+  bsum_swap<3>(c, sh);
   double M[10] = {0.0};   // 9 correlation entries + Gx
   for (int j = threadIdx.x; j < n; j += 256) {
     double xc[3];
@@ -667,7 +693,7 @@ __global__ __launch_bounds__(256) void align_kernel(const float* __restrict__ x,
       for (int s = 0; s < 3; ++s) M[3 * r + s] = fma(w[j] * ref_c[3 * j + r], xc[s], M[3 * r + s]);
     M[9] = fma(w[j], xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2], M[9]);
   }
-  bsum<10>(M, sh);
+  bsum_swap<10>(M, sh);
   double* S = st + (size_t)b * kAl;
   if (threadIdx.x == 0) {
     double F[10], lam, q[4], R[9];
@@ -716,8 +742,8 @@ __global__ __launch_bounds__(256) void align_back_kernel(const float* __restrict
                                                          const double* __restrict__ ref_c,
                                                          const double* __restrict__ st, const float* __restrict__ gx,
                                                          float* __restrict__ ds, float* __restrict__ dz) {
-  __shared__ double sh[4 * 12];
-  __shared__ double gam[9], rsum[3];
+  __shared__ double sh[4 * 27];
+  __shared__ double gam[2][9], rsum[2][3];
   const int b = blockIdx.x;
   const float* xb = x + (size_t)b * 3 * n;
   const double* S = st + (size_t)b * kAl;
@@ -726,50 +752,64 @@ __global__ __launch_bounds__(256) void align_back_kernel(const float* __restrict
   for (int d = 0; d < 3; ++d) c[d] = S[d];
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = S[3 + k];
+  // Both outputs (o = 0: s, 1: z) in one pass: per output, G = sum_j x_c,j
+  // g_j^T (9) and sum_j R g_j (3).
+  const float* g0 = gx + (size_t)(2 * b) * 3 * n;
+  const float* g1 = gx + (size_t)(2 * b + 1) * 3 * n;
+  double acc[24] = {0.0};
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double xc[3], ga[3], gb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xc[d] = (double)xb[3 * j + d] - c[d];
+      ga[d] = (double)g0[3 * j + d];
+      gb[d] = (double)g1[3 * j + d];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        acc[3 * r + s] = fma(xc[r], ga[s], acc[3 * r + s]);
+        acc[12 + 3 * r + s] = fma(xc[r], gb[s], acc[12 + 3 * r + s]);
+      }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      acc[9 + r] += R[3 * r + 0] * ga[0] + R[3 * r + 1] * ga[1] + R[3 * r + 2] * ga[2];
+      acc[21 + r] += R[3 * r + 0] * gb[0] + R[3 * r + 1] * gb[1] + R[3 * r + 2] * gb[2];
+    }
+  }
+  bsum_swap<24>(acc, sh);
+  // The two adjoints share the eigen-system's factor: lanes 0 and 1 of
+  // wave 0 take output 0 and 1.
+  if (threadIdx.x < 2) {
+    const int o = threadIdx.x;
+    double F[10], q[4], Gm[9], Gamma[9];
+    for (int k = 0; k < 10; ++k) F[k] = S[12 + k];
+    for (int k = 0; k < 4; ++k) q[k] = S[23 + k];
+    AdjointFactor af;
+    adjoint_factor(F, S[22], q, af);
+    for (int k = 0; k < 9; ++k) Gm[k] = o == 0 ? acc[k] : acc[12 + k];
+    adjoint_apply(af, q, Gm, Gamma);
+    for (int k = 0; k < 9; ++k) gam[o][k] = Gamma[k];
+    for (int r = 0; r < 3; ++r) rsum[o][r] = o == 0 ? acc[9 + r] : acc[21 + r];
+  }
+  __syncthreads();
   for (int o = 0; o < 2; ++o) {
     float* out = (o == 0) ? ds : dz;
-    const float* g = gx + (size_t)(2 * b + o) * 3 * n;
-    double acc[12] = {0.0};   // G[9], sum_j R g_j [3]
+    if (out == nullptr) continue;
+    const float* g = o == 0 ? g0 : g1;
     for (int j = threadIdx.x; j < n; j += 256) {
-      double xc[3], gj[3];
+      double gj[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xc[d] = (double)xb[3 * j + d] - c[d];
-        gj[d] = (double)g[3 * j + d];
-      }
+      for (int d = 0; d < 3; ++d) gj[d] = (double)g[3 * j + d];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int s = 0; s < 3; ++s) acc[3 * r + s] = fma(xc[r], gj[s], acc[3 * r + s]);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) acc[9 + r] += R[3 * r + 0] * gj[0] + R[3 * r + 1] * gj[1] + R[3 * r + 2] * gj[2];
-    }
-    bsum<12>(acc, sh);
-    if (threadIdx.x == 0) {
-      double F[10], q[4], Gm[9], Gamma[9];
-      for (int k = 0; k < 10; ++k) F[k] = S[12 + k];
-      for (int k = 0; k < 4; ++k) q[k] = S[23 + k];
-      for (int k = 0; k < 9; ++k) Gm[k] = acc[k];
-      rotation_adjoint(F, S[22], q, Gm, Gamma);
-      for (int k = 0; k < 9; ++k) gam[k] = Gamma[k];
-      for (int r = 0; r < 3; ++r) rsum[r] = acc[9 + r];
-    }
-    __syncthreads();
-    if (out != nullptr) {
-      for (int j = threadIdx.x; j < n; j += 256) {
-        double gj[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) gj[d] = (double)g[3 * j + d];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          const double ex = R[3 * r + 0] * gj[0] + R[3 * r + 1] * gj[1] + R[3 * r + 2] * gj[2] - w[j] * rsum[r];
-          const double rot = w[j] * (gam[0 * 3 + r] * ref_c[3 * j + 0] + gam[1 * 3 + r] * ref_c[3 * j + 1] +
-                                     gam[2 * 3 + r] * ref_c[3 * j + 2]);
-          out[(size_t)b * 3 * n + 3 * j + r] = (float)(ex + rot);
-        }
+      for (int r = 0; r < 3; ++r) {
+        const double ex = R[3 * r + 0] * gj[0] + R[3 * r + 1] * gj[1] + R[3 * r + 2] * gj[2] - w[j] * rsum[o][r];
+        const double rot = w[j] * (gam[o][0 * 3 + r] * ref_c[3 * j + 0] + gam[o][1 * 3 + r] * ref_c[3 * j + 1] +
+                                   gam[o][2 * 3 + r] * ref_c[3 * j + 2]);
+        out[(size_t)b * 3 * n + 3 * j + r] = (float)(ex + rot);
       }
     }
-    __syncthreads();
   }
 }
 
