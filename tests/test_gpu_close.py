@@ -132,3 +132,29 @@ def test_close_walk_every_engine(plan):
     n_re = _walk(torch, s.landmarks, frames, lam, 0.002, dtype=torch.float32, tol=TOL32,
                  name=f"close_{plan['engine']}", plan=plan)
     assert 2 <= n_re < len(frames)
+
+
+def test_many_work_items_close_and_exact():
+    """1,300 work items (one landmark each): more slots than one pass of the
+    merges' slot loops holds, so the exact merge reads headers beyond its
+    256 threads, and the one-pass close merge sums item headers and item G
+    sums beyond the 256 slots wave 0 reads ahead and partials beyond the
+    twelve items per wave it prefetches.  Close walk and Algorithm 1 with
+    the same plan against the oracle."""
+    import torch
+    import paper_1801_02362_amd as pcv
+    from gpu_util import TOL32, check_cv, dev, host
+    s = wl.small_path(300, 1300, 71, dtype=np.float32)
+    frames = wl.random_walk(s.waypoints[0].astype(np.float64), 20, rng=np.random.default_rng(72), step_sigma=0.01)
+    lam = landmark_lambda(s.landmarks)
+    plan = dict(engine=4, wg=512, apt=8, team=0, aptg=0, batch=1, items=1300)
+    n_re = _walk(torch, s.landmarks, frames, lam, 0.002, dtype=torch.float32, tol=TOL32, name="many_items", plan=plan)
+    assert 2 <= n_re < len(frames)
+    cv = pcv.PathCV(dev(s.landmarks, torch.float32), lam)
+    cv.set_plan(**plan)
+    assert cv.plan["items"] == 1300
+    for t in range(0, len(frames), 7):
+        o = cv.eval(dev(frames[t], torch.float32), msd=True)
+        ref = path_cv(frames[t].astype(np.float64), s.landmarks.astype(np.float64), lam)
+        check_cv(f"many_items_exact[{t}]", TOL32, host(o["sz"]), host(o["ds_dx"]), host(o["dz_dx"]), host(o["msd"]), ref)
+    cv.close()
