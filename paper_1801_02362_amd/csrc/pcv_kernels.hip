@@ -1141,7 +1141,6 @@ __device__ bool close_merge_one(const Problem& P, const CloseArgs& cs, const Out
   __shared__ double fq1[2][kMaxCloseSlots];
   __shared__ double red1[6][NW][64];
   __shared__ double gsum[18], gam1[18];
-  __shared__ double lse1[4];
   // The problem's fields, read with the flag (one round trip for all).
   const int n_pad = P.n_pad, ns = P.n_slots, n = P.n;
   const double lam = P.lam;
